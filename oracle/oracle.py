@@ -1,0 +1,189 @@
+"""Python access to the FP64 CPU oracle (oracle/lbo.c) and its S(k) measurement.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, __graft_entry__.smoke() and bench.py's
+cpu_baseline leg.  The product library never loads it.
+
+The oracle state is the pre-collision population array f[9][ny][nx] (FP64), i.e. the
+delta-m(t) of eq. (lb-lang-ft) of arXiv:1009.0254 after a moment transform.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbo.c")
+LIB = os.path.join(HERE, "liblbo.so")
+
+INIT_KINDS = {"uniform": 0, "slab": 1, "random": 2, "wave": 3}
+
+
+class LboParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("rho0", ctypes.c_double), ("rhoc", ctypes.c_double),
+        ("A", ctypes.c_double), ("B", ctypes.c_double),
+        ("kappa", ctypes.c_double), ("c0sq", ctypes.c_double),
+        ("tau_bulk", ctypes.c_double), ("tau_shear", ctypes.c_double),
+        ("tau_q", ctypes.c_double), ("tau_eps", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("replica", ctypes.c_uint32),
+        ("init_kind", ctypes.c_int32),
+        ("init_arg", ctypes.c_double * 6),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle/lbo.c into oracle/liblbo.so with gcc (FP64, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.POINTER(LboParams)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.lbo_init.argtypes = [P, dp]
+        L.lbo_step.argtypes = [P, dp, ctypes.c_int64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int64)]
+        L.lbo_moments.argtypes = [P, dp, dp]
+        L.lbo_stencils.argtypes = [P, dp, dp, dp, dp]
+        L.lbo_equilibrium.argtypes = [P] + [ctypes.c_double] * 6 + [dp]
+        L.lbo_pressure.argtypes = [P, ctypes.c_double]
+        L.lbo_pressure.restype = ctypes.c_double
+        L.lbo_sound_speed_sq.argtypes = [P, ctypes.c_double]
+        L.lbo_sound_speed_sq.restype = ctypes.c_double
+        L.lbo_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+        L.lbo_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, dp]
+        L.lbo_normals_batch.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, dp]
+        L.lbo_noise_samples.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                        ctypes.c_int64, dp]
+        L.lbo_tables.argtypes = [dp, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_params(cfg: dict) -> LboParams:
+    """Oracle parameter struct from a workload dict (see paper_1009_0254_amd.workloads)."""
+    p = LboParams()
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    p.rho0 = cfg.get("rho0", 1.0)
+    p.rhoc = cfg.get("rhoc", 1.0)
+    p.A, p.B, p.kappa = cfg["A"], cfg["B"], cfg["kappa"]
+    p.c0sq = cfg.get("c0sq", 1.0 / 3.0)
+    p.tau_bulk, p.tau_shear = cfg["tau_bulk"], cfg["tau_shear"]
+    p.tau_q, p.tau_eps = cfg.get("tau_q", 1.0), cfg.get("tau_eps", 1.0)
+    p.kT = cfg["kT"]
+    p.seed = int(cfg.get("seed", 1))
+    p.replica = int(cfg.get("replica", 0))
+    p.init_kind = INIT_KINDS[cfg.get("init", "uniform")]
+    args = list(cfg.get("init_arg", [])) + [0.0] * 6
+    for k in range(6):
+        p.init_arg[k] = float(args[k])
+    return p
+
+
+class Oracle:
+    """Plain FP64 stepper: state f[9][ny][nx] pre-collision, time t."""
+
+    def __init__(self, cfg: dict):
+        self.cfg = dict(cfg)
+        self.p = make_params(cfg)
+        self.nx, self.ny = self.p.nx, self.p.ny
+        self.f = np.zeros((9, self.ny, self.nx))
+        self.t = 0
+        self.flags = (ctypes.c_int64 * 2)(0, 0)
+        lib().lbo_init(ctypes.byref(self.p), _dp(self.f))
+
+    def step(self, nsteps: int):
+        lib().lbo_step(ctypes.byref(self.p), _dp(self.f), int(nsteps), int(self.t), self.flags)
+        self.t += int(nsteps)
+
+    def moments(self) -> np.ndarray:
+        m = np.zeros_like(self.f)
+        lib().lbo_moments(ctypes.byref(self.p), _dp(self.f), _dp(m))
+        return m
+
+    def totals(self) -> np.ndarray:
+        """sum rho, sum jx, sum jy, sum |j|^2, sum (-1)^x jx, sum (-1)^y jy."""
+        m = self.moments()
+        sx = (-1.0) ** np.arange(self.nx)[None, :]
+        sy = (-1.0) ** np.arange(self.ny)[:, None]
+        return np.array([m[0].sum(), m[1].sum(), m[2].sum(), (m[1] ** 2 + m[2] ** 2).sum(),
+                         (sx * m[1]).sum(), (sy * m[2]).sum()])
+
+
+def stencils(cfg: dict, rho: np.ndarray):
+    p = make_params(cfg)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    lap, gx, gy = (np.zeros_like(rho) for _ in range(3))
+    lib().lbo_stencils(ctypes.byref(p), _dp(rho), _dp(lap), _dp(gx), _dp(gy))
+    return lap, gx, gy
+
+
+def equilibrium(cfg: dict, rho, jx, jy, lap, gx, gy) -> np.ndarray:
+    p = make_params(cfg)
+    out = np.zeros(9)
+    lib().lbo_equilibrium(ctypes.byref(p), rho, jx, jy, lap, gx, gy, _dp(out))
+    return out
+
+
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    lib().lbo_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def normals(seed: int, node: int, replica: int, t: int) -> np.ndarray:
+    out = np.zeros(6)
+    lib().lbo_normals(seed, node, replica, t, _dp(out))
+    return out
+
+
+def normals_batch(seed: int, replica: int, t: int, n: int) -> np.ndarray:
+    out = np.zeros((n, 6))
+    lib().lbo_normals_batch(seed, replica, t, n, _dp(out))
+    return out
+
+
+def noise_samples(cfg: dict, rho: float, cs2: float, t: int, n: int) -> np.ndarray:
+    p = make_params(cfg)
+    out = np.zeros((n, 9))
+    lib().lbo_noise_samples(ctypes.byref(p), rho, cs2, t, n, _dp(out))
+    return out
+
+
+def tables():
+    T = np.zeros((9, 9)); N = np.zeros(9); Ti = np.zeros((9, 9)); w = np.zeros(9)
+    lib().lbo_tables(_dp(T), _dp(N), _dp(Ti), _dp(w))
+    return T, N, Ti, w
+
+
+def power_spectrum(m: np.ndarray) -> np.ndarray:
+    """|m_a(k)|^2 with a(k) = n^-1/2 sum_r e^{ik.r} a(r) (Sec. III, notation).
+
+    Returned on the half plane [9][ny][nx//2+1]; for a real field the power at k
+    equals that at -k, so the sign of the exponent does not matter."""
+    n = m.shape[-1] * m.shape[-2]
+    F = np.fft.rfft2(m, axes=(-2, -1))
+    return (F.real ** 2 + F.imag ** 2) / n
