@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Throughput of the fused fluctuating D2Q9 step on one MI355X.
+
+Workload (default): 8192 x 8192 periodic single phase (rho0 = 1, A = 0.05, B = 0.04,
+kappa = 0.02, c0sq = 1/3, tau_s = tau_b = 0.8, kT = 1e-5), populations stored in FP32 as
+deviations from w_i rho0, every step with noise.  A "step" is one pass of the whole
+update (pull-stream, density halo, stencils, equilibrium, Philox noise, MRT relaxation,
+store) over the lattice.  The same workload is also timed with FP64 storage.
+
+Prints one JSON line.  The CPU baseline is the FP64 oracle (test infrastructure) timed on
+a bounded sample of the same workload; the same leg reports the FP32-shifted moment error
+of the GPU against that oracle run.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % HBM roofline, FP32-shifted vs FP64, at stated S(k)/moment error"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = {"fp32s": 72, "fp32": 72, "fp64": 144}   # read + write of 9 populations
+COUNTERS = os.path.join(ROOT, "profiles", "k_step_fp32s_8192_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1009_0254_amd", "csrc", "lb_kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def time_precision(torch, L, cfg, precision, steps, warmup):
+    lat = L.Lattice(cfg, precision=precision)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    lat.step(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    flags, t = lat.lb_status_flags()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return wall, ev_ms, flags, t
+
+
+def traffic_from_counters():
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
+    scaled by the same counters' reading of a plain copy of known size; null when the
+    kernel source has changed since the counters were taken."""
+    try:
+        c = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_src_sha") != kernel_sha():
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(torch, L, cfg, steps):
+    import numpy as np
+    from oracle import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n = cfg["nx"] * cfg["ny"]
+    log("cpu baseline: oracle", cfg["nx"], "x", cfg["ny"], steps, "steps,", threads, "threads")
+    ora = O.Oracle(cfg)
+    t0 = time.perf_counter()
+    ora.step(steps)
+    dt = time.perf_counter() - t0
+    mo = ora.moments()
+    # the GPU on the same steps, FP32-shifted storage
+    lat = L.Lattice(cfg, precision="fp32s")
+    lat.step(steps)
+    mg = lat.moments()
+    lat.close()
+    err = []
+    for a in range(9):
+        scale = np.abs(mo[a] - mo[a].mean()).max()
+        err.append(float(np.abs(mg[a] - mo[a]).max() / scale))
+    del mo, mg, ora
+    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{cfg['nx']}x{cfg['ny']} lattice of the same workload, {steps} steps, FP64 "
+                      f"({dt:.1f} s)"}, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the lattice would shard as y-slabs with a 2-row halo exchange per step; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1009_0254_amd import lbfluct as L
+    from paper_1009_0254_amd import workloads as W
+
+    cfg = {"cfg2": W.cfg2, "cfg3": W.cfg3, "cfg5": W.cfg5}[args.workload]()
+    prec = "fp32s"
+    n = cfg["nx"] * cfg["ny"]
+    log("workload", args.workload, cfg["nx"], "x", cfg["ny"], "precision", prec)
+
+    wall, ev_ms, flags, t = time_precision(torch, L, cfg, prec, args.steps, args.warmup)
+    ms = wall * 1e3 / args.steps
+    kern_ms = ev_ms / args.steps
+    mlups = n * args.steps / wall / 1e6
+    achieved = BYTES_PER_UPDATE[prec] * n / (kern_ms * 1e-3) / 1e9
+    log(f"fp32s: {ms:.4f} ms/step wall, {kern_ms:.4f} ms/step events, {mlups:.0f} MLUPS, {achieved:.0f} GB/s")
+
+    out = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"d2q9 fluctuating Swift model, {cfg['nx']}x{cfg['ny']} periodic single phase, "
+                               f"kT={cfg['kT']}, FP32-shifted populations",
+                   "nx": cfg["nx"], "ny": cfg["ny"], "precision": prec, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(),
+                     "kernel": "k_step<float,float>", "bytes_per_update": BYTES_PER_UPDATE[prec]},
+        "status_flags": flags,
+    }
+    if not args.no_fp64:
+        w64, e64, f64, _ = time_precision(torch, L, cfg, "fp64", max(args.steps // 2, 10), args.warmup // 2 + 1)
+        s64 = max(args.steps // 2, 10)
+        k64 = e64 / s64
+        out["fp64"] = {"value": n * s64 / w64 / 1e6, "unit": "MLUPS", "ms_per_step": w64 * 1e3 / s64,
+                       "achieved_GBs": BYTES_PER_UPDATE["fp64"] * n / (k64 * 1e-3) / 1e9,
+                       "frac": BYTES_PER_UPDATE["fp64"] * n / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out["fp32s_over_fp64"] = out["value"] / out["fp64"]["value"]
+        log(f"fp64: {out['fp64']['ms_per_step']:.4f} ms/step, {out['fp64']['value']:.0f} MLUPS")
+    if not args.no_cpu_baseline:
+        cb, err = cpu_baseline(torch, L, cfg, args.cpu_steps)
+        out["cpu_baseline"] = cb
+        out["accuracy"] = {"moment_rel_err_fp32s_vs_oracle": max(err[:3]), "all_modes": err,
+                           "steps": args.cpu_steps, "tolerance": 1e-5}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

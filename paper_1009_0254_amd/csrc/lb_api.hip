@@ -1,0 +1,576 @@
+// C ABI of the fluctuating non-ideal-fluid lattice Boltzmann library (include/lbfluct.h).
+//
+// Host-side responsibilities: parameter validation (tau > 1/2, PSD of Xi(0), sizes),
+// the per-replica constants of the collision and of Xi(0) (eq. noise-yeo at k = 0),
+// carving the caller's device workspace, the XCD-aware tile list of the fused step,
+// a small autotuner for the strip width / rows per tile, and HIP-graph replay of
+// multi-step runs.
+
+#include "lb_internal.h"
+#include "lbfluct.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+using namespace lbf;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int MAX_RED_BLOCKS = 1024;
+constexpr int GRAPH_STEPS = 32;   // steps per captured graph (even: buffers return to place)
+constexpr int MIN_BX = 64, MIN_H = 8;
+constexpr int SK_MAX = 8192;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+size_t elem_size(int precision) { return precision == LB_FP64 ? sizeof(double) : sizeof(float); }
+
+struct Layout {
+    size_t fbuf[2], reps, tiles, tdev, flags, partials, tot, rho_tmp;
+    size_t twx, twy, work_a, work_b, acc;
+    size_t total;
+    long long nodes;      // sum of nx*ny
+    long long max_n;      // largest replica
+    int max_tiles;
+    int max_nx, max_ny;
+    size_t acc_elems;
+};
+
+int max_tiles_for(const lb_params *p, int n_rep)
+{
+    long long t = 0;
+    for (int r = 0; r < n_rep; ++r) t += (long long)((p[r].nx + MIN_BX - 1) / MIN_BX) * ((p[r].ny + MIN_H - 1) / MIN_H);
+    return (int)t;
+}
+
+// Xi(0) at (rho0, c_s^2(rho0)) must be positive semi-definite (Sec. III.C, Fig. 2):
+// with X of eq. (noise-yeo) at k = 0 the modes-4..9 block is diagonal except (4,9)
+bool xi0_psd(const lb_params &q)
+{
+    const double lb = -1.0 / q.tau_bulk, ls = -1.0 / q.tau_shear, lq = -1.0 / q.tau_q, le = -1.0 / q.tau_eps;
+    const double x = q.rho0 - q.rhoc;
+    const double cs2 = q.c0sq + q.rho0 * (q.A + 3 * q.B * x * x);
+    const double a44 = -4.0 * lb * (2 + lb) * (2 - 3 * cs2);
+    const double a49 = -12.0 * (lb + le + lb * le) * (cs2 - 1.0 / 3.0);
+    const double a99 = -16.0 * le * (2 + le) * (1.25 - 0.75 * cs2);
+    const bool diag_ok = ls * (2 + ls) <= 0 && lq * (2 + lq) <= 0;
+    const double tol = 1e-14 * (fabs(a44) + fabs(a99) + 1e-300);
+    return diag_ok && a44 >= -tol && a99 >= -tol && a44 * a99 - a49 * a49 >= -tol * (fabs(a44) + fabs(a99));
+}
+
+lb_status validate(const lb_params *p, int32_t n_rep, int32_t precision)
+{
+    if (!p || n_rep < 1) return LB_EINVAL;
+    if (precision < LB_FP64 || precision > LB_FP32_SHIFTED) return LB_EINVAL;
+    for (int r = 0; r < n_rep; ++r) {
+        const lb_params &q = p[r];
+        if (q.nx < 3 || q.ny < 3) return LB_EINVAL;
+        if ((long long)q.nx * q.ny >= (1ll << 32)) return LB_EINVAL;
+        if (!(q.rho0 > 0) || !isfinite(q.rho0)) return LB_EINVAL;
+        const double taus[4] = {q.tau_bulk, q.tau_shear, q.tau_q, q.tau_eps};
+        for (double tau : taus)
+            if (!(tau > 0.5) || !isfinite(tau)) return LB_EINVAL;
+        if (!(q.kT >= 0) || !isfinite(q.kT)) return LB_EINVAL;
+        if (!isfinite(q.A) || !isfinite(q.B) || !isfinite(q.kappa) || !isfinite(q.c0sq) || !isfinite(q.rhoc))
+            return LB_EINVAL;
+        if (q.init_kind < LB_INIT_UNIFORM || q.init_kind > LB_INIT_WAVE) return LB_EINVAL;
+        if (q.init_kind == LB_INIT_SLAB && !(q.init_arg[4] != 0)) return LB_EINVAL;
+        if (!xi0_psd(q)) return LB_ENOTPSD;
+    }
+    return LB_OK;
+}
+
+Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t features)
+{
+    Layout L{};
+    L.nodes = 0;
+    L.max_n = 0;
+    L.max_nx = L.max_ny = 0;
+    L.acc_elems = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        const long long n = (long long)p[r].nx * p[r].ny;
+        L.nodes += n;
+        L.max_n = std::max(L.max_n, n);
+        L.max_nx = std::max(L.max_nx, p[r].nx);
+        L.max_ny = std::max(L.max_ny, p[r].ny);
+        L.acc_elems += (size_t)9 * p[r].ny * (p[r].nx / 2 + 1);
+    }
+    L.max_tiles = max_tiles_for(p, n_rep);
+    size_t o = 0;
+    const size_t fb = align_up((size_t)9 * L.nodes * elem_size(precision));
+    L.fbuf[0] = o; o += fb;
+    L.fbuf[1] = o; o += fb;
+    L.reps = o; o += align_up(sizeof(RepDesc) * n_rep);
+    L.tiles = o; o += align_up(sizeof(Tile) * L.max_tiles);
+    L.tdev = o; o += ALIGN;
+    L.flags = o; o += ALIGN;
+    L.partials = o; o += align_up(sizeof(double) * 6 * MAX_RED_BLOCKS);
+    L.tot = o; o += ALIGN;
+    L.rho_tmp = o; o += align_up(sizeof(double) * L.max_n);
+    if (features & LB_FEATURE_STRUCTURE_FACTOR) {
+        L.twx = o; o += align_up(sizeof(double) * 2 * (L.max_nx / 2 + 1));
+        L.twy = o; o += align_up(sizeof(double) * 2 * (L.max_ny / 2 + 1));
+        const size_t cplx = align_up(sizeof(double) * 2 * (size_t)L.max_ny * (L.max_nx / 2 + 1));
+        L.work_a = o; o += cplx;
+        L.work_b = o; o += cplx;
+        L.acc = o; o += align_up(sizeof(double) * L.acc_elems);
+    }
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct lb_handle {
+    int n_rep = 0, precision = 0;
+    uint32_t features = 0;
+    std::vector<RepDesc> reps;
+    std::vector<size_t> acc_off;     // element offset of each replica's S(k) accumulator
+    std::vector<long long> nsamples;
+    hipStream_t stream = nullptr;
+    unsigned char *ws = nullptr;
+    Layout L{};
+    void *fbuf[2] = {nullptr, nullptr};
+    int par = 0;
+    long long t = 0;
+    RepDesc *reps_d = nullptr;
+    Tile *tiles_d = nullptr;
+    std::vector<Tile> tiles_h;
+    int ntiles = 0, bx = 256, rows = 32;
+    unsigned long long *tdev = nullptr;
+    unsigned *flags = nullptr;
+    double *partials = nullptr, *tot = nullptr, *rho_tmp = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    // structure factor
+    bool sk_ready = false;
+    int sk_nx = 0, sk_ny = 0;
+    double *twx = nullptr, *twy = nullptr, *work_a = nullptr, *work_b = nullptr, *acc = nullptr;
+};
+
+namespace {
+
+RepDesc describe(const lb_params &q, int precision, long long off, long long node_off)
+{
+    RepDesc d{};
+    d.nx = q.nx;
+    d.ny = q.ny;
+    d.off = off;
+    d.node_off = node_off;
+    d.seed_lo = (uint32_t)q.seed;
+    d.seed_hi = (uint32_t)(q.seed >> 32);
+    d.rep_id = q.replica;
+    d.noise = q.kT > 0 ? 1u : 0u;
+    d.rho0 = q.rho0;
+    d.xr0 = q.rho0 - q.rhoc;
+    d.A = q.A;
+    d.B = q.B;
+    d.c0m = q.c0sq - 1.0 / 3.0;
+    d.kappa = q.kappa;
+    d.lam_b = -1.0 / q.tau_bulk;
+    d.lam_s = -1.0 / q.tau_shear;
+    d.lam_q = -1.0 / q.tau_q;
+    d.lam_e = -1.0 / q.tau_eps;
+    // Xi(0) = -(rho kT / sigma_s^2) X with X of eq. (noise-yeo) at k = 0;
+    // tilde-lambda_a = lambda_a (2 + lambda_a), tilde-lambda_{e eps} = lambda_e + lambda_eps + lambda_e lambda_eps
+    const double ltb = d.lam_b * (2 + d.lam_b), lts = d.lam_s * (2 + d.lam_s);
+    const double ltq = d.lam_q * (2 + d.lam_q), lte = d.lam_e * (2 + d.lam_e);
+    const double ltbe = d.lam_b + d.lam_e + d.lam_b * d.lam_e;
+    const double N[9] = {1, 1.0 / 3, 1.0 / 3, 4, 4.0 / 9, 1.0 / 9, 2.0 / 3, 2.0 / 3, 16};
+    d.kT3 = 3.0 * q.kT;
+    d.k44 = -N[3] * ltb;
+    d.k49 = -12.0 * ltbe;
+    d.k99 = -N[8] * lte;
+    d.l55 = sqrt(-N[4] * lts);
+    d.l66 = sqrt(-N[5] * lts);
+    d.l77 = sqrt(-N[6] * ltq);
+    d.l88 = sqrt(-N[7] * ltq);
+    const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    for (int i = 0; i < 9; ++i) {
+        d.shift[i] = precision == LB_FP32_SHIFTED ? w[i] * q.rho0 : 0.0;
+        d.sub[i] = w[i] * q.rho0 - d.shift[i];
+    }
+    d.init_kind = q.init_kind;
+    for (int k = 0; k < 6; ++k) d.init_arg[k] = q.init_arg[k];
+    return d;
+}
+
+// Tiles of every replica for strip width bx and rows per tile h.  Workgroup i runs on
+// XCD i mod 8; tiles are ordered so that each XCD walks a contiguous run of the
+// (replica, strip, row-segment) order, keeping vertically adjacent tiles -- which share
+// their boundary rows -- on the same L2.
+std::vector<Tile> make_tiles(const std::vector<RepDesc> &reps, int bx, int h)
+{
+    std::vector<Tile> seq;
+    for (size_t r = 0; r < reps.size(); ++r) {
+        const RepDesc &d = reps[r];
+        for (int x0 = 0; x0 < d.nx; x0 += bx)
+            for (int y0 = 0; y0 < d.ny; y0 += h) seq.push_back(Tile{(int32_t)r, x0, y0, std::min(y0 + h, d.ny)});
+    }
+    const int T = (int)seq.size();
+    const int X = 8;
+    // XCD k takes the contiguous run [start_k, start_k + count_k) of the sequence, with
+    // counts as even as possible; its j-th tile goes to position j * X + k, so the only
+    // unused positions are at the end of the array
+    std::vector<Tile> out;
+    out.reserve(T);
+    const int base = T / X, extra = T % X;
+    std::vector<int> start(X + 1, 0);
+    for (int k = 0; k < X; ++k) start[k + 1] = start[k] + base + (k < extra ? 1 : 0);
+    for (int j = 0; j <= base; ++j)
+        for (int k = 0; k < X; ++k)
+            if (start[k] + j < start[k + 1]) out.push_back(seq[start[k] + j]);
+    return out;
+}
+
+lb_status hip_ok(hipError_t e) { return e == hipSuccess ? LB_OK : LB_EDEVICE; }
+
+lb_status set_tiles(lb_handle *h, int bx, int rows)
+{
+    h->tiles_h = make_tiles(h->reps, bx, rows);
+    if ((int)h->tiles_h.size() > h->L.max_tiles) return LB_EINVAL;
+    // synchronous: earlier launches may still read the previous list
+    if (hipMemcpyAsync(h->tiles_d, h->tiles_h.data(), sizeof(Tile) * h->tiles_h.size(), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return LB_EDEVICE;
+    h->ntiles = (int)h->tiles_h.size();
+    h->bx = bx;
+    h->rows = rows;
+    return LB_OK;
+}
+
+hipError_t step_once(lb_handle *h, int par, int toff, hipStream_t s)
+{
+    StepLaunch a;
+    a.fin = h->fbuf[par];
+    a.fout = h->fbuf[par ^ 1];
+    a.reps = h->reps_d;
+    a.tiles = h->tiles_d;
+    a.tdev = h->tdev;
+    a.flags = h->flags;
+    a.toff = toff;
+    a.ntiles = h->ntiles;
+    a.bx = h->bx;
+    return launch_step(h->precision, a, s);
+}
+
+void drop_graphs(lb_handle *h)
+{
+    for (int k = 0; k < 2; ++k)
+        if (h->graph[k]) {
+            (void)hipGraphExecDestroy(h->graph[k]);
+            h->graph[k] = nullptr;
+        }
+}
+
+// time a few steps of each candidate (bx, rows) and keep the fastest; the trial steps
+// read the current buffer and overwrite the other, so the state is unchanged
+lb_status autotune(lb_handle *h)
+{
+    int min_nx = 1 << 30;
+    for (auto &d : h->reps) min_nx = std::min(min_nx, d.nx);
+    const char *env = getenv("LBF_TILE");
+    if (env) {
+        int bx = 0, rows = 0;
+        if (sscanf(env, "%d,%d", &bx, &rows) == 2 && bx >= MIN_BX && bx <= 512 && bx % 64 == 0 && rows >= MIN_H)
+            return set_tiles(h, bx, rows);
+    }
+    int bx0 = 256;
+    while (bx0 > MIN_BX && bx0 / 2 >= min_nx) bx0 /= 2;
+    if (h->L.nodes < (1ll << 22)) return set_tiles(h, bx0, h->L.nodes < (1ll << 16) ? MIN_H : 16);
+
+    const int cand[][2] = {{128, 32}, {256, 16}, {256, 32}, {256, 64}, {512, 16}, {512, 32}, {128, 64}};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LB_EDEVICE;
+    float best = 1e30f;
+    int bbx = bx0, brows = 32;
+    for (auto &c : cand) {
+        if (c[0] > 2 * min_nx && c[0] > bx0) continue;
+        if (set_tiles(h, c[0], c[1]) != LB_OK) continue;
+        if (step_once(h, h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
+        (void)hipEventRecord(e0, h->stream);
+        for (int k = 0; k < 3; ++k)
+            if (step_once(h, h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
+        (void)hipEventRecord(e1, h->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) return LB_EDEVICE;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            bbx = c[0];
+            brows = c[1];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (hipMemsetAsync(h->flags, 0, sizeof(unsigned), h->stream) != hipSuccess) return LB_EDEVICE;
+    return set_tiles(h, bbx, brows);
+}
+
+lb_status capture_graph(lb_handle *h, int par)
+{
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LB_EDEVICE;
+    hipGraph_t g = nullptr;
+    lb_status st = LB_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return LB_EDEVICE;
+    }
+    int p = par;
+    for (int k = 0; k < GRAPH_STEPS; ++k) {
+        if (step_once(h, p, k, cs) != hipSuccess) st = LB_EDEVICE;
+        p ^= 1;
+    }
+    if (launch_advance_time(h->tdev, GRAPH_STEPS, cs) != hipSuccess) st = LB_EDEVICE;
+    if (hipStreamEndCapture(cs, &g) != hipSuccess) st = LB_EDEVICE;
+    if (st == LB_OK && hipGraphInstantiate(&h->graph[par], g, nullptr, nullptr, 0) != hipSuccess) st = LB_EDEVICE;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lb_strerror(lb_status s)
+{
+    switch (s) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument or parameter";
+    case LB_ENOTPSD: return "noise covariance Xi(0) is not positive semi-definite at rho0";
+    case LB_EUNSTABLE: return "parameters outside the stable range";
+    case LB_ENOMEM: return "workspace too small";
+    case LB_EDEVICE: return "HIP call failed";
+    case LB_ESTATE: return "operation not valid in this state";
+    default: return "unknown status";
+    }
+}
+
+lb_status lb_workspace_size(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t features, size_t *bytes)
+{
+    if (!bytes) return LB_EINVAL;
+    lb_status st = validate(p, n_rep, precision);
+    if (st != LB_OK) return st;
+    *bytes = make_layout(p, n_rep, precision, features).total;
+    return LB_OK;
+}
+
+lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t features, void *d_workspace,
+                  size_t bytes, void *stream, lb_handle **out)
+{
+    if (!out) return LB_EINVAL;
+    *out = nullptr;
+    lb_status st = validate(p, n_rep, precision);
+    if (st != LB_OK) return st;
+    if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0) return LB_EINVAL;
+    const Layout L = make_layout(p, n_rep, precision, features);
+    if (bytes < L.total) return LB_ENOMEM;
+
+    lb_handle *h = new (std::nothrow) lb_handle();
+    if (!h) return LB_ENOMEM;
+    h->n_rep = n_rep;
+    h->precision = precision;
+    h->features = features;
+    h->stream = (hipStream_t)stream;
+    h->ws = (unsigned char *)d_workspace;
+    h->L = L;
+    h->fbuf[0] = h->ws + L.fbuf[0];
+    h->fbuf[1] = h->ws + L.fbuf[1];
+    h->reps_d = (RepDesc *)(h->ws + L.reps);
+    h->tiles_d = (Tile *)(h->ws + L.tiles);
+    h->tdev = (unsigned long long *)(h->ws + L.tdev);
+    h->flags = (unsigned *)(h->ws + L.flags);
+    h->partials = (double *)(h->ws + L.partials);
+    h->tot = (double *)(h->ws + L.tot);
+    h->rho_tmp = (double *)(h->ws + L.rho_tmp);
+
+    long long off = 0, node_off = 0;
+    size_t acc_off = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        h->reps.push_back(describe(p[r], precision, off, node_off));
+        h->acc_off.push_back(acc_off);
+        h->nsamples.push_back(0);
+        const long long n = (long long)p[r].nx * p[r].ny;
+        off += 9 * n;
+        node_off += n;
+        acc_off += (size_t)9 * p[r].ny * (p[r].nx / 2 + 1);
+    }
+
+    hipError_t e = hipMemcpyAsync(h->reps_d, h->reps.data(), sizeof(RepDesc) * n_rep, hipMemcpyHostToDevice, h->stream);
+    const unsigned long long zero64 = 0;
+    const unsigned zero32[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h->tdev, &zero64, sizeof(zero64), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->flags, zero32, sizeof(zero32), hipMemcpyHostToDevice, h->stream);
+    for (int r = 0; r < n_rep && e == hipSuccess; ++r) {
+        e = launch_init(precision, h->fbuf[0], h->rho_tmp, h->reps_d, h->reps[r], r, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // rho_tmp is reused per replica
+    }
+    if (e != hipSuccess) {
+        delete h;
+        return LB_EDEVICE;
+    }
+    if ((st = autotune(h)) != LB_OK || (e = hipStreamSynchronize(h->stream)) != hipSuccess) {
+        delete h;
+        return st != LB_OK ? st : LB_EDEVICE;
+    }
+    if (features & LB_FEATURE_STRUCTURE_FACTOR) {
+        h->twx = (double *)(h->ws + L.twx);
+        h->twy = (double *)(h->ws + L.twy);
+        h->work_a = (double *)(h->ws + L.work_a);
+        h->work_b = (double *)(h->ws + L.work_b);
+        h->acc = (double *)(h->ws + L.acc);
+        e = launch_fill(h->acc, (int64_t)L.acc_elems, 0.0, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) {
+            delete h;
+            return LB_EDEVICE;
+        }
+    }
+    *out = h;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_handle *h, int64_t nsteps)
+{
+    if (!h || nsteps < 0) return LB_EINVAL;
+    long long left = nsteps;
+    while (left >= GRAPH_STEPS) {
+        if (!h->graph[h->par]) {
+            lb_status st = capture_graph(h, h->par);
+            if (st != LB_OK) return st;
+        }
+        if (hipGraphLaunch(h->graph[h->par], h->stream) != hipSuccess) return LB_EDEVICE;
+        left -= GRAPH_STEPS;
+        h->t += GRAPH_STEPS;
+    }
+    if (left > 0) {
+        for (int k = 0; k < left; ++k) {
+            if (step_once(h, h->par, k, h->stream) != hipSuccess) return LB_EDEVICE;
+            h->par ^= 1;
+        }
+        if (launch_advance_time(h->tdev, left, h->stream) != hipSuccess) return LB_EDEVICE;
+        h->t += left;
+    }
+    return LB_OK;
+}
+
+lb_status lb_moments(lb_handle *h, int32_t rep, double *d_m9, double *h_totals)
+{
+    if (!h || rep < 0 || rep >= h->n_rep) return LB_EINVAL;
+    const RepDesc &d = h->reps[rep];
+    const long long n = (long long)d.nx * d.ny;
+    int nb = (int)std::min<long long>(MAX_RED_BLOCKS, (n + 255) / 256);
+    if (launch_moments(h->precision, h->fbuf[h->par], h->reps_d, d, rep, d_m9, h->partials, nb, h->tot, h->stream) !=
+        hipSuccess)
+        return LB_EDEVICE;
+    if (h_totals &&
+        hipMemcpyAsync(h_totals, h->tot, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+        return LB_EDEVICE;
+    return hip_ok(hipStreamSynchronize(h->stream));
+}
+
+lb_status lb_structure_factor(lb_handle *h, int32_t op, int32_t rep, double *out, int64_t *nsamples)
+{
+    if (!h) return LB_EINVAL;
+    if (!(h->features & LB_FEATURE_STRUCTURE_FACTOR)) return LB_ESTATE;
+    if (rep < -1 || rep >= h->n_rep) return LB_EINVAL;
+    const int r0 = rep < 0 ? 0 : rep, r1 = rep < 0 ? h->n_rep : rep + 1;
+    for (int r = r0; r < r1; ++r) {
+        const RepDesc &d = h->reps[r];
+        if (!is_pow2(d.nx) || !is_pow2(d.ny) || d.nx > SK_MAX || d.ny > SK_MAX || d.nx < 4 || d.ny < 4)
+            return LB_EINVAL;
+    }
+    switch (op) {
+    case LB_SK_RESET:
+        for (int r = r0; r < r1; ++r) {
+            const RepDesc &d = h->reps[r];
+            if (launch_fill(h->acc + h->acc_off[r], (int64_t)9 * d.ny * (d.nx / 2 + 1), 0.0, h->stream) != hipSuccess)
+                return LB_EDEVICE;
+            h->nsamples[r] = 0;
+        }
+        return LB_OK;
+    case LB_SK_SAMPLE:
+        for (int r = r0; r < r1; ++r) {
+            const RepDesc &d = h->reps[r];
+            if (d.nx != h->sk_nx) {
+                if (launch_twiddles(h->twx, d.nx, h->stream) != hipSuccess) return LB_EDEVICE;
+                h->sk_nx = d.nx;
+            }
+            if (d.ny != h->sk_ny) {
+                if (launch_twiddles(h->twy, d.ny, h->stream) != hipSuccess) return LB_EDEVICE;
+                h->sk_ny = d.ny;
+            }
+            SkPlan plan{d.nx, d.ny, ilog2(d.nx), ilog2(d.ny), h->twx, h->twy};
+            if (launch_sk_sample(h->precision, h->fbuf[h->par], h->reps_d, d, r, plan, h->work_a, h->work_b,
+                                 h->acc + h->acc_off[r], h->stream) != hipSuccess)
+                return LB_EDEVICE;
+            h->nsamples[r] += 1;
+        }
+        return LB_OK;
+    case LB_SK_READ: {
+        if (rep < 0 || !out) return LB_EINVAL;
+        const RepDesc &d = h->reps[rep];
+        const double inv = h->nsamples[rep] > 0 ? 1.0 / (double)h->nsamples[rep] : 0.0;
+        if (launch_sk_read(h->acc + h->acc_off[rep], out, d.nx, d.ny, inv, h->stream) != hipSuccess) return LB_EDEVICE;
+        if (nsamples) *nsamples = h->nsamples[rep];
+        return hip_ok(hipStreamSynchronize(h->stream));
+    }
+    default:
+        return LB_EINVAL;
+    }
+}
+
+lb_status lb_status_flags(lb_handle *h, uint32_t *flags, int64_t *step)
+{
+    if (!h) return LB_EINVAL;
+    unsigned f = 0;
+    if (hipMemcpyAsync(&f, h->flags, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream) != hipSuccess) return LB_EDEVICE;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return LB_EDEVICE;
+    if (flags) *flags = f;
+    if (step) *step = h->t;
+    return LB_OK;
+}
+
+lb_status lb_noise_normals(uint64_t seed, uint32_t replica, uint64_t t, int64_t n, int32_t precision, double *d_out,
+                           void *stream)
+{
+    if (n < 0 || (n > 0 && !d_out) || precision < LB_FP64 || precision > LB_FP32_SHIFTED || n >= (1ll << 32))
+        return LB_EINVAL;
+    if (n == 0) return LB_OK;
+    return hip_ok(launch_normals(seed, replica, t, n, precision, d_out, (hipStream_t)stream));
+}
+
+lb_status lb_philox(uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, int64_t n, uint32_t *d_out,
+                    void *stream)
+{
+    if (n < 0 || (n > 0 && !d_out) || n >= (1ll << 32)) return LB_EINVAL;
+    if (n == 0) return LB_OK;
+    return hip_ok(launch_philox(c1, c2, c3, k0, k1, n, d_out, (hipStream_t)stream));
+}
+
+void lb_free(lb_handle *h)
+{
+    if (!h) return;
+    drop_graphs(h);
+    delete h;
+}
+
+}  // extern "C"

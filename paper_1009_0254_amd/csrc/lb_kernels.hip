@@ -1,0 +1,614 @@
+// Kernels of the fluctuating modified-equilibrium (Swift) D2Q9 lattice Boltzmann step,
+// Gross, Adhikari, Cates & Varnik, arXiv:1009.0254, for gfx950.
+//
+// Memory holds the post-collision populations f*(r, t-1); the fused step pulls
+// f_i(r, t) = f*_i(r - c_i, t-1) (streaming, eq. gen-lbe), collides and writes f*(r, t).
+// Each workgroup owns a strip of blockDim.x columns and marches down rows y0..y1-1,
+// keeping the density of rows y-1, y, y+1 in a 4-slot LDS ring so that the 9-point
+// stencils (App. B Laplacian; isotropic gradient) never re-read populations from HBM.
+// The two halo columns of the strip are pulled by lanes 0 and 1 of the first wave.
+
+#include "lb_internal.h"
+
+#include <math.h>
+
+namespace lbf {
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror & Shaw, SC'11: 10 rounds of two 32x32->64 products with the
+// multipliers 0xD2511F53 / 0xCD9E8D57 and a Weyl key schedule 0x9E3779B9 / 0xBB67AE85.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const unsigned long long p0 = (unsigned long long)0xD2511F53u * c.x;
+        const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// the six 21-bit integers of one Philox block: the top 21 bits of each word, then the
+// low 11 bits of words (0,1) and (2,3) joined (dropping one bit of words 1 and 3)
+__device__ __forceinline__ void bits21(uint4 x, uint32_t b[6])
+{
+    b[0] = x.x >> 11;
+    b[1] = x.y >> 11;
+    b[2] = x.z >> 11;
+    b[3] = x.w >> 11;
+    b[4] = ((x.x & 0x7FFu) << 10) | ((x.y & 0x7FFu) >> 1);
+    b[5] = ((x.z & 0x7FFu) << 10) | ((x.w & 0x7FFu) >> 1);
+}
+
+// Box-Muller on u = (b + 1/2) 2^-21 (exact in float and double)
+template <typename R> struct Gauss;
+
+template <> struct Gauss<float> {
+    static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, float &a, float &b)
+    {
+        const float ue = ((float)be + 0.5f) * 0x1p-21f;
+        const float uo = ((float)bo + 0.5f) * 0x1p-21f;
+        // -2 ln u = -2 ln(2) log2(u); v_log_f32 is log2, v_sin/v_cos take revolutions
+        const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ue));
+        a = r * __builtin_amdgcn_cosf(uo);
+        b = r * __builtin_amdgcn_sinf(uo);
+    }
+};
+
+template <> struct Gauss<double> {
+    static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, double &a, double &b)
+    {
+        const double ue = ((double)be + 0.5) * 0x1p-21;
+        const double uo = ((double)bo + 0.5) * 0x1p-21;
+        const double r = sqrt(-2.0 * log(ue));
+        double s, c;
+        sincospi(2.0 * uo, &s, &c);
+        a = r * c;
+        b = r * s;
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ void normals6(uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
+                                         uint32_t k1, R nu[6])
+{
+    const uint4 x = philox10(make_uint4(node, rep, (uint32_t)t, (uint32_t)(t >> 32)), k0, k1);
+    uint32_t b[6];
+    bits21(x, b);
+    Gauss<R>::pair(b[0], b[1], nu[0], nu[1]);
+    Gauss<R>::pair(b[2], b[3], nu[2], nu[3]);
+    Gauss<R>::pair(b[4], b[5], nu[4], nu[5]);
+}
+
+template <typename R> __device__ __forceinline__ R fsqrt(R v);
+template <> __device__ __forceinline__ float fsqrt<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
+template <> __device__ __forceinline__ double fsqrt<double>(double v) { return sqrt(v); }
+
+// ------------------------------------------------------------------ the collision
+// Deviations df_i = f_i - w_i rho0 in, post-collision deviations out.  Stencil values
+// are of drho = rho - rho0.  Returns status bits (LB_FLAG_*).
+template <typename R>
+__device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const RepDesc &d, uint32_t node,
+                                            unsigned long long t)
+{
+    // m = T f (Table I rows, eq. Tmat), sharing the axis / diagonal partial sums
+    const R sa = (f[1] + f[2]) + (f[3] + f[4]);
+    const R sd = (f[5] + f[6]) + (f[7] + f[8]);
+    const R drho = f[0] + sa + sd;
+    const R ax = f[1] - f[3], ay = f[2] - f[4];
+    const R d68 = f[5] - f[7], d97 = f[8] - f[6];
+    const R jx = ax + d68 + d97;
+    const R jy = ay + d68 - d97;
+    const R m4 = -2 * f[0] + sa + 4 * sd;
+    const R m5 = (f[1] + f[3]) - (f[2] + f[4]);
+    const R m6 = (f[5] + f[7]) - (f[6] + f[8]);
+    const R m7 = -ax + 2 * (d68 + d97);
+    const R m8 = -ay + 2 * (d68 - d97);
+    const R m9 = 2 * f[0] - 4 * sa + 8 * sd;
+
+    unsigned st = 0;
+    const R rho = (R)d.rho0 + drho;
+    if (!(rho == rho) || rho - rho != 0) st |= 4u;
+    const R irho = (R)1 / rho;
+
+    // local thermodynamics, x = rho - rhoc: p0 - rho sigma_s^2 and c_s^2 (Sec. II.A)
+    const R x = (R)d.xr0 + drho;
+    const R A = (R)d.A, B = (R)d.B, kap = (R)d.kappa;
+    const R x2 = x * x;
+    const R pex = (R)d.c0m * rho + rho * x * (A + B * x2) - x2 * ((R)0.5 * A + (R)0.25 * B * x2);
+    const R piso = pex - kap * rho * lap;
+
+    // Table II (C_n = 0)
+    const R jj = (jx * jx + jy * jy) * irho;
+    const R g2 = gx * gx + gy * gy;
+    const R e4 = 3 * jj + 6 * piso;
+    const R e5 = (jx * jx - jy * jy) * irho + kap * (gx * gx - gy * gy);
+    const R e6 = jx * jy * irho + kap * gx * gy;
+    const R e9 = -6 * piso - 3 * kap * g2;
+
+    // MRT relaxation m* = m + lambda (m - m^eq)
+    const R lb = (R)d.lam_b, ls = (R)d.lam_s, lq = (R)d.lam_q, le = (R)d.lam_e;
+    R s4 = m4 + lb * (m4 - e4);
+    R s5 = m5 + ls * (m5 - e5);
+    R s6 = m6 + ls * (m6 - e6);
+    R s7 = m7 + lq * m7;
+    R s8 = m8 + lq * m8;
+    R s9 = m9 + le * (m9 - e9);
+
+    if (d.noise) {
+        // xi = L nu, L L^T = Xi(0) at the local rho and c_s^2 (eq. noise-yeo at k = 0)
+        R nu[6];
+        normals6<R>(node, d.rep_id, t, d.seed_lo, d.seed_hi, nu);
+        R rr = rho;
+        if (!(rr > 0)) {
+            st |= 2u;
+            rr = 0;
+        }
+        const R xx = (R)d.xr0 + (rr - (R)d.rho0);
+        const R cs2 = ((R)d.c0m + (R)(1.0 / 3.0)) + rr * (A + 3 * B * xx * xx);
+        const R sq = fsqrt<R>(rr * (R)d.kT3);
+        const R a44 = (R)d.k44 * (2 - 3 * cs2);
+        const R a49 = (R)d.k49 * (cs2 - (R)(1.0 / 3.0));
+        const R a99 = (R)d.k99 * ((R)1.25 - (R)0.75 * cs2);
+        R l44 = 0, l94 = 0;
+        if (a44 > 0) {
+            l44 = fsqrt<R>(a44);
+            l94 = a49 / l44;
+        } else if (a44 < 0) {
+            st |= 1u;
+        }
+        R p99 = a99 - l94 * l94;
+        if (p99 < 0) {
+            st |= 1u;
+            p99 = 0;
+        }
+        const R l99 = fsqrt<R>(p99);
+        s4 += sq * l44 * nu[0];
+        s5 += sq * (R)d.l55 * nu[1];
+        s6 += sq * (R)d.l66 * nu[2];
+        s7 += sq * (R)d.l77 * nu[3];
+        s8 += sq * (R)d.l88 * nu[4];
+        s9 += sq * (l94 * nu[0] + l99 * nu[5]);
+    }
+
+    // f* = T^-1 m*, (T^-1)_ia = w_i T_ai / N_a, N = (1, 1/3, 1/3, 4, 4/9, 1/9, 2/3, 2/3, 16)
+    const R M1 = drho, M2 = 3 * jx, M3 = 3 * jy;
+    const R M4 = (R)0.25 * s4, M5 = (R)2.25 * s5, M6 = 9 * s6;
+    const R M7 = (R)1.5 * s7, M8 = (R)1.5 * s8, M9 = (R)0.0625 * s9;
+    const R a = (M1 + M4 - 4 * M9) * (R)(1.0 / 9.0);
+    const R bx = (M2 - M7) * (R)(1.0 / 9.0);
+    const R by = (M3 - M8) * (R)(1.0 / 9.0);
+    const R c5 = M5 * (R)(1.0 / 9.0);
+    const R dd = (M1 + 4 * M4 + 8 * M9) * (R)(1.0 / 36.0);
+    const R ex = (M2 + 2 * M7) * (R)(1.0 / 36.0);
+    const R ey = (M3 + 2 * M8) * (R)(1.0 / 36.0);
+    const R g = M6 * (R)(1.0 / 36.0);
+    f[0] = (M1 - 2 * M4 + 2 * M9) * (R)(4.0 / 9.0);
+    f[1] = a + bx + c5;
+    f[2] = a + by - c5;
+    f[3] = a - bx + c5;
+    f[4] = a - by - c5;
+    f[5] = dd + ex + ey + g;
+    f[6] = dd - ex + ey - g;
+    f[7] = dd - ex - ey + g;
+    f[8] = dd + ex - ey - g;
+    return st;
+}
+
+// ------------------------------------------------------------------ fused step kernel
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__restrict__ fout,
+                                              const RepDesc *__restrict__ reps, const Tile *__restrict__ tiles,
+                                              const unsigned long long *__restrict__ tdev,
+                                              unsigned *__restrict__ flags, int toff)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *ring = reinterpret_cast<R *>(smem_raw);
+    const int BX = blockDim.x;
+    const int WL = BX + 2;
+    const Tile tl = tiles[blockIdx.x];
+    const RepDesc &d = reps[tl.rep];
+    const int nx = d.nx, ny = d.ny;
+    const long long n = (long long)nx * ny;
+    const unsigned long long t = tdev[0] + (unsigned long long)toff;
+
+    // per-plane base pointers (uniform); in-plane offsets stay 32-bit
+    const S *Pl[Q];
+    S *Ql[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        Pl[i] = fin + d.off + (long long)i * n;
+        Ql[i] = fout + d.off + (long long)i * n;
+    }
+    const int tid = threadIdx.x;
+
+    R sub[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sub[i] = (R)d.sub[i];
+
+    auto wrapx = [nx](int v) { v %= nx; return v < 0 ? v + nx : v; };
+    auto wrapy = [ny](int v) { return v < 0 ? v + ny : (v >= ny ? v - ny : v); };
+
+    // own column and its neighbours
+    const int xg = tl.x0 + tid;
+    const int xw = wrapx(xg);
+    const int cm = xw == 0 ? nx - 1 : xw - 1;
+    const int cp = xw == nx - 1 ? 0 : xw + 1;
+    const bool store = xg < nx;
+    // halo column handled by lanes 0 (left) and 1 (right)
+    const bool halo = tid < 2;
+    const int hxw = wrapx(tid == 0 ? tl.x0 - 1 : tl.x0 + BX);
+    const int hcm = hxw == 0 ? nx - 1 : hxw - 1;
+    const int hcp = hxw == nx - 1 ? 0 : hxw + 1;
+    const int hslot = tid == 0 ? 0 : BX + 1;
+
+    // pulled populations of row yy at column (c0, with neighbours cl, cr)
+    auto pull = [&](int yy, int c0, int cl, int cr, R f[Q]) {
+        const int rm = wrapy(yy - 1) * nx, r0 = wrapy(yy) * nx, rp = wrapy(yy + 1) * nx;
+        f[0] = (R)Pl[0][r0 + c0] - sub[0];
+        f[1] = (R)Pl[1][r0 + cl] - sub[1];
+        f[2] = (R)Pl[2][rm + c0] - sub[2];
+        f[3] = (R)Pl[3][r0 + cr] - sub[3];
+        f[4] = (R)Pl[4][rp + c0] - sub[4];
+        f[5] = (R)Pl[5][rm + cl] - sub[5];
+        f[6] = (R)Pl[6][rm + cr] - sub[6];
+        f[7] = (R)Pl[7][rp + cr] - sub[7];
+        f[8] = (R)Pl[8][rp + cl] - sub[8];
+    };
+    auto dens = [](const R f[Q]) {
+        return f[0] + ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
+    };
+
+    R fc[Q], fn[Q];
+    // prologue: densities of rows y0-1 and y0, populations of row y0
+    {
+        R ft[Q];
+        pull(tl.y0 - 1, xw, cm, cp, ft);
+        ring[((tl.y0 - 1) & 3) * WL + tid + 1] = dens(ft);
+        pull(tl.y0, xw, cm, cp, fc);
+        ring[(tl.y0 & 3) * WL + tid + 1] = dens(fc);
+        if (halo) {
+            pull(tl.y0 - 1, hxw, hcm, hcp, ft);
+            ring[((tl.y0 - 1) & 3) * WL + hslot] = dens(ft);
+            pull(tl.y0, hxw, hcm, hcp, ft);
+            ring[(tl.y0 & 3) * WL + hslot] = dens(ft);
+        }
+    }
+
+    unsigned st = 0;
+    for (int y = tl.y0; y < tl.y1; ++y) {
+        // look-ahead row y+1
+        pull(y + 1, xw, cm, cp, fn);
+        const int sp = ((y + 1) & 3) * WL;
+        ring[sp + tid + 1] = dens(fn);
+        if (halo) {
+            R ft[Q];
+            pull(y + 1, hxw, hcm, hcp, ft);
+            ring[sp + hslot] = dens(ft);
+        }
+        __syncthreads();
+
+        const int s0 = (y & 3) * WL, sm = ((y - 1) & 3) * WL;
+        const R C = ring[s0 + tid + 1], E = ring[s0 + tid + 2], Wv = ring[s0 + tid];
+        const R N = ring[sp + tid + 1], NE = ring[sp + tid + 2], NW = ring[sp + tid];
+        const R Sv = ring[sm + tid + 1], SE = ring[sm + tid + 2], SW = ring[sm + tid];
+        // Laplacian of App. B: [4 (E + W + N + S) + (NE + NW + SW + SE) - 20 C] / 6
+        const R lap = (4 * ((E + Wv) + (N + Sv)) + ((NE + NW) + (SW + SE)) - 20 * C) * (R)(1.0 / 6.0);
+        // isotropic gradient 3 sum_i w_i c_i rho(r + c_i)
+        const R gx = (4 * (E - Wv) + (NE - NW) + (SE - SW)) * (R)(1.0 / 12.0);
+        const R gy = (4 * (N - Sv) + (NE - SE) + (NW - SW)) * (R)(1.0 / 12.0);
+
+        const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)xw;
+        st |= collide<R>(fc, lap, gx, gy, d, node, t);
+        if (store) {
+            const int o = y * nx + xw;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) Ql[i][o] = (S)(fc[i] + sub[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fc[i] = fn[i];
+    }
+    if (st && store) atomicOr(flags, st);
+}
+
+__global__ void k_advance_time(unsigned long long *tdev, long long by)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) tdev[0] += (unsigned long long)by;
+}
+
+// ------------------------------------------------------------------ initial state
+
+__device__ double init_density(const RepDesc &d, int x, int y, uint32_t rep_index)
+{
+    const double *a = d.init_arg;
+    switch (d.init_kind) {
+    case 1:
+        return a[1] + 0.5 * (a[0] - a[1]) * (tanh((y - a[2]) / a[4]) - tanh((y - a[3]) / a[4]));
+    case 2: {
+        double nu[6];
+        normals6<double>((uint32_t)y * (uint32_t)d.nx + (uint32_t)x, d.rep_id, ~0ull, d.seed_lo, d.seed_hi, nu);
+        return d.rho0 + a[0] * nu[0];
+    }
+    case 3: {
+        const double th = 2.0 * (a[0] * x / d.nx + a[1] * y / d.ny);   // in units of pi
+        return d.rho0 + a[2] * cospi(th);
+    }
+    default:
+        return d.rho0;
+    }
+}
+
+__global__ void k_init_rho(double *rho, const RepDesc *__restrict__ reps, int rep_index)
+{
+    const RepDesc &d = reps[rep_index];
+    const long long n = (long long)d.nx * d.ny;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / d.nx), x = (int)(k - (long long)y * d.nx);
+        rho[k] = init_density(d, x, y, rep_index);
+    }
+}
+
+// f(r, 0) = T^-1 m^eq(rho, u, grad rho, lap rho), written where the pull of the first
+// step finds it: slot r - c_i of plane i
+template <typename S>
+__global__ void k_init_f(S *__restrict__ f, const double *__restrict__ rho, const RepDesc *__restrict__ reps,
+                         int rep_index)
+{
+    const RepDesc &d = reps[rep_index];
+    const int nx = d.nx, ny = d.ny;
+    const long long n = (long long)nx * ny;
+    S *P = f + d.off;
+    const int cx[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int cy[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / nx), x = (int)(k - (long long)y * nx);
+        auto at = [&](int dx, int dy) {
+            int xx = x + dx, yy = y + dy;
+            xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+            yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+            return rho[(long long)yy * nx + xx];
+        };
+        const double C = at(0, 0), E = at(1, 0), W = at(-1, 0), N = at(0, 1), Sd = at(0, -1);
+        const double NE = at(1, 1), NW = at(-1, 1), SW = at(-1, -1), SE = at(1, -1);
+        const double lap = (4 * ((E + W) + (N + Sd)) + ((NE + NW) + (SW + SE)) - 20 * C) / 6.0;
+        const double gx = (4 * (E - W) + (NE - NW) + (SE - SW)) / 12.0;
+        const double gy = (4 * (N - Sd) + (NE - SE) + (NW - SW)) / 12.0;
+        double ux = 0, uy = 0;
+        if (d.init_kind == 3) {
+            const double th = 2.0 * (d.init_arg[0] * x / nx + d.init_arg[1] * y / ny);
+            const double c = cospi(th);
+            ux = d.init_arg[5] + d.init_arg[3] * c;
+            uy = d.init_arg[4] * c;
+        }
+        const double r = C;
+        const double jx = r * ux, jy = r * uy;
+        // Table II at (rho, j) with the square-gradient terms
+        const double xx = r - (d.rho0 - d.xr0);
+        const double x2 = xx * xx;
+        const double pex = d.c0m * r + r * xx * (d.A + d.B * x2) - x2 * (0.5 * d.A + 0.25 * d.B * x2);
+        const double piso = pex - d.kappa * r * lap;
+        double m[Q];
+        m[0] = r;
+        m[1] = jx;
+        m[2] = jy;
+        m[3] = 3 * (jx * jx + jy * jy) / r + 6 * piso;
+        m[4] = (jx * jx - jy * jy) / r + d.kappa * (gx * gx - gy * gy);
+        m[5] = jx * jy / r + d.kappa * gx * gy;
+        m[6] = 0;
+        m[7] = 0;
+        m[8] = -6 * piso - 3 * d.kappa * (gx * gx + gy * gy);
+        const double M1 = m[0], M2 = 3 * m[1], M3 = 3 * m[2], M4 = 0.25 * m[3], M5 = 2.25 * m[4];
+        const double M6 = 9 * m[5], M7 = 1.5 * m[6], M8 = 1.5 * m[7], M9 = 0.0625 * m[8];
+        double fo[Q];
+        fo[0] = (M1 - 2 * M4 + 2 * M9) * (4.0 / 9.0);
+        fo[1] = (M1 + M2 + M4 + M5 - M7 - 4 * M9) / 9.0;
+        fo[2] = (M1 + M3 + M4 - M5 - M8 - 4 * M9) / 9.0;
+        fo[3] = (M1 - M2 + M4 + M5 + M7 - 4 * M9) / 9.0;
+        fo[4] = (M1 - M3 + M4 - M5 + M8 - 4 * M9) / 9.0;
+        fo[5] = (M1 + M2 + M3 + 4 * M4 + M6 + 2 * M7 + 2 * M8 + 8 * M9) / 36.0;
+        fo[6] = (M1 - M2 + M3 + 4 * M4 - M6 - 2 * M7 + 2 * M8 + 8 * M9) / 36.0;
+        fo[7] = (M1 - M2 - M3 + 4 * M4 + M6 - 2 * M7 - 2 * M8 + 8 * M9) / 36.0;
+        fo[8] = (M1 + M2 - M3 + 4 * M4 - M6 + 2 * M7 - 2 * M8 + 8 * M9) / 36.0;
+        for (int i = 0; i < Q; ++i) {
+            int xs = x - cx[i], ys = y - cy[i];
+            xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+            ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+            P[i * n + (long long)ys * nx + xs] = (S)(fo[i] - d.shift[i]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ moments and totals
+
+constexpr int RED_THREADS = 256;
+
+// Pre-collision moments (pull, then m = T f in FP64) of one replica; optional planes
+// [9][ny][nx]; per-block partial sums of (rho, jx, jy, |j|^2, (-1)^x jx, (-1)^y jy).
+template <typename S>
+__global__ void __launch_bounds__(RED_THREADS) k_moments(const S *__restrict__ f, const RepDesc *__restrict__ reps,
+                                                         int rep_index, double *__restrict__ m9,
+                                                         double *__restrict__ partials)
+{
+    const RepDesc &d = reps[rep_index];
+    const int nx = d.nx, ny = d.ny;
+    const long long n = (long long)nx * ny;
+    const S *P = f + d.off;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(k / nx), x = (int)(k - (long long)y * nx);
+        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        const long long r0 = (long long)y * nx, rm = (long long)ym * nx, rp = (long long)yp * nx;
+        double g[Q];
+        g[0] = (double)P[r0 + x] + d.shift[0];
+        g[1] = (double)P[n + r0 + xm] + d.shift[1];
+        g[2] = (double)P[2 * n + rm + x] + d.shift[2];
+        g[3] = (double)P[3 * n + r0 + xp] + d.shift[3];
+        g[4] = (double)P[4 * n + rp + x] + d.shift[4];
+        g[5] = (double)P[5 * n + rm + xm] + d.shift[5];
+        g[6] = (double)P[6 * n + rm + xp] + d.shift[6];
+        g[7] = (double)P[7 * n + rp + xp] + d.shift[7];
+        g[8] = (double)P[8 * n + rp + xm] + d.shift[8];
+        const double sa = (g[1] + g[2]) + (g[3] + g[4]);
+        const double sd = (g[5] + g[6]) + (g[7] + g[8]);
+        double m[Q];
+        m[0] = g[0] + sa + sd;
+        const double ax = g[1] - g[3], ay = g[2] - g[4], d68 = g[5] - g[7], d97 = g[8] - g[6];
+        m[1] = ax + d68 + d97;
+        m[2] = ay + d68 - d97;
+        m[3] = -2 * g[0] + sa + 4 * sd;
+        m[4] = (g[1] + g[3]) - (g[2] + g[4]);
+        m[5] = (g[5] + g[7]) - (g[6] + g[8]);
+        m[6] = -ax + 2 * (d68 + d97);
+        m[7] = -ay + 2 * (d68 - d97);
+        m[8] = 2 * g[0] - 4 * sa + 8 * sd;
+        if (m9) {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) m9[a * n + k] = m[a];
+        }
+        acc[0] += m[0];
+        acc[1] += m[1];
+        acc[2] += m[2];
+        acc[3] += m[1] * m[1] + m[2] * m[2];
+        acc[4] += (x & 1) ? -m[1] : m[1];
+        acc[5] += (y & 1) ? -m[2] : m[2];
+    }
+    __shared__ double red[6][RED_THREADS];
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 6; ++c) partials[blockIdx.x * 6 + c] = red[c][0];
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_partials(const double *__restrict__ partials, int nblocks,
+                                                                 double *__restrict__ tot)
+{
+    __shared__ double red[6][RED_THREADS];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int c = 0; c < 6; ++c) acc[c] += partials[b * 6 + c];
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 6; ++c) tot[c] = red[c][0];
+}
+
+// ------------------------------------------------------------------ RNG exposure
+
+template <typename R>
+__global__ void k_normals(uint64_t seed, uint32_t replica, unsigned long long t, long long n, double *out)
+{
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        R nu[6];
+        normals6<R>((uint32_t)k, replica, t, (uint32_t)seed, (uint32_t)(seed >> 32), nu);
+        for (int j = 0; j < 6; ++j) out[6 * k + j] = (double)nu[j];
+    }
+}
+
+__global__ void k_philox(uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, long long n, uint32_t *out)
+{
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const uint4 x = philox10(make_uint4((uint32_t)k, c1, c2, c3), k0, k1);
+        out[4 * k + 0] = x.x;
+        out[4 * k + 1] = x.y;
+        out[4 * k + 2] = x.z;
+        out[4 * k + 3] = x.w;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static int grid_for(long long n, int threads, int cap = 65536)
+{
+    long long g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_step(int precision, const StepLaunch &a, hipStream_t s)
+{
+    const dim3 grid(a.ntiles), block(a.bx);
+    if (precision == 0) {
+        const size_t lds = 4 * (a.bx + 2) * sizeof(double);
+        hipLaunchKernelGGL((k_step<double, double>), grid, block, lds, s, (const double *)a.fin, (double *)a.fout,
+                           a.reps, a.tiles, a.tdev, a.flags, a.toff);
+    } else {
+        const size_t lds = 4 * (a.bx + 2) * sizeof(float);
+        hipLaunchKernelGGL((k_step<float, float>), grid, block, lds, s, (const float *)a.fin, (float *)a.fout,
+                           a.reps, a.tiles, a.tdev, a.flags, a.toff);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_time(unsigned long long *tdev, long long by, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, s, tdev, by);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int precision, void *f, double *rho_tmp, const RepDesc *d_reps, const RepDesc &h_rep,
+                       int rep_index, hipStream_t s)
+{
+    const long long n = (long long)h_rep.nx * h_rep.ny;
+    const int g = grid_for(n, 256);
+    hipLaunchKernelGGL(k_init_rho, dim3(g), dim3(256), 0, s, rho_tmp, d_reps, rep_index);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_init_f<double>, dim3(g), dim3(256), 0, s, (double *)f, rho_tmp, d_reps, rep_index);
+    else
+        hipLaunchKernelGGL(k_init_f<float>, dim3(g), dim3(256), 0, s, (float *)f, rho_tmp, d_reps, rep_index);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int precision, const void *f, const RepDesc *d_reps, const RepDesc &h_rep, int rep_index,
+                          double *d_m9, double *partials, int nblocks, double *d_tot, hipStream_t s)
+{
+    if (precision == 0)
+        hipLaunchKernelGGL(k_moments<double>, dim3(nblocks), dim3(RED_THREADS), 0, s, (const double *)f, d_reps,
+                           rep_index, d_m9, partials);
+    else
+        hipLaunchKernelGGL(k_moments<float>, dim3(nblocks), dim3(RED_THREADS), 0, s, (const float *)f, d_reps,
+                           rep_index, d_m9, partials);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(RED_THREADS), 0, s, partials, nblocks, d_tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_normals(uint64_t seed, uint32_t replica, uint64_t t, int64_t n, int precision, double *d_out,
+                          hipStream_t s)
+{
+    const int g = grid_for(n, 256);
+    if (precision == 0)
+        hipLaunchKernelGGL(k_normals<double>, dim3(g), dim3(256), 0, s, seed, replica, (unsigned long long)t,
+                           (long long)n, d_out);
+    else
+        hipLaunchKernelGGL(k_normals<float>, dim3(g), dim3(256), 0, s, seed, replica, (unsigned long long)t,
+                           (long long)n, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, int64_t n, uint32_t *d_out,
+                         hipStream_t s)
+{
+    const int g = grid_for(n, 256);
+    hipLaunchKernelGGL(k_philox, dim3(g), dim3(256), 0, s, c1, c2, c3, k0, k1, (long long)n, d_out);
+    return hipGetLastError();
+}
+
+}  // namespace lbf

@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry point,
+the Python struct matches the C layout, and parameter validation rejects what the
+model forbids (tau <= 1/2 by the stability requirement of Sec. III.A; a noise matrix
+Xi(0) that is not positive semi-definite, Sec. III.C).  No GPU is touched."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1009_0254_amd import lbfluct as L
+from paper_1009_0254_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbfluct.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:lb_status|void|const char \*)\s*\**\s*(lb_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("lb_workspace_size", "lb_init", "lb_step", "lb_moments", "lb_structure_factor",
+                 "lb_status_flags", "lb_free", "lb_strerror"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(lb_\w+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+def test_param_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "lbfluct.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(lb_params), offsetof(lb_params, rho0), offsetof(lb_params, kT),
+         offsetof(lb_params, seed), offsetof(lb_params, init_kind), offsetof(lb_params, init_arg));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    P = L.LbParams
+    assert got == [ctypes.sizeof(P), P.rho0.offset, P.kT.offset, P.seed.offset, P.init_kind.offset,
+                   P.init_arg.offset]
+
+
+def test_strerror():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert isinstance(L.lb_strerror(code), str) and L.lb_strerror(code)
+    assert L.lb_strerror(-99) == "unknown status"
+
+
+def test_workspace_size_counts_both_population_buffers():
+    c = W.single_phase(64, 48)
+    n = 64 * 48
+    b64 = L.lb_workspace_size([c], L.LB_FP64)
+    b32 = L.lb_workspace_size([c], L.LB_FP32_SHIFTED)
+    assert b64 >= 2 * 9 * n * 8 and b32 >= 2 * 9 * n * 4 and b64 > b32
+    bsk = L.lb_workspace_size([c], L.LB_FP32_SHIFTED, L.LB_FEATURE_STRUCTURE_FACTOR)
+    assert bsk >= b32 + 9 * 48 * 33 * 8
+    two = L.lb_workspace_size([c, W.single_phase(128, 128)], L.LB_FP32_SHIFTED)
+    assert two >= b32 + 2 * 9 * 128 * 128 * 4
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(tau_shear=0.5), L.LB_EINVAL),
+    (dict(tau_bulk=0.3), L.LB_EINVAL),
+    (dict(tau_eps=float("nan")), L.LB_EINVAL),
+    (dict(nx=2), L.LB_EINVAL),
+    (dict(ny=0), L.LB_EINVAL),
+    (dict(rho0=0.0), L.LB_EINVAL),
+    (dict(kT=-1e-6), L.LB_EINVAL),
+    (dict(A=0.5), L.LB_ENOTPSD),          # c_s^2 = 0.83 > 2/3 makes Xi_44 negative
+    (dict(c0sq=1.0), L.LB_ENOTPSD),
+])
+def test_validation_rejects(over, code):
+    c = W.single_phase(16, 16)
+    c.update(over)
+    with pytest.raises(L.LbError) as e:
+        L.lb_workspace_size([c], L.LB_FP32_SHIFTED)
+    assert e.value.status == code
+
+
+def test_validation_rejects_bad_precision_and_count():
+    arr = (L.LbParams * 1)()
+    arr[0] = L.make_params(W.single_phase(16, 16))
+    n = ctypes.c_size_t(0)
+    assert L.lib().lb_workspace_size(arr, 1, 7, 0, ctypes.byref(n)) == L.LB_EINVAL
+    assert L.lib().lb_workspace_size(arr, 0, 0, 0, ctypes.byref(n)) == L.LB_EINVAL
+    h = ctypes.c_void_p()
+    # a misaligned workspace pointer is rejected before any device call
+    assert L.lib().lb_init(arr, 1, 0, 0, 8, 1 << 30, None, ctypes.byref(h)) == L.LB_EINVAL
+    assert L.lib().lb_noise_normals(1, 0, 0, -1, 0, None, None) == L.LB_EINVAL
+    assert L.lib().lb_philox(0, 0, 0, 0, 0, -5, None, None) == L.LB_EINVAL
+
+
+def test_all_workloads_validate():
+    for cfg in (W.cfg1(), W.cfg2(), W.cfg3(), W.cfg5(), W.e4()):
+        assert L.lb_workspace_size([cfg], L.LB_FP32_SHIFTED) > 0
+    reps = W.cfg4()
+    assert len(reps) == 336
+    assert sum(r["nx"] * r["ny"] for r in reps) == 12_582_912
+    assert L.lb_workspace_size(reps, L.LB_FP32_SHIFTED) > 2 * 9 * 12_582_912 * 4

@@ -1,0 +1,311 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs, element by element.
+
+Error metric for moment planes (FP32-shifted storage is judged on the fluctuation, not on
+rho0 ~ 1): err_a = max_r |m_a^gpu - m_a^oracle| / max_r |m_a^oracle - mean(m_a^oracle)|.
+Tolerances: FP64 1e-11 (noise-free) / 1e-9 (noisy, since the FP64 transcendentals of the
+two sides may differ in the last bit); FP32-shifted 1e-5 (noise-free, the required
+tolerance) and 1e-4 (noisy, where single-precision Box-Muller differs from FP64 by ~1e-6
+per draw).  Integer work (Philox) is compared bit for bit.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from oracle import theory as th  # noqa: E402
+from paper_1009_0254_amd import workloads as W  # noqa: E402
+
+
+def _L():
+    from paper_1009_0254_amd import lbfluct as L
+    return L
+
+
+def say(*a):
+    print("[gpu-parity]", *a, file=sys.stderr, flush=True)
+
+
+def rel_err(mg, mo):
+    out = []
+    for a in range(9):
+        rng = np.abs(mo[a] - mo[a].mean()).max()
+        out.append(np.abs(mg[a] - mo[a]).max() / max(rng, 1e-300))
+    return np.array(out)
+
+
+def run_pair(cfg, precision, steps, chunks=1):
+    L = _L()
+    say("case", cfg.get("nx"), cfg.get("ny"), cfg.get("init"), "kT", cfg["kT"], precision, "steps", steps)
+    lat = L.Lattice(cfg, precision=precision)
+    ora = O.Oracle(cfg)
+    per = steps // chunks
+    for _ in range(chunks):
+        lat.step(per)
+        ora.step(per)
+    mg = lat.moments()
+    mo = ora.moments()
+    lat.close()
+    return mg, mo
+
+
+# ------------------------------------------------------------------ RNG
+
+
+def test_philox_bitwise():
+    L = _L()
+    n = 4096
+    out = torch.zeros(4 * n, dtype=torch.int32, device="cuda")
+    L.lb_philox(7, 123456789, 0xFFFFFFFF, 0xDEADBEEF, 0x01234567, n, out)
+    got = out.cpu().numpy().view(np.uint32).reshape(n, 4)
+    for k in list(range(0, n, 97)) + [n - 1]:
+        assert list(got[k]) == O.philox4x32_10([k, 7, 123456789, 0xFFFFFFFF], [0xDEADBEEF, 0x01234567])
+    # published known answers through the GPU path
+    for ln in open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        v = [int(s, 16) for s in ln.split()]
+        if v[0] != 0:
+            continue
+        L.lb_philox(v[1], v[2], v[3], v[4], v[5], 1, out)
+        assert list(out[:4].cpu().numpy().view(np.uint32)) == v[6:10]
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-14), (1, 3e-6)])
+def test_normals_match_oracle(precision, tol):
+    L = _L()
+    n = 20000
+    out = torch.zeros(6 * n, dtype=torch.float64, device="cuda")
+    seed, rep, t = 0x1234_5678_9ABC, 5, 3_000_000_123
+    L.lb_noise_normals(seed, rep, t, n, precision, out)
+    got = out.cpu().numpy().reshape(n, 6)
+    want = O.normals_batch(seed, rep, t, n)
+    err = np.abs(got - want) / np.maximum(1.0, np.abs(want))
+    say("normals precision", precision, "max err", err.max())
+    assert err.max() < tol
+
+
+# ------------------------------------------------------------------ initial state
+
+
+@pytest.mark.parametrize("precision", [0, 2, 1])
+@pytest.mark.parametrize("cfgf", [
+    lambda: W.wave(W.single_phase(64, 40, kT=0), 2, 1, 1e-3, 2e-3, -1e-3, U=0.01),
+    lambda: W.slab(48, 64, kT=0),
+    lambda: W.spinodal(70, 33, kT=0, seed=4),
+])
+def test_initial_moments(cfgf, precision):
+    cfg = cfgf()
+    mg, mo = run_pair(cfg, precision, 0)
+    e = rel_err(mg, mo)
+    say("init", cfg["init"], precision, e.max())
+    tol = {0: 1e-13, 2: 1e-6, 1: 1e-4}[precision]
+    assert e[:3].max() < tol
+
+
+# ------------------------------------------------------------------ deterministic dynamics
+
+
+DET = [
+    ("wave64", lambda: W.wave(W.single_phase(64, 64, kT=0), 1, 0, 1e-4, 0, 1e-4), 400),
+    ("wave_ragged", lambda: W.wave(W.single_phase(100, 37, kT=0, tau_bulk=0.7, tau_q=0.9), 3, 2, 1e-4, 1e-4, 0), 300),
+    ("flow", lambda: W.wave(W.single_phase(96, 64, kT=0), 2, 1, 1e-4, 0, 1e-4, U=0.02), 300),
+    ("slab", lambda: W.slab(64, 128, kT=0), 500),
+    ("spinodal", lambda: W.spinodal(128, 96, kT=0, amp=0.01, seed=2), 300),
+    ("tiny", lambda: W.wave(W.single_phase(3, 5, kT=0), 1, 1, 1e-4, 1e-4, 0), 100),
+]
+
+
+@pytest.mark.parametrize("label,cfgf,steps", DET, ids=[d[0] for d in DET])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-11), (2, 1e-5)])
+def test_deterministic_parity(label, cfgf, steps, precision, tol):
+    cfg = cfgf()
+    mg, mo = run_pair(cfg, precision, steps, chunks=2)
+    e = rel_err(mg, mo)
+    say(label, "precision", precision, "err rho,jx,jy", e[:3], "max all", e.max())
+    assert e[:3].max() < tol
+    assert e.max() < 10 * tol
+
+
+def test_fp32_plain_is_reported():
+    cfg = W.wave(W.single_phase(64, 64, kT=0), 1, 0, 1e-4, 0, 1e-4)
+    mg, mo = run_pair(cfg, 1, 400)
+    e = rel_err(mg, mo)
+    say("fp32 plain err rho,jx,jy", e[:3])
+    assert np.isfinite(e).all() and e[:3].max() < 1e-2
+
+
+# ------------------------------------------------------------------ noisy dynamics
+
+
+NOISY = [
+    ("cfg1_64", lambda: W.cfg1(), 2000),
+    ("ragged", lambda: W.single_phase(72, 50, kT=1e-5, seed=17, replica=3), 500),
+    ("slab", lambda: W.slab(64, 128, kT=1e-6, seed=5), 500),
+    ("e4", lambda: W.e4(64, 64, kT=1e-7), 500),
+]
+
+
+@pytest.mark.parametrize("label,cfgf,steps", NOISY, ids=[d[0] for d in NOISY])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (2, 1e-4)])
+def test_noisy_parity(label, cfgf, steps, precision, tol):
+    cfg = cfgf()
+    mg, mo = run_pair(cfg, precision, steps, chunks=2)
+    e = rel_err(mg, mo)
+    say(label, "precision", precision, "err rho,jx,jy", e[:3], "max all", e.max())
+    assert e.max() < tol
+
+
+# ------------------------------------------------------------------ ensembles, graphs, determinism
+
+
+def test_ensemble_of_uneven_replicas():
+    L = _L()
+    cfgs = [W.single_phase(64, 64, kT=3e-5, seed=11, replica=0),
+            W.single_phase(128, 96, kT=1e-6, seed=12, replica=1),
+            W.slab(64, 128, kT=1e-6, seed=13, replica=2),
+            W.wave(W.single_phase(40, 24, kT=0), 1, 1, 1e-4, 0, 1e-4)]
+    lat = L.Lattice(cfgs, precision=0)
+    lat.step(150)
+    for r, c in enumerate(cfgs):
+        o = O.Oracle(c)
+        o.step(150)
+        e = rel_err(lat.moments(r), o.moments())
+        say("ensemble replica", r, e.max())
+        assert e.max() < 1e-9
+    lat.close()
+
+
+def test_graph_replay_matches_single_steps_bitwise():
+    L = _L()
+    cfg = W.single_phase(96, 80, kT=1e-5, seed=3)
+    a = L.Lattice(cfg, precision=2)
+    a.step(70)                     # two graph replays + 6 single steps
+    b = L.Lattice(cfg, precision=2)
+    for _ in range(70):
+        b.step(1)
+    ma, mb = a.moments(), b.moments()
+    assert np.array_equal(ma, mb)
+    assert a.lb_status_flags()[1] == 70 and b.lb_status_flags()[1] == 70
+    a.close()
+    b.close()
+
+
+def test_tile_shape_does_not_change_bits(monkeypatch):
+    L = _L()
+    cfg = W.single_phase(300, 130, kT=1e-5, seed=8)
+    res = []
+    for tile in ("64,8", "256,32", "128,16", "512,64"):
+        monkeypatch.setenv("LBF_TILE", tile)
+        lat = L.Lattice(cfg, precision=2)
+        lat.step(40)
+        res.append(lat.moments())
+        lat.close()
+    for m in res[1:]:
+        assert np.array_equal(m, res[0])
+
+
+def test_conservation_fp64_and_fp32s():
+    L = _L()
+    for prec, tol in ((0, 1e-13), (2, 1e-9)):
+        cfg = W.single_phase(256, 256, kT=1e-5, seed=99)
+        lat = L.Lattice(cfg, precision=prec)
+        lat.step(3)
+        t0 = lat.totals()
+        lat.step(1)
+        t1 = lat.totals()
+        lat.step(200)
+        t2 = lat.totals()
+        say("totals", prec, t0, t1, t2)
+        assert abs(t2[0] - t0[0]) / t0[0] < tol
+        assert abs(t2[1] - t0[1]) < 1e-9 and abs(t2[2] - t0[2]) < 1e-9
+        # streaming flips the staggered momentum sums exactly in exact arithmetic
+        assert abs(t1[4] + t0[4]) < 1e-9 and abs(t1[5] + t0[5]) < 1e-9
+        lat.close()
+
+
+def test_status_flags_clean_and_clamp():
+    L = _L()
+    lat = L.Lattice(W.cfg1(), precision=2)
+    lat.step(100)
+    f, t = lat.lb_status_flags()
+    assert f == 0 and t == 100
+    lat.close()
+    # a density field whose local c_s^2 exceeds 2/3 somewhere makes Xi_44 negative there:
+    # the pivot is clamped (flag), never NaN
+    cfg = W.spinodal(64, 64, kT=1e-6, seed=3, amp=0.25)
+    cfg.update(c0sq=1.0 / 3.0, A=0.05, B=4.0)
+    lat = L.Lattice(cfg, precision=0)
+    lat.step(2)
+    f, _ = lat.lb_status_flags()
+    assert f & L.LB_FLAG_CLAMPED_PIVOT
+    assert not (f & L.LB_FLAG_NAN)
+    o = O.Oracle(cfg)
+    o.step(2)
+    assert o.flags[0] > 0
+    e = rel_err(lat.moments(), o.moments())
+    assert e.max() < 1e-9
+    lat.close()
+
+
+# ------------------------------------------------------------------ structure factor
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (2, 1e-4)])
+def test_structure_factor_matches_oracle_fft(precision, tol):
+    L = _L()
+    cfg = W.single_phase(64, 32, kT=1e-5, seed=31)
+    lat = L.Lattice(cfg, precision=precision, structure_factor=True)
+    ora = O.Oracle(cfg)
+    acc = np.zeros((9, 32, 33))
+    for _ in range(5):
+        lat.step(7)
+        ora.step(7)
+        lat.lb_structure_factor(L.LB_SK_SAMPLE, 0)
+        acc += O.power_spectrum(ora.moments())
+    S, ns = lat.lb_structure_factor(L.LB_SK_READ, 0)
+    S = S.cpu().numpy()
+    want = acc / 5
+    assert ns == 5
+    mask = np.ones_like(want, dtype=bool)
+    mask[:, 0, 0] = False                     # k = 0 carries the conserved totals
+    err = np.abs(S - want)[mask].max() / want[mask].max()
+    say("S(k) precision", precision, "err", err)
+    assert err < tol
+    lat.lb_structure_factor(L.LB_SK_RESET, -1)
+    S2, ns2 = lat.lb_structure_factor(L.LB_SK_READ, 0)
+    assert ns2 == 0 and float(S2.abs().max()) == 0.0
+    lat.close()
+
+
+# ------------------------------------------------------------------ full size, sampled
+
+
+def test_full_size_8192_sampled_parity():
+    """The bench workload (8192^2 single phase, FP32-shifted, autotuned tiles): one and
+    two steps against the oracle on the full lattice, compared at sampled nodes."""
+    L = _L()
+    cfg = W.cfg3()
+    lat = L.Lattice(cfg, precision=2)
+    ora = O.Oracle(cfg)
+    rng = np.random.default_rng(0)
+    idx = rng.integers(0, 8192 * 8192, size=200_000)
+    for s in (1, 1):
+        lat.step(s)
+        ora.step(s)
+        mg, _ = lat.lb_moments(0, True)
+        mg = mg.reshape(9, -1)[:, torch.from_numpy(idx).to(mg.device)].cpu().numpy()
+        mo = ora.moments().reshape(9, -1)[:, idx]
+        scale = np.abs(mo - mo.mean(axis=1, keepdims=True)).max(axis=1)
+        e = np.abs(mg - mo).max(axis=1) / scale
+        say("8192^2 t=", ora.t, "err", e)
+        assert e.max() < 1e-5
+    t = lat.totals()
+    assert abs(t[0] - 8192.0 * 8192.0) / (8192.0 * 8192.0) < 1e-9
+    lat.close()
