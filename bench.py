@@ -52,10 +52,11 @@ def time_precision(torch, L, cfg, precision, steps, warmup):
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     flags, t = lat.lb_status_flags()
+    tune = lat.lb_tuning()
     lat.close()
     del lat
     torch.cuda.empty_cache()
-    return wall, ev_ms, flags, t
+    return wall, ev_ms, flags, tune
 
 
 def traffic_from_counters():
@@ -124,7 +125,7 @@ def main():
     n = cfg["nx"] * cfg["ny"]
     log("workload", args.workload, cfg["nx"], "x", cfg["ny"], "precision", prec)
 
-    wall, ev_ms, flags, t = time_precision(torch, L, cfg, prec, args.steps, args.warmup)
+    wall, ev_ms, flags, tune = time_precision(torch, L, cfg, prec, args.steps, args.warmup)
     ms = wall * 1e3 / args.steps
     kern_ms = ev_ms / args.steps
     mlups = n * args.steps / wall / 1e6
@@ -137,19 +138,21 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"d2q9 fluctuating Swift model, {cfg['nx']}x{cfg['ny']} periodic single phase, "
                                f"kT={cfg['kT']}, FP32-shifted populations",
-                   "nx": cfg["nx"], "ny": cfg["ny"], "precision": prec, "parallelism": "single GPU"},
+                   "nx": cfg["nx"], "ny": cfg["ny"], "precision": prec, "parallelism": "single GPU",
+                   "tile": {"strip_width": tune[0], "rows": tune[1], "tiles": tune[2]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(),
                      "kernel": "k_step<float,float>", "bytes_per_update": BYTES_PER_UPDATE[prec]},
         "status_flags": flags,
     }
     if not args.no_fp64:
-        w64, e64, f64, _ = time_precision(torch, L, cfg, "fp64", max(args.steps // 2, 10), args.warmup // 2 + 1)
+        w64, e64, f64, tune64 = time_precision(torch, L, cfg, "fp64", max(args.steps // 2, 10), args.warmup // 2 + 1)
         s64 = max(args.steps // 2, 10)
         k64 = e64 / s64
         out["fp64"] = {"value": n * s64 / w64 / 1e6, "unit": "MLUPS", "ms_per_step": w64 * 1e3 / s64,
                        "achieved_GBs": BYTES_PER_UPDATE["fp64"] * n / (k64 * 1e-3) / 1e9,
-                       "frac": BYTES_PER_UPDATE["fp64"] * n / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                       "frac": BYTES_PER_UPDATE["fp64"] * n / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "tile": {"strip_width": tune64[0], "rows": tune64[1]}}
         out["fp32s_over_fp64"] = out["value"] / out["fp64"]["value"]
         log(f"fp64: {out['fp64']['ms_per_step']:.4f} ms/step, {out['fp64']['value']:.0f} MLUPS")
     if not args.no_cpu_baseline:

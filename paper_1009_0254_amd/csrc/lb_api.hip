@@ -165,6 +165,35 @@ struct lb_handle {
 
 namespace {
 
+template <typename R> void fill_consts(Consts<R> &c, const lb_params &q, const double sub[9])
+{
+    const double lb = -1.0 / q.tau_bulk, ls = -1.0 / q.tau_shear, lq = -1.0 / q.tau_q, le = -1.0 / q.tau_eps;
+    // Xi(0) = -(rho kT / sigma_s^2) X with X of eq. (noise-yeo) at k = 0;
+    // tilde-lambda_a = lambda_a (2 + lambda_a), tilde-lambda_{e eps} = lambda_e + lambda_eps + lambda_e lambda_eps
+    const double ltb = lb * (2 + lb), lts = ls * (2 + ls), ltq = lq * (2 + lq), lte = le * (2 + le);
+    const double ltbe = lb + le + lb * le;
+    const double N[9] = {1, 1.0 / 3, 1.0 / 3, 4, 4.0 / 9, 1.0 / 9, 2.0 / 3, 2.0 / 3, 16};
+    c.rho0 = (R)q.rho0;
+    c.xr0 = (R)(q.rho0 - q.rhoc);
+    c.A = (R)q.A;
+    c.B = (R)q.B;
+    c.c0m = (R)(q.c0sq - 1.0 / 3.0);
+    c.kappa = (R)q.kappa;
+    c.lam_b = (R)lb;
+    c.lam_s = (R)ls;
+    c.lam_q = (R)lq;
+    c.lam_e = (R)le;
+    c.kT3 = (R)(3.0 * q.kT);
+    c.k44 = (R)(-N[3] * ltb);
+    c.k49 = (R)(-12.0 * ltbe);
+    c.k99 = (R)(-N[8] * lte);
+    c.l55 = (R)sqrt(-N[4] * lts);
+    c.l66 = (R)sqrt(-N[5] * lts);
+    c.l77 = (R)sqrt(-N[6] * ltq);
+    c.l88 = (R)sqrt(-N[7] * ltq);
+    for (int i = 0; i < 9; ++i) c.sub[i] = (R)sub[i];
+}
+
 RepDesc describe(const lb_params &q, int precision, long long off, long long node_off)
 {
     RepDesc d{};
@@ -176,35 +205,14 @@ RepDesc describe(const lb_params &q, int precision, long long off, long long nod
     d.seed_hi = (uint32_t)(q.seed >> 32);
     d.rep_id = q.replica;
     d.noise = q.kT > 0 ? 1u : 0u;
-    d.rho0 = q.rho0;
-    d.xr0 = q.rho0 - q.rhoc;
-    d.A = q.A;
-    d.B = q.B;
-    d.c0m = q.c0sq - 1.0 / 3.0;
-    d.kappa = q.kappa;
-    d.lam_b = -1.0 / q.tau_bulk;
-    d.lam_s = -1.0 / q.tau_shear;
-    d.lam_q = -1.0 / q.tau_q;
-    d.lam_e = -1.0 / q.tau_eps;
-    // Xi(0) = -(rho kT / sigma_s^2) X with X of eq. (noise-yeo) at k = 0;
-    // tilde-lambda_a = lambda_a (2 + lambda_a), tilde-lambda_{e eps} = lambda_e + lambda_eps + lambda_e lambda_eps
-    const double ltb = d.lam_b * (2 + d.lam_b), lts = d.lam_s * (2 + d.lam_s);
-    const double ltq = d.lam_q * (2 + d.lam_q), lte = d.lam_e * (2 + d.lam_e);
-    const double ltbe = d.lam_b + d.lam_e + d.lam_b * d.lam_e;
-    const double N[9] = {1, 1.0 / 3, 1.0 / 3, 4, 4.0 / 9, 1.0 / 9, 2.0 / 3, 2.0 / 3, 16};
-    d.kT3 = 3.0 * q.kT;
-    d.k44 = -N[3] * ltb;
-    d.k49 = -12.0 * ltbe;
-    d.k99 = -N[8] * lte;
-    d.l55 = sqrt(-N[4] * lts);
-    d.l66 = sqrt(-N[5] * lts);
-    d.l77 = sqrt(-N[6] * ltq);
-    d.l88 = sqrt(-N[7] * ltq);
     const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    double sub[9];
     for (int i = 0; i < 9; ++i) {
         d.shift[i] = precision == LB_FP32_SHIFTED ? w[i] * q.rho0 : 0.0;
-        d.sub[i] = w[i] * q.rho0 - d.shift[i];
+        sub[i] = w[i] * q.rho0 - d.shift[i];
     }
+    fill_consts(d.cd, q, sub);
+    fill_consts(d.cf, q, sub);
     d.init_kind = q.init_kind;
     for (int k = 0; k < 6; ++k) d.init_arg[k] = q.init_arg[k];
     return d;
@@ -546,6 +554,15 @@ lb_status lb_status_flags(lb_handle *h, uint32_t *flags, int64_t *step)
     if (hipStreamSynchronize(h->stream) != hipSuccess) return LB_EDEVICE;
     if (flags) *flags = f;
     if (step) *step = h->t;
+    return LB_OK;
+}
+
+lb_status lb_tuning(lb_handle *h, int32_t *strip_width, int32_t *rows_per_tile, int32_t *ntiles)
+{
+    if (!h) return LB_EINVAL;
+    if (strip_width) *strip_width = h->bx;
+    if (rows_per_tile) *rows_per_tile = h->rows;
+    if (ntiles) *ntiles = h->ntiles;
     return LB_OK;
 }
 

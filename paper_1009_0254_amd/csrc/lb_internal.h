@@ -8,7 +8,23 @@ namespace lbf {
 
 constexpr int Q = 9;
 
-// Per-replica constants, uploaded once by lb_init.  The populations of replica r live
+// Per-replica constants of the collision in the arithmetic type R of a kernel (float or
+// double), so that kernels read them as scalars without conversions.
+template <typename R> struct Consts {
+    R rho0;
+    R xr0;           // rho0 - rhoc
+    R A, B;
+    R c0m;           // c0sq - 1/3
+    R kappa;
+    R lam_b, lam_s, lam_q, lam_e;   // lambda_a = -1/tau_a
+    R kT3;           // 3 kT = rho kT / sigma_s^2 per unit density
+    R k44, k49, k99; // Xi(0)/(3 rho kT): (4,4) = k44 (2 - 3 c_s^2), (4,9) = k49 (c_s^2 - 1/3),
+                     // (9,9) = k99 (5/4 - 3 c_s^2 / 4)
+    R l55, l66, l77, l88;   // sqrt of Xi(0)_aa / (3 rho kT), a = 5..8
+    R sub[9];        // df_i = s_i - sub_i (see RepDesc)
+};
+
+// Per-replica description, uploaded once by lb_init.  The populations of replica r live
 // at element offset `off` of each population buffer as planes [9][ny][nx].
 // Stored value s_i and population f_i are related by f_i = s_i + shift_i; kernels work
 // on the deviation df_i = f_i - w_i rho0 = s_i - sub_i with sub_i = w_i rho0 - shift_i.
@@ -17,21 +33,16 @@ struct RepDesc {
     int64_t off;          // element offset of plane 0 in a population buffer
     int64_t node_off;     // node offset of this replica in replica-concatenated node arrays
     uint32_t seed_lo, seed_hi, rep_id, noise;
-    double rho0;
-    double xr0;           // rho0 - rhoc
-    double A, B;
-    double c0m;           // c0sq - 1/3
-    double kappa;
-    double lam_b, lam_s, lam_q, lam_e;   // lambda_a = -1/tau_a
-    double kT3;           // 3 kT = rho kT / sigma_s^2 per unit density
-    double k44, k49, k99; // Xi(0)/(3 rho kT): (4,4) = k44 (2 - 3 c_s^2), (4,9) = k49 (c_s^2 - 1/3),
-                          // (9,9) = k99 (5/4 - 3 c_s^2 / 4)
-    double l55, l66, l77, l88;   // sqrt of Xi(0)_aa / (3 rho kT), a = 5..8
-    double sub[Q];
+    Consts<double> cd;
+    Consts<float> cf;
     double shift[Q];
     int32_t init_kind, pad_;
     double init_arg[6];
 };
+
+template <typename R> __host__ __device__ inline const Consts<R> &consts(const RepDesc &d);
+template <> __host__ __device__ inline const Consts<double> &consts<double>(const RepDesc &d) { return d.cd; }
+template <> __host__ __device__ inline const Consts<float> &consts<float>(const RepDesc &d) { return d.cf; }
 
 // A unit of work of the fused step: replica `rep`, columns [x0, x0 + blockDim.x)
 // (wrapped modulo nx, stored only where < nx), rows [y0, y1).

@@ -7,6 +7,8 @@
 // keeping the density of rows y-1, y, y+1 in a 4-slot LDS ring so that the 9-point
 // stencils (App. B Laplacian; isotropic gradient) never re-read populations from HBM.
 // The two halo columns of the strip are pulled by lanes 0 and 1 of the first wave.
+// Loads run two rows ahead: while row y collides, the populations of row y+2 are in
+// flight (on gfx950 a workgroup barrier only waits for LDS, not for global loads).
 
 #include "lb_internal.h"
 
@@ -86,6 +88,21 @@ __device__ __forceinline__ void normals6(uint32_t node, uint32_t rep, unsigned l
     Gauss<R>::pair(b[4], b[5], nu[4], nu[5]);
 }
 
+// element at a 32-bit byte offset from a uniform base (lets the compiler address with an
+// SGPR base and one 32-bit VGPR offset)
+template <typename S> __device__ __forceinline__ S ld_at(const S *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename S> __device__ __forceinline__ void st_at(S *base, unsigned byte_off, S v)
+{
+    *reinterpret_cast<S *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
+template <typename R> __device__ __forceinline__ R frcp(R v);
+template <> __device__ __forceinline__ float frcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <> __device__ __forceinline__ double frcp<double>(double v) { return 1.0 / v; }
+
 template <typename R> __device__ __forceinline__ R fsqrt(R v);
 template <> __device__ __forceinline__ float fsqrt<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
 template <> __device__ __forceinline__ double fsqrt<double>(double v) { return sqrt(v); }
@@ -94,8 +111,9 @@ template <> __device__ __forceinline__ double fsqrt<double>(double v) { return s
 // Deviations df_i = f_i - w_i rho0 in, post-collision deviations out.  Stencil values
 // are of drho = rho - rho0.  Returns status bits (LB_FLAG_*).
 template <typename R>
-__device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const RepDesc &d, uint32_t node,
-                                            unsigned long long t)
+__device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Consts<R> &c, uint32_t noise,
+                                            uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
+                                            uint32_t k1)
 {
     // m = T f (Table I rows, eq. Tmat), sharing the axis / diagonal partial sums
     const R sa = (f[1] + f[2]) + (f[3] + f[4]);
@@ -113,15 +131,15 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Rep
     const R m9 = 2 * f[0] - 4 * sa + 8 * sd;
 
     unsigned st = 0;
-    const R rho = (R)d.rho0 + drho;
+    const R rho = c.rho0 + drho;
     if (!(rho == rho) || rho - rho != 0) st |= 4u;
-    const R irho = (R)1 / rho;
+    const R irho = frcp<R>(rho);
 
     // local thermodynamics, x = rho - rhoc: p0 - rho sigma_s^2 and c_s^2 (Sec. II.A)
-    const R x = (R)d.xr0 + drho;
-    const R A = (R)d.A, B = (R)d.B, kap = (R)d.kappa;
+    const R x = c.xr0 + drho;
+    const R A = c.A, B = c.B, kap = c.kappa;
     const R x2 = x * x;
-    const R pex = (R)d.c0m * rho + rho * x * (A + B * x2) - x2 * ((R)0.5 * A + (R)0.25 * B * x2);
+    const R pex = c.c0m * rho + rho * x * (A + B * x2) - x2 * ((R)0.5 * A + (R)0.25 * B * x2);
     const R piso = pex - kap * rho * lap;
 
     // Table II (C_n = 0)
@@ -133,7 +151,7 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Rep
     const R e9 = -6 * piso - 3 * kap * g2;
 
     // MRT relaxation m* = m + lambda (m - m^eq)
-    const R lb = (R)d.lam_b, ls = (R)d.lam_s, lq = (R)d.lam_q, le = (R)d.lam_e;
+    const R lb = c.lam_b, ls = c.lam_s, lq = c.lam_q, le = c.lam_e;
     R s4 = m4 + lb * (m4 - e4);
     R s5 = m5 + ls * (m5 - e5);
     R s6 = m6 + ls * (m6 - e6);
@@ -141,25 +159,25 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Rep
     R s8 = m8 + lq * m8;
     R s9 = m9 + le * (m9 - e9);
 
-    if (d.noise) {
+    if (noise) {
         // xi = L nu, L L^T = Xi(0) at the local rho and c_s^2 (eq. noise-yeo at k = 0)
         R nu[6];
-        normals6<R>(node, d.rep_id, t, d.seed_lo, d.seed_hi, nu);
+        normals6<R>(node, rep, t, k0, k1, nu);
         R rr = rho;
         if (!(rr > 0)) {
             st |= 2u;
             rr = 0;
         }
-        const R xx = (R)d.xr0 + (rr - (R)d.rho0);
-        const R cs2 = ((R)d.c0m + (R)(1.0 / 3.0)) + rr * (A + 3 * B * xx * xx);
-        const R sq = fsqrt<R>(rr * (R)d.kT3);
-        const R a44 = (R)d.k44 * (2 - 3 * cs2);
-        const R a49 = (R)d.k49 * (cs2 - (R)(1.0 / 3.0));
-        const R a99 = (R)d.k99 * ((R)1.25 - (R)0.75 * cs2);
+        const R xx = c.xr0 + (rr - c.rho0);
+        const R cs2 = (c.c0m + (R)(1.0 / 3.0)) + rr * (A + 3 * B * xx * xx);
+        const R sq = fsqrt<R>(rr * c.kT3);
+        const R a44 = c.k44 * (2 - 3 * cs2);
+        const R a49 = c.k49 * (cs2 - (R)(1.0 / 3.0));
+        const R a99 = c.k99 * ((R)1.25 - (R)0.75 * cs2);
         R l44 = 0, l94 = 0;
         if (a44 > 0) {
             l44 = fsqrt<R>(a44);
-            l94 = a49 / l44;
+            l94 = a49 * frcp<R>(l44);
         } else if (a44 < 0) {
             st |= 1u;
         }
@@ -170,10 +188,10 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Rep
         }
         const R l99 = fsqrt<R>(p99);
         s4 += sq * l44 * nu[0];
-        s5 += sq * (R)d.l55 * nu[1];
-        s6 += sq * (R)d.l66 * nu[2];
-        s7 += sq * (R)d.l77 * nu[3];
-        s8 += sq * (R)d.l88 * nu[4];
+        s5 += sq * c.l55 * nu[1];
+        s6 += sq * c.l66 * nu[2];
+        s7 += sq * c.l77 * nu[3];
+        s8 += sq * c.l88 * nu[4];
         s9 += sq * (l94 * nu[0] + l99 * nu[5]);
     }
 
@@ -211,91 +229,90 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__re
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R *ring = reinterpret_cast<R *>(smem_raw);
-    const int BX = blockDim.x;
-    const int WL = BX + 2;
+    const unsigned BX = blockDim.x;
+    const unsigned WL = BX + 2;
     const Tile tl = tiles[blockIdx.x];
     const RepDesc &d = reps[tl.rep];
-    const int nx = d.nx, ny = d.ny;
-    const long long n = (long long)nx * ny;
+    const Consts<R> &c = consts<R>(d);
+    const unsigned nx = (unsigned)d.nx, ny = (unsigned)d.ny;
+    const unsigned long long n = (unsigned long long)nx * ny;
     const unsigned long long t = tdev[0] + (unsigned long long)toff;
+    const S *__restrict__ P = fin + d.off;
+    S *__restrict__ Qo = fout + d.off;
+    const unsigned tid = threadIdx.x;
 
-    // per-plane base pointers (uniform); in-plane offsets stay 32-bit
-    const S *Pl[Q];
-    S *Ql[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        Pl[i] = fin + d.off + (long long)i * n;
-        Ql[i] = fout + d.off + (long long)i * n;
-    }
-    const int tid = threadIdx.x;
-
-    R sub[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) sub[i] = (R)d.sub[i];
-
-    auto wrapx = [nx](int v) { v %= nx; return v < 0 ? v + nx : v; };
-    auto wrapy = [ny](int v) { return v < 0 ? v + ny : (v >= ny ? v - ny : v); };
-
-    // own column and its neighbours
-    const int xg = tl.x0 + tid;
-    const int xw = wrapx(xg);
-    const int cm = xw == 0 ? nx - 1 : xw - 1;
-    const int cp = xw == nx - 1 ? 0 : xw + 1;
+    // lane columns (loop invariant); x may exceed nx in a ragged or narrow strip: it wraps
+    // and such lanes only supply densities.  Columns are kept as byte offsets.
+    constexpr unsigned ES = sizeof(S);
+    const unsigned xg = (unsigned)tl.x0 + tid;
+    const unsigned xw = xg % nx;
+    const unsigned cm = (xw == 0 ? nx - 1 : xw - 1) * ES;
+    const unsigned c0 = xw * ES;
+    const unsigned cp = (xw == nx - 1 ? 0 : xw + 1) * ES;
     const bool store = xg < nx;
-    // halo column handled by lanes 0 (left) and 1 (right)
+    // halo columns of the strip, pulled by lanes 0 (left) and 1 (right)
     const bool halo = tid < 2;
-    const int hxw = wrapx(tid == 0 ? tl.x0 - 1 : tl.x0 + BX);
-    const int hcm = hxw == 0 ? nx - 1 : hxw - 1;
-    const int hcp = hxw == nx - 1 ? 0 : hxw + 1;
-    const int hslot = tid == 0 ? 0 : BX + 1;
+    const unsigned hxw = tid == 0 ? ((unsigned)tl.x0 + nx - 1) % nx : ((unsigned)tl.x0 + BX) % nx;
+    const unsigned hcm = (hxw == 0 ? nx - 1 : hxw - 1) * ES;
+    const unsigned hc0 = hxw * ES;
+    const unsigned hcp = (hxw == nx - 1 ? 0 : hxw + 1) * ES;
+    const unsigned hslot = tid == 0 ? 0 : BX + 1;
 
-    // pulled populations of row yy at column (c0, with neighbours cl, cr)
-    auto pull = [&](int yy, int c0, int cl, int cr, R f[Q]) {
-        const int rm = wrapy(yy - 1) * nx, r0 = wrapy(yy) * nx, rp = wrapy(yy + 1) * nx;
-        f[0] = (R)Pl[0][r0 + c0] - sub[0];
-        f[1] = (R)Pl[1][r0 + cl] - sub[1];
-        f[2] = (R)Pl[2][rm + c0] - sub[2];
-        f[3] = (R)Pl[3][r0 + cr] - sub[3];
-        f[4] = (R)Pl[4][rp + c0] - sub[4];
-        f[5] = (R)Pl[5][rm + cl] - sub[5];
-        f[6] = (R)Pl[6][rm + cr] - sub[6];
-        f[7] = (R)Pl[7][rp + cr] - sub[7];
-        f[8] = (R)Pl[8][rp + cl] - sub[8];
+    auto wrapy = [ny](int v) -> unsigned { return (unsigned)(v < 0 ? v + (int)ny : (v >= (int)ny ? v - (int)ny : v)); };
+
+    // pulled populations f_i(x, yy) = f*_i(x - c_i, yy - c_iy): uniform row pointers, lane
+    // byte offsets
+    auto pull = [&](int yy, unsigned o0, unsigned ol, unsigned orr, R f[Q]) {
+        const S *rm = P + (unsigned long long)wrapy(yy - 1) * nx;
+        const S *r0 = P + (unsigned long long)wrapy(yy) * nx;
+        const S *rp = P + (unsigned long long)wrapy(yy + 1) * nx;
+        f[0] = (R)ld_at(r0, o0);
+        f[1] = (R)ld_at(r0 + n, ol);
+        f[2] = (R)ld_at(rm + 2 * n, o0);
+        f[3] = (R)ld_at(r0 + 3 * n, orr);
+        f[4] = (R)ld_at(rp + 4 * n, o0);
+        f[5] = (R)ld_at(rm + 5 * n, ol);
+        f[6] = (R)ld_at(rm + 6 * n, orr);
+        f[7] = (R)ld_at(rp + 7 * n, orr);
+        f[8] = (R)ld_at(rp + 8 * n, ol);
     };
-    auto dens = [](const R f[Q]) {
-        return f[0] + ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
+    // density deviation of pulled (stored) values
+    auto dens = [&](const R f[Q]) {
+        R s = f[0] - c.sub[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) s += f[i] - c.sub[i];
+        return s;
     };
 
-    R fc[Q], fn[Q];
-    // prologue: densities of rows y0-1 and y0, populations of row y0
-    {
-        R ft[Q];
-        pull(tl.y0 - 1, xw, cm, cp, ft);
-        ring[((tl.y0 - 1) & 3) * WL + tid + 1] = dens(ft);
-        pull(tl.y0, xw, cm, cp, fc);
-        ring[(tl.y0 & 3) * WL + tid + 1] = dens(fc);
-        if (halo) {
-            pull(tl.y0 - 1, hxw, hcm, hcp, ft);
-            ring[((tl.y0 - 1) & 3) * WL + hslot] = dens(ft);
-            pull(tl.y0, hxw, hcm, hcp, ft);
-            ring[(tl.y0 & 3) * WL + hslot] = dens(ft);
-        }
+    const int y0 = tl.y0, y1 = tl.y1;
+    R fa[Q], fb[Q], fcq[Q], hv[Q];
+    // prologue: densities of rows y0-1 and y0; populations of row y0 (fa); row y0+1 and its
+    // halo in flight (fb, hv)
+    pull(y0 - 1, c0, cm, cp, fcq);
+    ring[((unsigned)(y0 - 1) & 3u) * WL + tid + 1] = dens(fcq);
+    if (halo) {
+        pull(y0 - 1, hc0, hcm, hcp, hv);
+        ring[((unsigned)(y0 - 1) & 3u) * WL + hslot] = dens(hv);
+        pull(y0, hc0, hcm, hcp, hv);
+        ring[((unsigned)y0 & 3u) * WL + hslot] = dens(hv);
     }
+    pull(y0, c0, cm, cp, fa);
+    ring[((unsigned)y0 & 3u) * WL + tid + 1] = dens(fa);
+    pull(y0 + 1, c0, cm, cp, fb);
+    if (halo) pull(y0 + 1, hc0, hcm, hcp, hv);
 
     unsigned st = 0;
-    for (int y = tl.y0; y < tl.y1; ++y) {
-        // look-ahead row y+1
-        pull(y + 1, xw, cm, cp, fn);
-        const int sp = ((y + 1) & 3) * WL;
-        ring[sp + tid + 1] = dens(fn);
-        if (halo) {
-            R ft[Q];
-            pull(y + 1, hxw, hcm, hcp, ft);
-            ring[sp + hslot] = dens(ft);
+    // one row: cur = populations of row y, nxt = row y+1 (loaded), nn receives row y+2
+    auto row = [&](int y, R cur[Q], R nxt[Q], R nn[Q]) {
+        const unsigned sp = ((unsigned)(y + 1) & 3u) * WL;
+        ring[sp + tid + 1] = dens(nxt);
+        if (halo) ring[sp + hslot] = dens(hv);
+        if (y + 1 < y1) {
+            pull(y + 2, c0, cm, cp, nn);
+            if (halo) pull(y + 2, hc0, hcm, hcp, hv);
         }
         __syncthreads();
-
-        const int s0 = (y & 3) * WL, sm = ((y - 1) & 3) * WL;
+        const unsigned s0 = ((unsigned)y & 3u) * WL, sm = ((unsigned)(y - 1) & 3u) * WL;
         const R C = ring[s0 + tid + 1], E = ring[s0 + tid + 2], Wv = ring[s0 + tid];
         const R N = ring[sp + tid + 1], NE = ring[sp + tid + 2], NW = ring[sp + tid];
         const R Sv = ring[sm + tid + 1], SE = ring[sm + tid + 2], SW = ring[sm + tid];
@@ -304,16 +321,20 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__re
         // isotropic gradient 3 sum_i w_i c_i rho(r + c_i)
         const R gx = (4 * (E - Wv) + (NE - NW) + (SE - SW)) * (R)(1.0 / 12.0);
         const R gy = (4 * (N - Sv) + (NE - SE) + (NW - SW)) * (R)(1.0 / 12.0);
-
-        const uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)xw;
-        st |= collide<R>(fc, lap, gx, gy, d, node, t);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) cur[i] -= c.sub[i];
+        st |= collide<R>(cur, lap, gx, gy, c, d.noise, (unsigned)y * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi);
         if (store) {
-            const int o = y * nx + xw;
+            S *__restrict__ o = Qo + (unsigned long long)(unsigned)y * nx;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) Ql[i][o] = (S)(fc[i] + sub[i]);
+            for (int i = 0; i < Q; ++i) st_at(o + (unsigned long long)i * n, c0, (S)(cur[i] + c.sub[i]));
         }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) fc[i] = fn[i];
+    };
+
+    for (int y = y0; y < y1; y += 3) {
+        row(y, fa, fb, fcq);
+        if (y + 1 < y1) row(y + 1, fb, fcq, fa);
+        if (y + 2 < y1) row(y + 2, fcq, fa, fb);
     }
     if (st && store) atomicOr(flags, st);
 }
@@ -334,14 +355,14 @@ __device__ double init_density(const RepDesc &d, int x, int y, uint32_t rep_inde
     case 2: {
         double nu[6];
         normals6<double>((uint32_t)y * (uint32_t)d.nx + (uint32_t)x, d.rep_id, ~0ull, d.seed_lo, d.seed_hi, nu);
-        return d.rho0 + a[0] * nu[0];
+        return d.cd.rho0 + a[0] * nu[0];
     }
     case 3: {
         const double th = 2.0 * (a[0] * x / d.nx + a[1] * y / d.ny);   // in units of pi
-        return d.rho0 + a[2] * cospi(th);
+        return d.cd.rho0 + a[2] * cospi(th);
     }
     default:
-        return d.rho0;
+        return d.cd.rho0;
     }
 }
 
@@ -390,20 +411,21 @@ __global__ void k_init_f(S *__restrict__ f, const double *__restrict__ rho, cons
         const double r = C;
         const double jx = r * ux, jy = r * uy;
         // Table II at (rho, j) with the square-gradient terms
-        const double xx = r - (d.rho0 - d.xr0);
+        const Consts<double> &c = d.cd;
+        const double xx = r - (c.rho0 - c.xr0);
         const double x2 = xx * xx;
-        const double pex = d.c0m * r + r * xx * (d.A + d.B * x2) - x2 * (0.5 * d.A + 0.25 * d.B * x2);
-        const double piso = pex - d.kappa * r * lap;
+        const double pex = c.c0m * r + r * xx * (c.A + c.B * x2) - x2 * (0.5 * c.A + 0.25 * c.B * x2);
+        const double piso = pex - c.kappa * r * lap;
         double m[Q];
         m[0] = r;
         m[1] = jx;
         m[2] = jy;
         m[3] = 3 * (jx * jx + jy * jy) / r + 6 * piso;
-        m[4] = (jx * jx - jy * jy) / r + d.kappa * (gx * gx - gy * gy);
-        m[5] = jx * jy / r + d.kappa * gx * gy;
+        m[4] = (jx * jx - jy * jy) / r + c.kappa * (gx * gx - gy * gy);
+        m[5] = jx * jy / r + c.kappa * gx * gy;
         m[6] = 0;
         m[7] = 0;
-        m[8] = -6 * piso - 3 * d.kappa * (gx * gx + gy * gy);
+        m[8] = -6 * piso - 3 * c.kappa * (gx * gx + gy * gy);
         const double M1 = m[0], M2 = 3 * m[1], M3 = 3 * m[2], M4 = 0.25 * m[3], M5 = 2.25 * m[4];
         const double M6 = 9 * m[5], M7 = 1.5 * m[6], M8 = 1.5 * m[7], M9 = 0.0625 * m[8];
         double fo[Q];

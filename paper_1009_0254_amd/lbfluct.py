@@ -69,12 +69,13 @@ def lib() -> ctypes.CDLL:
         L.lb_noise_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64,
                                        ctypes.c_int32, vp, vp]
         L.lb_philox.argtypes = [ctypes.c_uint32] * 5 + [ctypes.c_int64, vp, vp]
+        L.lb_tuning.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 3
         L.lb_free.argtypes = [vp]
         L.lb_free.restype = None
         L.lb_strerror.argtypes = [ctypes.c_int32]
         L.lb_strerror.restype = ctypes.c_char_p
         for fn in ("lb_workspace_size", "lb_init", "lb_step", "lb_moments", "lb_structure_factor",
-                   "lb_status_flags", "lb_noise_normals", "lb_philox"):
+                   "lb_status_flags", "lb_noise_normals", "lb_philox", "lb_tuning"):
             getattr(L, fn).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -184,6 +185,11 @@ class Lattice:
         t = ctypes.c_int64(0)
         _check("lb_status_flags", lib().lb_status_flags(self._h, ctypes.byref(f), ctypes.byref(t)))
         return f.value, t.value
+
+    def lb_tuning(self):
+        v = [ctypes.c_int32(0) for _ in range(3)]
+        _check("lb_tuning", lib().lb_tuning(self._h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     # -- conveniences ------------------------------------------------------------------
     step = lb_step
