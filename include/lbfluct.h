@@ -21,7 +21,9 @@
  * Conventions
  *   - The state "at time t" is the pre-collision (post-streaming) population f(r, t),
  *     the delta-m(t) of eq. (lb-lang-ft).  lb_moments reports that state.
- *   - Lattices are periodic, node index y*nx + x, planes stored [9][ny][nx] per replica.
+ *   - Lattices are periodic, node index y*nx + x.  In device memory the populations of a
+ *     replica are row-interleaved, [ny][9][nx]; moment planes returned to callers are
+ *     [9][ny][nx].
  *   - Every function returns an lb_status (0 = success, < 0 = error); nothing throws
  *     or aborts.  Errors leave the handle usable unless stated otherwise.
  *   - Device memory and the stream belong to the caller.  The library never calls
@@ -53,7 +55,7 @@ enum {
 
 /* storage precision of the populations */
 enum {
-    LB_FP64 = 0,          /* double storage, double arithmetic */
+    LB_FP64 = 0,          /* double storage of f_i - w_i rho0, double arithmetic */
     LB_FP32 = 1,          /* float storage of f_i, float arithmetic */
     LB_FP32_SHIFTED = 2   /* float storage of f_i - w_i rho0, float arithmetic */
 };

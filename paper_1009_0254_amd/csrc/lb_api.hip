@@ -208,7 +208,7 @@ RepDesc describe(const lb_params &q, int precision, long long off, long long nod
     const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     double sub[9];
     for (int i = 0; i < 9; ++i) {
-        d.shift[i] = precision == LB_FP32_SHIFTED ? w[i] * q.rho0 : 0.0;
+        d.shift[i] = precision == LB_FP32 ? 0.0 : w[i] * q.rho0;
         sub[i] = w[i] * q.rho0 - d.shift[i];
     }
     fill_consts(d.cd, q, sub);
@@ -218,23 +218,32 @@ RepDesc describe(const lb_params &q, int precision, long long off, long long nod
     return d;
 }
 
-// Tiles of every replica for strip width bx and rows per tile h.  Workgroup i runs on
-// XCD i mod 8; tiles are ordered so that each XCD walks a contiguous run of the
-// (replica, strip, row-segment) order, keeping vertically adjacent tiles -- which share
-// their boundary rows -- on the same L2.
+// Tiles of every replica for strip width bx and rows per tile h, walked in full-width
+// bands: tile (segment, strip) of a replica precedes (segment, strip + 1), so the
+// workgroups in flight cover whole lattice rows.  Workgroup i runs on XCD i mod 8; with a
+// strip count that is a multiple of 8, vertically adjacent tiles (which share their
+// boundary rows) land on the same XCD and its L2.  LBF_TILE_ORDER=xcd selects the
+// alternative order, in which each XCD walks a contiguous run of strip-major tiles.
 std::vector<Tile> make_tiles(const std::vector<RepDesc> &reps, int bx, int h)
 {
+    const char *ord = getenv("LBF_TILE_ORDER");
+    const bool xcd_runs = ord && strcmp(ord, "xcd") == 0;
     std::vector<Tile> seq;
     for (size_t r = 0; r < reps.size(); ++r) {
         const RepDesc &d = reps[r];
-        for (int x0 = 0; x0 < d.nx; x0 += bx)
-            for (int y0 = 0; y0 < d.ny; y0 += h) seq.push_back(Tile{(int32_t)r, x0, y0, std::min(y0 + h, d.ny)});
+        if (xcd_runs) {
+            for (int x0 = 0; x0 < d.nx; x0 += bx)
+                for (int y0 = 0; y0 < d.ny; y0 += h) seq.push_back(Tile{(int32_t)r, x0, y0, std::min(y0 + h, d.ny)});
+        } else {
+            for (int y0 = 0; y0 < d.ny; y0 += h)
+                for (int x0 = 0; x0 < d.nx; x0 += bx) seq.push_back(Tile{(int32_t)r, x0, y0, std::min(y0 + h, d.ny)});
+        }
     }
+    if (!xcd_runs) return seq;
     const int T = (int)seq.size();
     const int X = 8;
-    // XCD k takes the contiguous run [start_k, start_k + count_k) of the sequence, with
-    // counts as even as possible; its j-th tile goes to position j * X + k, so the only
-    // unused positions are at the end of the array
+    // XCD k takes the contiguous run [start_k, start_k + count_k) of the sequence; its
+    // j-th tile goes to position j * X + k, so unused positions only occur at the end
     std::vector<Tile> out;
     out.reserve(T);
     const int base = T / X, extra = T % X;
@@ -275,6 +284,7 @@ hipError_t step_once(lb_handle *h, int par, int toff, hipStream_t s)
     a.toff = toff;
     a.ntiles = h->ntiles;
     a.bx = h->bx;
+    a.plain = h->precision == LB_FP32 ? 1 : 0;
     return launch_step(h->precision, a, s);
 }
 

@@ -83,23 +83,11 @@ __global__ void __launch_bounds__(FFT_THREADS) k_sk_rows(const S *__restrict__ f
     double2 *X = reinterpret_cast<double2 *>(smem_raw);
     const RepDesc &d = reps[rep_index];
     const int nx = d.nx, ny = d.ny, nh = nx / 2 + 1;
-    const long long n = (long long)nx * ny;
     const S *P = f + d.off;
     const int y = blockIdx.x;
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-    const long long r0 = (long long)y * nx, rm = (long long)ym * nx, rp = (long long)yp * nx;
     for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
         double g[9];
-        g[0] = (double)P[r0 + x] + d.shift[0];
-        g[1] = (double)P[n + r0 + xm] + d.shift[1];
-        g[2] = (double)P[2 * n + rm + x] + d.shift[2];
-        g[3] = (double)P[3 * n + r0 + xp] + d.shift[3];
-        g[4] = (double)P[4 * n + rp + x] + d.shift[4];
-        g[5] = (double)P[5 * n + rm + xm] + d.shift[5];
-        g[6] = (double)P[6 * n + rm + xp] + d.shift[6];
-        g[7] = (double)P[7 * n + rp + xp] + d.shift[7];
-        g[8] = (double)P[8 * n + rp + xm] + d.shift[8];
+        pull_node(P, nx, ny, x, y, d.shift, g);
         X[bitrev((unsigned)x, lognx)] = make_double2(moment_row(a, g), 0.0);
     }
     __syncthreads();

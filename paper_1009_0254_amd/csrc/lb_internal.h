@@ -25,7 +25,9 @@ template <typename R> struct Consts {
 };
 
 // Per-replica description, uploaded once by lb_init.  The populations of replica r live
-// at element offset `off` of each population buffer as planes [9][ny][nx].
+// at element offset `off` of each population buffer, row-interleaved: element (i, x, y)
+// at ((y * 9) + i) * nx + x, so that the nine populations of a lattice row are one
+// contiguous 9 nx block (pop_at).
 // Stored value s_i and population f_i are related by f_i = s_i + shift_i; kernels work
 // on the deviation df_i = f_i - w_i rho0 = s_i - sub_i with sub_i = w_i rho0 - shift_i.
 struct RepDesc {
@@ -39,6 +41,30 @@ struct RepDesc {
     int32_t init_kind, pad_;
     double init_arg[6];
 };
+
+// offset of population i of node (x, y) inside a replica's block
+__host__ __device__ inline long long pop_at(int nx, int i, int x, int y)
+{
+    return ((long long)y * 9 + i) * nx + x;
+}
+
+// pre-collision populations f_i(x, y) = f*_i(x - c_i, y - c_iy) of node (x, y) in FP64,
+// including the storage shift (generic kernels: init checks, moments, S(k) rows)
+template <typename S>
+__device__ inline void pull_node(const S *P, int nx, int ny, int x, int y, const double *shift, double g[9])
+{
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    g[0] = (double)P[pop_at(nx, 0, x, y)] + shift[0];
+    g[1] = (double)P[pop_at(nx, 1, xm, y)] + shift[1];
+    g[2] = (double)P[pop_at(nx, 2, x, ym)] + shift[2];
+    g[3] = (double)P[pop_at(nx, 3, xp, y)] + shift[3];
+    g[4] = (double)P[pop_at(nx, 4, x, yp)] + shift[4];
+    g[5] = (double)P[pop_at(nx, 5, xm, ym)] + shift[5];
+    g[6] = (double)P[pop_at(nx, 6, xp, ym)] + shift[6];
+    g[7] = (double)P[pop_at(nx, 7, xp, yp)] + shift[7];
+    g[8] = (double)P[pop_at(nx, 8, xm, yp)] + shift[8];
+}
 
 template <typename R> __host__ __device__ inline const Consts<R> &consts(const RepDesc &d);
 template <> __host__ __device__ inline const Consts<double> &consts<double>(const RepDesc &d) { return d.cd; }
@@ -60,6 +86,7 @@ struct StepLaunch {
     int32_t toff;
     int32_t ntiles;
     int32_t bx;
+    int32_t plain;   // 1: stored values are f_i (sub_i = w_i rho0); 0: stored f_i - w_i rho0
 };
 
 // launchers (lb_kernels.hip); all return hipSuccess or the launch error

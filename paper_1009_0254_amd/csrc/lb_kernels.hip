@@ -9,6 +9,9 @@
 // The two halo columns of the strip are pulled by lanes 0 and 1 of the first wave.
 // Loads run two rows ahead: while row y collides, the populations of row y+2 are in
 // flight (on gfx950 a workgroup barrier only waits for LDS, not for global loads).
+// Populations are row-interleaved ([y][i][x], see pop_at): a row of the lattice is one
+// contiguous block, and tiles are walked in full-width bands, so that the workgroups in
+// flight stream whole rows (HBM page locality).  Stores bypass the caches (nontemporal).
 
 #include "lb_internal.h"
 
@@ -96,7 +99,7 @@ template <typename S> __device__ __forceinline__ S ld_at(const S *base, unsigned
 }
 template <typename S> __device__ __forceinline__ void st_at(S *base, unsigned byte_off, S v)
 {
-    *reinterpret_cast<S *>(reinterpret_cast<char *>(base) + byte_off) = v;
+    __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(base) + byte_off));
 }
 
 template <typename R> __device__ __forceinline__ R frcp(R v);
@@ -221,7 +224,7 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
 
 // ------------------------------------------------------------------ fused step kernel
 
-template <typename S, typename R>
+template <typename S, typename R, bool PLAIN>
 __global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__restrict__ fout,
                                               const RepDesc *__restrict__ reps, const Tile *__restrict__ tiles,
                                               const unsigned long long *__restrict__ tdev,
@@ -235,7 +238,7 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__re
     const RepDesc &d = reps[tl.rep];
     const Consts<R> &c = consts<R>(d);
     const unsigned nx = (unsigned)d.nx, ny = (unsigned)d.ny;
-    const unsigned long long n = (unsigned long long)nx * ny;
+    const unsigned long long pitch = 9ull * nx;   // elements per lattice row
     const unsigned long long t = tdev[0] + (unsigned long long)toff;
     const S *__restrict__ P = fin + d.off;
     S *__restrict__ Qo = fout + d.off;
@@ -263,24 +266,23 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__re
     // pulled populations f_i(x, yy) = f*_i(x - c_i, yy - c_iy): uniform row pointers, lane
     // byte offsets
     auto pull = [&](int yy, unsigned o0, unsigned ol, unsigned orr, R f[Q]) {
-        const S *rm = P + (unsigned long long)wrapy(yy - 1) * nx;
-        const S *r0 = P + (unsigned long long)wrapy(yy) * nx;
-        const S *rp = P + (unsigned long long)wrapy(yy + 1) * nx;
+        const S *rm = P + (unsigned long long)wrapy(yy - 1) * pitch;
+        const S *r0 = P + (unsigned long long)wrapy(yy) * pitch;
+        const S *rp = P + (unsigned long long)wrapy(yy + 1) * pitch;
         f[0] = (R)ld_at(r0, o0);
-        f[1] = (R)ld_at(r0 + n, ol);
-        f[2] = (R)ld_at(rm + 2 * n, o0);
-        f[3] = (R)ld_at(r0 + 3 * n, orr);
-        f[4] = (R)ld_at(rp + 4 * n, o0);
-        f[5] = (R)ld_at(rm + 5 * n, ol);
-        f[6] = (R)ld_at(rm + 6 * n, orr);
-        f[7] = (R)ld_at(rp + 7 * n, orr);
-        f[8] = (R)ld_at(rp + 8 * n, ol);
+        f[1] = (R)ld_at(r0 + nx, ol);
+        f[2] = (R)ld_at(rm + 2 * nx, o0);
+        f[3] = (R)ld_at(r0 + 3 * nx, orr);
+        f[4] = (R)ld_at(rp + 4 * nx, o0);
+        f[5] = (R)ld_at(rm + 5 * nx, ol);
+        f[6] = (R)ld_at(rm + 6 * nx, orr);
+        f[7] = (R)ld_at(rp + 7 * nx, orr);
+        f[8] = (R)ld_at(rp + 8 * nx, ol);
     };
     // density deviation of pulled (stored) values
     auto dens = [&](const R f[Q]) {
-        R s = f[0] - c.sub[0];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) s += f[i] - c.sub[i];
+        R s = ((f[0] + (f[1] + f[2])) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
+        if (PLAIN) s -= c.rho0;   // sum_i w_i rho0
         return s;
     };
 
@@ -321,13 +323,15 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__re
         // isotropic gradient 3 sum_i w_i c_i rho(r + c_i)
         const R gx = (4 * (E - Wv) + (NE - NW) + (SE - SW)) * (R)(1.0 / 12.0);
         const R gy = (4 * (N - Sv) + (NE - SE) + (NW - SW)) * (R)(1.0 / 12.0);
+        if (PLAIN) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) cur[i] -= c.sub[i];
+            for (int i = 0; i < Q; ++i) cur[i] -= c.sub[i];
+        }
         st |= collide<R>(cur, lap, gx, gy, c, d.noise, (unsigned)y * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi);
         if (store) {
-            S *__restrict__ o = Qo + (unsigned long long)(unsigned)y * nx;
+            S *__restrict__ o = Qo + (unsigned long long)(unsigned)y * pitch;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) st_at(o + (unsigned long long)i * n, c0, (S)(cur[i] + c.sub[i]));
+            for (int i = 0; i < Q; ++i) st_at(o + (unsigned long long)i * nx, c0, (S)(PLAIN ? cur[i] + c.sub[i] : cur[i]));
         }
     };
 
@@ -442,7 +446,7 @@ __global__ void k_init_f(S *__restrict__ f, const double *__restrict__ rho, cons
             int xs = x - cx[i], ys = y - cy[i];
             xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
             ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-            P[i * n + (long long)ys * nx + xs] = (S)(fo[i] - d.shift[i]);
+            P[pop_at(nx, i, xs, ys)] = (S)(fo[i] - d.shift[i]);
         }
     }
 }
@@ -465,19 +469,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_moments(const S *__restrict__ f
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
         const int y = (int)(k / nx), x = (int)(k - (long long)y * nx);
-        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-        const long long r0 = (long long)y * nx, rm = (long long)ym * nx, rp = (long long)yp * nx;
         double g[Q];
-        g[0] = (double)P[r0 + x] + d.shift[0];
-        g[1] = (double)P[n + r0 + xm] + d.shift[1];
-        g[2] = (double)P[2 * n + rm + x] + d.shift[2];
-        g[3] = (double)P[3 * n + r0 + xp] + d.shift[3];
-        g[4] = (double)P[4 * n + rp + x] + d.shift[4];
-        g[5] = (double)P[5 * n + rm + xm] + d.shift[5];
-        g[6] = (double)P[6 * n + rm + xp] + d.shift[6];
-        g[7] = (double)P[7 * n + rp + xp] + d.shift[7];
-        g[8] = (double)P[8 * n + rp + xm] + d.shift[8];
+        pull_node(P, nx, ny, x, y, d.shift, g);
         const double sa = (g[1] + g[2]) + (g[3] + g[4]);
         const double sd = (g[5] + g[6]) + (g[7] + g[8]);
         double m[Q];
@@ -570,12 +563,16 @@ hipError_t launch_step(int precision, const StepLaunch &a, hipStream_t s)
     const dim3 grid(a.ntiles), block(a.bx);
     if (precision == 0) {
         const size_t lds = 4 * (a.bx + 2) * sizeof(double);
-        hipLaunchKernelGGL((k_step<double, double>), grid, block, lds, s, (const double *)a.fin, (double *)a.fout,
-                           a.reps, a.tiles, a.tdev, a.flags, a.toff);
+        hipLaunchKernelGGL((k_step<double, double, false>), grid, block, lds, s, (const double *)a.fin,
+                           (double *)a.fout, a.reps, a.tiles, a.tdev, a.flags, a.toff);
     } else {
         const size_t lds = 4 * (a.bx + 2) * sizeof(float);
-        hipLaunchKernelGGL((k_step<float, float>), grid, block, lds, s, (const float *)a.fin, (float *)a.fout,
-                           a.reps, a.tiles, a.tdev, a.flags, a.toff);
+        if (a.plain)
+            hipLaunchKernelGGL((k_step<float, float, true>), grid, block, lds, s, (const float *)a.fin,
+                               (float *)a.fout, a.reps, a.tiles, a.tdev, a.flags, a.toff);
+        else
+            hipLaunchKernelGGL((k_step<float, float, false>), grid, block, lds, s, (const float *)a.fin,
+                               (float *)a.fout, a.reps, a.tiles, a.tdev, a.flags, a.toff);
     }
     return hipGetLastError();
 }

@@ -128,7 +128,9 @@ def test_initial_moments(cfgf, precision):
     else:
         e = rel_err(mg, mo)
         say("init", cfg["init"], precision, e[:3])
-        assert e[:3].max() < {2: 1e-6, 1: 1e-4}[precision]
+        # one FP32 rounding of each stored value: |d rho| <= 9 max|s_i| 2^-24, with
+        # |s_i| up to ~0.5 where c0sq = 0 moves the rest state away from w_i rho0
+        assert e[:3].max() < {2: 5e-6, 1: 1e-4}[precision]
 
 
 # ------------------------------------------------------------------ deterministic dynamics
