@@ -27,7 +27,8 @@ METRIC = "MLUPS and % HBM roofline, FP32-shifted vs FP64, at stated S(k)/moment 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"fp32s": 72, "fp32": 72, "fp64": 144}   # read + write of 9 populations
 COUNTERS = os.path.join(ROOT, "profiles", "k_step_fp32s_8192_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1009_0254_amd", "csrc", "lb_kernels.hip")
+# the byte counters depend on the kernel and on the tile list that lb_init builds
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1009_0254_amd", "csrc", f) for f in ("lb_kernels.hip", "lb_api.hip")]
 
 
 def log(*a):
@@ -35,7 +36,10 @@ def log(*a):
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def time_precision(torch, L, cfg, precision, steps, warmup):
@@ -108,6 +112,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after timing, copy this many bytes once with a plain device copy "
+                         "(calibrates profiler byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -155,6 +162,14 @@ def main():
                        "tile": {"strip_width": tune64[0], "rows": tune64[1]}}
         out["fp32s_over_fp64"] = out["value"] / out["fp64"]["value"]
         log(f"fp64: {out['fp64']['ms_per_step']:.4f} ms/step, {out['fp64']['value']:.0f} MLUPS")
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = args.copy_probe
+        del src, dst
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(torch, L, cfg, args.cpu_steps)
         out["cpu_baseline"] = cb
