@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-sk", action="store_true", help="skip timing one S(k) sample")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after timing, copy this many bytes once with a plain device copy "
                          "(calibrates profiler byte counters)")
@@ -162,6 +163,22 @@ def main():
                        "tile": {"strip_width": tune64[0], "rows": tune64[1]}}
         out["fp32s_over_fp64"] = out["value"] / out["fp64"]["value"]
         log(f"fp64: {out['fp64']['ms_per_step']:.4f} ms/step, {out['fp64']['value']:.0f} MLUPS")
+    if not args.no_sk and max(cfg["nx"], cfg["ny"]) <= 8192:
+        lat = L.Lattice(cfg, precision=prec, structure_factor=True)
+        lat.step(2)
+        lat.lb_structure_factor(L.LB_SK_SAMPLE, 0)       # twiddles, first-touch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            lat.lb_structure_factor(L.LB_SK_SAMPLE, 0)
+        torch.cuda.synchronize()
+        sk_ms = (time.perf_counter() - t0) * 1e3 / 3
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        out["structure_factor"] = {"sample_ms": sk_ms, "modes": 9, "every_steps_for_10pct_overhead":
+                                   int(round(sk_ms / (ms * 0.1)))}
+        log(f"S(k) sample of all 9 modes: {sk_ms:.2f} ms")
     if args.copy_probe:
         src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

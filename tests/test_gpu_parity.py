@@ -352,3 +352,71 @@ def test_full_size_8192_sampled_parity():
     t = lat.totals()
     assert abs(t[0] - 8192.0 * 8192.0) / (8192.0 * 8192.0) < 1e-9
     lat.close()
+
+
+# ------------------------------------------------------------------ equipartition on the GPU
+
+
+def _unc_targets(cfg, kxv, kyv, mask):
+    lam = th.relaxation_rates(cfg["tau_bulk"], cfg["tau_shear"], cfg["tau_q"], cfg["tau_eps"])
+    cs2 = th.sound_speed2(cfg["rho0"], cfg["c0sq"], cfg["A"], cfg["B"], cfg["rhoc"])
+    Gu = np.full((9, len(kyv), len(kxv)), np.nan)
+    Gp = np.full_like(Gu, np.nan)
+    for iy, ky in enumerate(kyv):
+        for ix, kx in enumerate(kxv):
+            if not mask[iy, ix]:
+                continue
+            Gu[:, iy, ix] = np.diag(th.stationary_covariance_uncorrelated(
+                kx, ky, lam, cs2, cfg["rho0"], cfg["kappa"], cfg["kT"])).real
+            Gp[:, iy, ix] = np.diag(th.equilibrium_correlations(kx, ky, cs2, cfg["rho0"], cfg["kappa"], cfg["kT"])).real
+    return Gu, Gp
+
+
+@pytest.mark.parametrize("precision", [2, 0])
+def test_equipartition_all_modes_within_one_percent(precision):
+    """S_a(k) of all nine modes from the GPU's FP64 S(k) accumulators equals the stationary
+    covariance of the linear model driven by Xi(0) (the noise the path uses) within 1% on
+    average over k, and within sampling error per |k| shell; the paper's G(k) (eq. g-mat-yeo)
+    is matched at small k."""
+    L = _L()
+    nx = ny = 64
+    cfg = W.single_phase(nx, ny, kT=1e-5, seed=101 + precision)
+    lat = L.Lattice(cfg, precision=precision, structure_factor=True)
+    lat.step(3000)
+    lat.lb_structure_factor(L.LB_SK_RESET, 0)
+    nsamp = 4000
+    for _ in range(nsamp):
+        lat.step(10)
+        lat.lb_structure_factor(L.LB_SK_SAMPLE, 0)
+    S, ns = lat.lb_structure_factor(L.LB_SK_READ, 0)
+    S = S.cpu().numpy()
+    f, _ = lat.lb_status_flags()
+    lat.close()
+    assert ns == nsamp and f == 0
+    kyv = 2 * np.pi * np.fft.fftfreq(ny)
+    kxv = 2 * np.pi * np.fft.rfftfreq(nx)
+    KX, KY = np.meshgrid(kxv, kyv)
+    mask = np.ones_like(KX, dtype=bool)
+    mask[0, 0] = False
+    undamped = ((np.abs(KX) == np.pi) & (KY == 0)) | ((KX == 0) & (np.abs(KY) == np.pi))
+    mask &= ~undamped
+    Gu, Gp = _unc_targets(cfg, kxv, kyv, mask)
+    ratio = S / Gu
+    kmag = np.sqrt(KX ** 2 + KY ** 2)
+    means = []
+    for a in range(9):
+        r = ratio[a][mask]
+        means.append(r.mean())
+        assert abs(r.mean() - 1) < 0.01, (a, r.mean())
+        # shells of width 0.25: sampling error of a shell mean, with the 10-step sampling
+        # interval well below the slowest correlation time only at small k
+        for lo in np.arange(0.0, 4.5, 0.25):
+            sel = mask & (kmag >= lo) & (kmag < lo + 0.25)
+            if sel.sum() < 20:
+                continue
+            assert abs(ratio[a][sel].mean() - 1) < 0.05, (a, lo, ratio[a][sel].mean())
+    small = mask & (kmag < 0.35)
+    pg = [(S[a][small] / Gp[a][small]).mean() for a in range(9)]
+    say("equipartition precision", precision, "mean S/G_unc", np.round(means, 4), "S/G (|k|<0.35)", np.round(pg, 3))
+    for a in range(3):
+        assert abs(pg[a] - 1) < 0.03
