@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -128,12 +128,22 @@ def main():
     from paper_1009_0254_amd import lbfluct as L
     from paper_1009_0254_amd import workloads as W
 
-    cfg = {"cfg2": W.cfg2, "cfg3": W.cfg3, "cfg5": W.cfg5}[args.workload]()
+    cfg = {"cfg2": W.cfg2, "cfg3": W.cfg3, "cfg4": W.cfg4, "cfg5": W.cfg5}[args.workload]()
     prec = "fp32s"
-    n = cfg["nx"] * cfg["ny"]
-    log("workload", args.workload, cfg["nx"], "x", cfg["ny"], "precision", prec)
+    reps = cfg if isinstance(cfg, list) else [cfg]
+    n = sum(r["nx"] * r["ny"] for r in reps)
+    if isinstance(cfg, list):
+        sizes = sorted({r["nx"] for r in reps})
+        mix = ", ".join("%d x %d^2" % (sum(1 for r in reps if r["nx"] == z), z) for z in sizes)
+        desc = (f"d2q9 fluctuating Swift model, ensemble of {len(reps)} replicas ({mix}), "
+                "kT log-uniform in [1e-6, 1e-4], FP32-shifted populations")
+        cfg = dict(nx=n, ny=1, kT=None)          # for the report only
+    else:
+        desc = (f"d2q9 fluctuating Swift model, {cfg['nx']}x{cfg['ny']} periodic "
+                f"{'two-phase' if cfg['c0sq'] == 0 else 'single phase'}, kT={cfg['kT']}, FP32-shifted populations")
+    log("workload", args.workload, desc)
 
-    wall, ev_ms, flags, tune = time_precision(torch, L, cfg, prec, args.steps, args.warmup)
+    wall, ev_ms, flags, tune = time_precision(torch, L, reps, prec, args.steps, args.warmup)
     ms = wall * 1e3 / args.steps
     kern_ms = ev_ms / args.steps
     mlups = n * args.steps / wall / 1e6
@@ -144,9 +154,8 @@ def main():
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"d2q9 fluctuating Swift model, {cfg['nx']}x{cfg['ny']} periodic single phase, "
-                               f"kT={cfg['kT']}, FP32-shifted populations",
-                   "nx": cfg["nx"], "ny": cfg["ny"], "precision": prec, "parallelism": "single GPU",
+        "config": {"workload": desc, "nodes": n, "replicas": len(reps),
+                   "nx": reps[0]["nx"], "ny": reps[0]["ny"], "precision": prec, "parallelism": "single GPU",
                    "tile": {"strip_width": tune[0], "rows": tune[1], "tiles": tune[2]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(),
@@ -154,7 +163,7 @@ def main():
         "status_flags": flags,
     }
     if not args.no_fp64:
-        w64, e64, f64, tune64 = time_precision(torch, L, cfg, "fp64", max(args.steps // 2, 10), args.warmup // 2 + 1)
+        w64, e64, f64, tune64 = time_precision(torch, L, reps, "fp64", max(args.steps // 2, 10), args.warmup // 2 + 1)
         s64 = max(args.steps // 2, 10)
         k64 = e64 / s64
         out["fp64"] = {"value": n * s64 / w64 / 1e6, "unit": "MLUPS", "ms_per_step": w64 * 1e3 / s64,
@@ -163,7 +172,7 @@ def main():
                        "tile": {"strip_width": tune64[0], "rows": tune64[1]}}
         out["fp32s_over_fp64"] = out["value"] / out["fp64"]["value"]
         log(f"fp64: {out['fp64']['ms_per_step']:.4f} ms/step, {out['fp64']['value']:.0f} MLUPS")
-    if not args.no_sk and max(cfg["nx"], cfg["ny"]) <= 8192:
+    if not args.no_sk and len(reps) == 1 and max(cfg["nx"], cfg["ny"]) <= 8192:
         lat = L.Lattice(cfg, precision=prec, structure_factor=True)
         lat.step(2)
         lat.lb_structure_factor(L.LB_SK_SAMPLE, 0)       # twiddles, first-touch
@@ -187,7 +196,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = args.copy_probe
         del src, dst
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and len(reps) == 1:
         cb, err = cpu_baseline(torch, L, cfg, args.cpu_steps)
         out["cpu_baseline"] = cb
         out["accuracy"] = {"moment_rel_err_fp32s_vs_oracle": max(err[:3]), "all_modes": err,
