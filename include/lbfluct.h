@@ -146,9 +146,11 @@ lb_status lb_structure_factor(lb_handle *h, int32_t op, int32_t rep, double *out
 /* Accumulated LB_FLAG_* bits since lb_init and the current time step t.  Synchronous. */
 lb_status lb_status_flags(lb_handle *h, uint32_t *flags, int64_t *step);
 
-/* The fused step's launch shape chosen by lb_init (strip width in lanes, rows per tile,
- * number of tiles), picked by timing candidate shapes on the caller's stream for
- * lattices of 2^22 nodes or more.  Host-only. */
+/* The fused step's launch shape chosen by lb_init: strip width in lanes, rows per tile and
+ * number of tiles.  For lattices of 2^22 nodes or more it is picked by timing candidate
+ * shapes on the caller's stream; the environment variable LBF_TILE="width,rows" pins it.
+ * The shape changes the schedule only: results are bitwise identical for every shape.
+ * Host-only; any output pointer may be NULL. */
 lb_status lb_tuning(lb_handle *h, int32_t *strip_width, int32_t *rows_per_tile, int32_t *ntiles);
 
 /* The six unit normals nu_4..nu_9 (as [n][6] doubles, device pointer) that the fused

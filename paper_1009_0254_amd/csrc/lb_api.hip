@@ -341,8 +341,10 @@ void drop_graphs(lb_handle *h)
         }
 }
 
-// time a few steps of each candidate (bx, rows) and keep the fastest; the trial steps
-// read the current buffer and overwrite the other, so the state is unchanged
+// time a few steps of each candidate (strip width, rows per tile) and keep the fastest;
+// the trial steps read the current buffer and overwrite the other, so the state is
+// unchanged.  The shape changes the schedule only, never the arithmetic: results are
+// bitwise the same for every shape.
 lb_status autotune(lb_handle *h)
 {
     int min_nx = 1 << 30;
@@ -356,27 +358,30 @@ lb_status autotune(lb_handle *h)
     int bx0 = 256;
     while (bx0 > MIN_BX && bx0 / 2 >= min_nx) bx0 /= 2;
     if (h->L.nodes < (1ll << 22)) return set_tiles(h, bx0, h->L.nodes < (1ll << 16) ? MIN_H : 16);
-
-    const int cand[][2] = {{128, 32}, {256, 16}, {256, 32}, {256, 64}, {512, 16}, {512, 32}, {128, 64}};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LB_EDEVICE;
     float best = 1e30f;
-    int bbx = bx0, brows = 32;
-    for (auto &c : cand) {
-        if (c[0] > 2 * min_nx && c[0] > bx0) continue;
-        if (set_tiles(h, c[0], c[1]) != LB_OK) continue;
-        if (step_once(h, h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
-        (void)hipEventRecord(e0, h->stream);
-        for (int k = 0; k < 3; ++k)
+    int bbx = bx0, brows = 16;
+    const int widths[] = {64, 128, 256, 512};
+    const int heights[] = {8, 16, 32, 64};
+    for (int bx : widths) {
+        // strips much wider than the narrowest replica only add idle lanes
+        if (bx > std::max(2 * min_nx, 64)) continue;
+        for (int rows : heights) {
+            if (set_tiles(h, bx, rows) != LB_OK) continue;
             if (step_once(h, h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
-        (void)hipEventRecord(e1, h->stream);
-        if (hipEventSynchronize(e1) != hipSuccess) return LB_EDEVICE;
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) {
-            best = ms;
-            bbx = c[0];
-            brows = c[1];
+            (void)hipEventRecord(e0, h->stream);
+            for (int k = 0; k < 3; ++k)
+                if (step_once(h, h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
+            (void)hipEventRecord(e1, h->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) return LB_EDEVICE;
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                bbx = bx;
+                brows = rows;
+            }
         }
     }
     (void)hipEventDestroy(e0);

@@ -287,33 +287,10 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__re
     };
 
     const int y0 = tl.y0, y1 = tl.y1;
-    R fa[Q], fb[Q], fcq[Q], hv[Q];
-    // prologue: densities of rows y0-1 and y0; populations of row y0 (fa); row y0+1 and its
-    // halo in flight (fb, hv)
-    pull(y0 - 1, c0, cm, cp, fcq);
-    ring[((unsigned)(y0 - 1) & 3u) * WL + tid + 1] = dens(fcq);
-    if (halo) {
-        pull(y0 - 1, hc0, hcm, hcp, hv);
-        ring[((unsigned)(y0 - 1) & 3u) * WL + hslot] = dens(hv);
-        pull(y0, hc0, hcm, hcp, hv);
-        ring[((unsigned)y0 & 3u) * WL + hslot] = dens(hv);
-    }
-    pull(y0, c0, cm, cp, fa);
-    ring[((unsigned)y0 & 3u) * WL + tid + 1] = dens(fa);
-    pull(y0 + 1, c0, cm, cp, fb);
-    if (halo) pull(y0 + 1, hc0, hcm, hcp, hv);
-
     unsigned st = 0;
-    // one row: cur = populations of row y, nxt = row y+1 (loaded), nn receives row y+2
-    auto row = [&](int y, R cur[Q], R nxt[Q], R nn[Q]) {
-        const unsigned sp = ((unsigned)(y + 1) & 3u) * WL;
-        ring[sp + tid + 1] = dens(nxt);
-        if (halo) ring[sp + hslot] = dens(hv);
-        if (y + 1 < y1) {
-            pull(y + 2, c0, cm, cp, nn);
-            if (halo) pull(y + 2, hc0, hcm, hcp, hv);
-        }
-        __syncthreads();
+
+    // stencils from the LDS ring and the collision of row y (populations cur, pulled)
+    auto finish_row = [&](int y, R cur[Q], unsigned sp) {
         const unsigned s0 = ((unsigned)y & 3u) * WL, sm = ((unsigned)(y - 1) & 3u) * WL;
         const R C = ring[s0 + tid + 1], E = ring[s0 + tid + 2], Wv = ring[s0 + tid];
         const R N = ring[sp + tid + 1], NE = ring[sp + tid + 2], NW = ring[sp + tid];
@@ -335,6 +312,35 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__re
         }
     };
 
+    R fa[Q], fb[Q], hv[Q];
+    // prologue: densities of rows y0-1 and y0 (own and halo columns), populations of row y0
+    pull(y0 - 1, c0, cm, cp, fb);
+    ring[((unsigned)(y0 - 1) & 3u) * WL + tid + 1] = dens(fb);
+    if (halo) {
+        pull(y0 - 1, hc0, hcm, hcp, hv);
+        ring[((unsigned)(y0 - 1) & 3u) * WL + hslot] = dens(hv);
+        pull(y0, hc0, hcm, hcp, hv);
+        ring[((unsigned)y0 & 3u) * WL + hslot] = dens(hv);
+    }
+    pull(y0, c0, cm, cp, fa);
+    ring[((unsigned)y0 & 3u) * WL + tid + 1] = dens(fa);
+
+    // row y+1 is already in flight when row y starts; row y+2 is issued before the barrier
+    // and lands while row y collides
+    R fcq[Q];
+    pull(y0 + 1, c0, cm, cp, fb);
+    if (halo) pull(y0 + 1, hc0, hcm, hcp, hv);
+    auto row = [&](int y, R cur[Q], R nxt[Q], R nn[Q]) {
+        const unsigned sp = ((unsigned)(y + 1) & 3u) * WL;
+        ring[sp + tid + 1] = dens(nxt);
+        if (halo) ring[sp + hslot] = dens(hv);
+        if (y + 1 < y1) {
+            pull(y + 2, c0, cm, cp, nn);
+            if (halo) pull(y + 2, hc0, hcm, hcp, hv);
+        }
+        __syncthreads();
+        finish_row(y, cur, sp);
+    };
     for (int y = y0; y < y1; y += 3) {
         row(y, fa, fb, fcq);
         if (y + 1 < y1) row(y + 1, fb, fcq, fa);
@@ -558,22 +564,23 @@ static int grid_for(long long n, int threads, int cap = 65536)
     return (int)g;
 }
 
-hipError_t launch_step(int precision, const StepLaunch &a, hipStream_t s)
+template <typename S, typename R, bool PLAIN>
+static void launch_step_t(const StepLaunch &a, hipStream_t s)
 {
     const dim3 grid(a.ntiles), block(a.bx);
-    if (precision == 0) {
-        const size_t lds = 4 * (a.bx + 2) * sizeof(double);
-        hipLaunchKernelGGL((k_step<double, double, false>), grid, block, lds, s, (const double *)a.fin,
-                           (double *)a.fout, a.reps, a.tiles, a.tdev, a.flags, a.toff);
-    } else {
-        const size_t lds = 4 * (a.bx + 2) * sizeof(float);
-        if (a.plain)
-            hipLaunchKernelGGL((k_step<float, float, true>), grid, block, lds, s, (const float *)a.fin,
-                               (float *)a.fout, a.reps, a.tiles, a.tdev, a.flags, a.toff);
-        else
-            hipLaunchKernelGGL((k_step<float, float, false>), grid, block, lds, s, (const float *)a.fin,
-                               (float *)a.fout, a.reps, a.tiles, a.tdev, a.flags, a.toff);
-    }
+    const size_t lds = 4 * (a.bx + 2) * sizeof(R);
+    hipLaunchKernelGGL((k_step<S, R, PLAIN>), grid, block, lds, s, (const S *)a.fin, (S *)a.fout, a.reps, a.tiles,
+                       a.tdev, a.flags, a.toff);
+}
+
+hipError_t launch_step(int precision, const StepLaunch &a, hipStream_t s)
+{
+    if (precision == 0)
+        launch_step_t<double, double, false>(a, s);
+    else if (a.plain)
+        launch_step_t<float, float, true>(a, s);
+    else
+        launch_step_t<float, float, false>(a, s);
     return hipGetLastError();
 }
 

@@ -241,7 +241,7 @@ def test_tile_shape_does_not_change_bits(monkeypatch):
     L = _L()
     cfg = W.single_phase(300, 130, kT=1e-5, seed=8)
     res = []
-    for tile in ("64,8", "256,32", "128,16", "512,64"):
+    for tile in ("64,8", "256,32", "128,16", "512,64", "256,8"):
         monkeypatch.setenv("LBF_TILE", tile)
         lat = L.Lattice(cfg, precision=2)
         lat.step(40)
