@@ -25,6 +25,11 @@
  *   7. f*_i = sum_a (T^-1)_ia m*_a, (T^-1)_ia = w_i T_ai / N_a
  *   8. streaming f_i(r + c_i, t+1) = f*_i(r, t), periodic           (eq. gen-lbe)
  *
+ * Spatially correlated noise (Sec. IV, last paragraph; Fig. 3): modes 4 and 9 take fields
+ * xi_4(r), xi_9(r) built outside this file (oracle.py: white fields, FFT, L(k) of
+ * eq. noise-yeo, inverse FFT); modes 5..8, whose entries of Xi(k) do not depend on k,
+ * stay uncorrelated with the homogeneous rho0 (lbo_step_fields).
+ *
  * Random numbers (the paper only asks for independent unit Gaussians, Sec. IV):
  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key = seed, counter =
  * (node, replica, t_lo, t_hi); the 128 output bits give six 21-bit uniforms
@@ -45,6 +50,8 @@ typedef struct {
     uint64_t seed;
     uint32_t replica;
     int32_t init_kind;
+    int32_t noise_kind;   /* 0: Xi(0) at the local rho (uncorrelated); 1: exact Xi(k) (correlated) */
+    int32_t pad_;
     double init_arg[6];
 } lbo_params;
 
@@ -416,6 +423,55 @@ void lbo_step(const lbo_params *p, double *f, int64_t nsteps, uint64_t t0, int64
         memcpy(f, fn, sizeof(double) * Q * n);
     }
     if (flags) { flags[0] += nclamp; flags[1] += nneg; }
+    free(fn); free(rho); free(lap); free(gx); free(gy);
+}
+
+/* One step with externally supplied noise of modes 4 and 9 (correlated noise): xi4, xi9
+   are [ny][nx] fields for time t; modes 5..8 use the k-independent diagonal of Xi at the
+   homogeneous state (rho0, c_s^2(rho0)) with the normals nu_5..nu_8 of (seed, node,
+   replica, t). */
+void lbo_step_fields(const lbo_params *p, double *f, uint64_t t, const double *xi4, const double *xi9)
+{
+    build_tables();
+    int64_t n = (int64_t)p->nx * p->ny;
+    double *fn = malloc(sizeof(double) * Q * n);
+    double *rho = malloc(sizeof(double) * n), *lap = malloc(sizeof(double) * n);
+    double *gx = malloc(sizeof(double) * n), *gy = malloc(sizeof(double) * n);
+    double lam[Q], X[Q][Q];
+    for (int a = 0; a < Q; a++) lam[a] = lam_of(p, a);
+    noise_covariance(p, p->rho0, sound_speed_sq(p, p->rho0), X);
+    for (int64_t k = 0; k < n; k++) {
+        double r = 0.0;
+        for (int i = 0; i < Q; i++) r += f[(int64_t)i * n + k];
+        rho[k] = r;
+    }
+    lbo_stencils(p, rho, lap, gx, gy);
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < p->ny; y++) {
+        for (int x = 0; x < p->nx; x++) {
+            int64_t k = idx(p, x, y);
+            double fl[Q], m[Q], meq[Q], xi[Q], ms[Q], nu[6];
+            for (int i = 0; i < Q; i++) fl[i] = f[(int64_t)i * n + k];
+            for (int a = 0; a < Q; a++) {
+                double s2 = 0.0;
+                for (int i = 0; i < Q; i++) s2 += Tm[a][i] * fl[i];
+                m[a] = s2;
+            }
+            equilibrium(p, rho[k], m[1], m[2], lap[k], gx[k], gy[k], meq);
+            lbo_normals(p->seed, (uint32_t)k, p->replica, t, nu);
+            for (int a = 0; a < Q; a++) xi[a] = 0.0;
+            xi[3] = xi4[k];
+            xi[8] = xi9[k];
+            for (int a = 4; a < 8; a++) xi[a] = sqrt(X[a][a]) * nu[a - 3];
+            for (int a = 0; a < Q; a++) ms[a] = m[a] + lam[a] * (m[a] - meq[a]) + xi[a];
+            for (int i = 0; i < Q; i++) {
+                double v = 0.0;
+                for (int a = 0; a < Q; a++) v += Ti[i][a] * ms[a];
+                fn[(int64_t)i * n + idx(p, x + CX[i], y + CY[i])] = v;
+            }
+        }
+    }
+    memcpy(f, fn, sizeof(double) * Q * n);
     free(fn); free(rho); free(lap); free(gx); free(gy);
 }
 

@@ -33,8 +33,15 @@ class LboParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("replica", ctypes.c_uint32),
         ("init_kind", ctypes.c_int32),
+        ("noise_kind", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
         ("init_arg", ctypes.c_double * 6),
     ]
+
+
+NOISE_KINDS = {"k0": 0, "correlated": 1}
+# counter word 1 of the white fields behind the correlated noise: replica | 2^31
+CORRELATED_STREAM = 0x80000000
 
 
 def build(force: bool = False) -> str:
@@ -72,6 +79,7 @@ def lib():
         L.lbo_noise_samples.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                         ctypes.c_int64, dp]
         L.lbo_tables.argtypes = [dp, dp, dp, dp]
+        L.lbo_step_fields.argtypes = [P, dp, ctypes.c_uint64, dp, dp]
         _lib = L
     return _lib
 
@@ -95,10 +103,48 @@ def make_params(cfg: dict) -> LboParams:
     p.seed = int(cfg.get("seed", 1))
     p.replica = int(cfg.get("replica", 0))
     p.init_kind = INIT_KINDS[cfg.get("init", "uniform")]
+    p.noise_kind = NOISE_KINDS[cfg.get("noise", "k0")]
     args = list(cfg.get("init_arg", [])) + [0.0] * 6
     for k in range(6):
         p.init_arg[k] = float(args[k])
     return p
+
+
+def correlated_noise_fields(cfg: dict, t: int):
+    """xi_4(r), xi_9(r) with <xi_a(k) xi_b(-k)> = Xi_ab(k) of eq. (noise-yeo) for a, b in {4, 9}.
+
+    White unit normals w_4, w_9 per node (Philox, counter (node, replica | 2^31, t), the
+    first two normals of the block) are transformed with the unitary FFT, multiplied by
+    the lower Cholesky factor L(k) of the (4,9) block of Xi(k) at the homogeneous state
+    (rho0, c_s^2(rho0)), with c_s^2(k) = c_s^2 + rho0 kappa k^2 and k^2 minus the App. B
+    Laplacian symbol (eq. sound-speed-k), and transformed back.  Sec. IV (last paragraph)."""
+    nx, ny = int(cfg["nx"]), int(cfg["ny"])
+    n = nx * ny
+    rep = int(cfg.get("replica", 0)) | CORRELATED_STREAM
+    z = normals_batch(int(cfg.get("seed", 1)), rep, t, n)
+    w4 = z[:, 0].reshape(ny, nx)
+    w9 = z[:, 1].reshape(ny, nx)
+    W4 = np.fft.fft2(w4) / np.sqrt(n)
+    W9 = np.fft.fft2(w9) / np.sqrt(n)
+    kx = 2 * np.pi * np.fft.fftfreq(nx)[None, :]
+    ky = 2 * np.pi * np.fft.fftfreq(ny)[:, None]
+    lap = ((4.0 / 9.0) * (np.cos(kx) + np.cos(ky)) + (2.0 / 9.0) * np.cos(kx) * np.cos(ky) - 10.0 / 9.0) * 3.0
+    rho0 = cfg.get("rho0", 1.0)
+    x = rho0 - cfg.get("rhoc", 1.0)
+    cs2 = cfg.get("c0sq", 1.0 / 3.0) + rho0 * (cfg["A"] + 3.0 * cfg["B"] * x * x)
+    cs2k = cs2 - rho0 * cfg["kappa"] * lap
+    le = -1.0 / cfg["tau_bulk"]
+    leps = -1.0 / cfg.get("tau_eps", 1.0)
+    pref = -rho0 * cfg["kT"] * 3.0
+    x44 = pref * 4.0 * (2.0 - 3.0 * cs2k) * le * (2.0 + le)
+    x49 = pref * 12.0 * (cs2k - 1.0 / 3.0) * (le + leps + le * leps)
+    x99 = pref * 16.0 * (1.25 - 0.75 * cs2k) * leps * (2.0 + leps)
+    l44 = np.sqrt(np.maximum(x44, 0.0))
+    l94 = np.where(l44 > 0, x49 / np.where(l44 > 0, l44, 1.0), 0.0)
+    l99 = np.sqrt(np.maximum(x99 - l94 * l94, 0.0))
+    xi4 = np.fft.ifft2(l44 * W4) * np.sqrt(n)
+    xi9 = np.fft.ifft2(l94 * W4 + l99 * W9) * np.sqrt(n)
+    return np.ascontiguousarray(xi4.real), np.ascontiguousarray(xi9.real)
 
 
 class Oracle:
@@ -114,6 +160,12 @@ class Oracle:
         lib().lbo_init(ctypes.byref(self.p), _dp(self.f))
 
     def step(self, nsteps: int):
+        if self.cfg.get("noise", "k0") == "correlated" and self.cfg["kT"] > 0:
+            for _ in range(int(nsteps)):
+                xi4, xi9 = correlated_noise_fields(self.cfg, self.t)
+                lib().lbo_step_fields(ctypes.byref(self.p), _dp(self.f), int(self.t), _dp(xi4), _dp(xi9))
+                self.t += 1
+            return
         lib().lbo_step(ctypes.byref(self.p), _dp(self.f), int(nsteps), int(self.t), self.flags)
         self.t += int(nsteps)
 

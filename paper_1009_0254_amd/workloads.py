@@ -16,6 +16,8 @@ Both the HIP library binding and the FP64 oracle read these dicts.  Keys:
       random   rho = rho0 + amp * N(0,1) per node (Philox, reserved counter), arg = (amp,)
       wave     rho = rho0 + a_rho cos(th), u = (U + a_ux cos(th), a_uy cos(th)),
                th = 2 pi (kx x / nx + ky y / ny), arg = (kx, ky, a_rho, a_ux, a_uy, U)
+  noise             "k0" (default): Xi(0) at the local density, uncorrelated in space;
+                    "correlated": the exact Xi(k) at rho0 (modes 4 and 9 correlated)
 
 The model is the paper's modified-equilibrium D2Q9 model; the five lattice workloads
 are the fixed benchmark set of this project (single-phase 64^2, two-phase 2048^2 slab,
@@ -101,6 +103,16 @@ def cfg4(seed: int = 11) -> list:
 def cfg5(seed: int = 5) -> dict:
     """16384x16384 spinodal quench, rho = 1 + 0.01 N(0,1), kT = 1e-6, FP32-shifted."""
     return dict(spinodal(16384, 16384, kT=1e-6, seed=seed), steps=50000, precision="fp32s")
+
+
+def e3(nx: int = 128, ny: int = 128, kT: float = 1e-7, seed: int = 4) -> dict:
+    """Correlated-noise equilibration run of Sec. V.A (kappa = 0.08, c_s ~ 0.265, tau = 1).
+
+    Double well with rho_V = 0.5, rho_L = 1, beta = 0.14, run in the liquid at rho0 = 1."""
+    beta, rv, rl = 0.14, 0.5, 1.0
+    return dict(nx=nx, ny=ny, rho0=1.0, rhoc=0.5 * (rl + rv), A=-beta * (rl - rv) ** 2, B=4 * beta,
+                kappa=0.08, c0sq=0.0, tau_bulk=1.0, tau_shear=1.0, tau_q=1.0, tau_eps=1.0,
+                kT=kT, seed=seed, init="uniform", noise="correlated")
 
 
 def e4(nx: int = 128, ny: int = 128, kT: float = 1e-7, seed: int = 3) -> dict:

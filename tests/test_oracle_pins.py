@@ -405,3 +405,78 @@ def test_equipartition_uncorrelated_noise():
                 G[:, iy, ix] = np.diag(th.equilibrium_correlations(kx, ky, cs2, 1.0, cfg["kappa"], cfg["kT"])).real
     for a in (0, 1, 2):
         assert abs((S[a][small] / G[a][small]).mean() - 1) < 0.06, a
+
+
+# ------------------------------------------------------------------ spatially correlated noise
+
+
+def _paper_fourier(field):
+    """a(k) = n^-1/2 sum_r exp(i k.r) a(r) on the numpy frequency grid (Sec. III notation)."""
+    n = field.size
+    return np.conj(np.fft.fft2(field)) / np.sqrt(n)   # real field: exp(+ikr) sum = conj of exp(-ikr) sum
+
+
+def test_correlated_noise_fields_have_the_fdt_spectrum():
+    """<xi_a(k) xi_b(-k)> of the generated fields equals Xi(k) from the FDT product form
+    A G A(-k)^T - (I + Omega) G (I + Omega(-k))^T (eq. noise-matrix) for a, b in {4, 9}."""
+    nx, ny = 16, 12
+    cfg = W.e3(nx, ny, kT=1e-6, seed=5)
+    lam = _lam(cfg)
+    cs2 = _cs2(cfg)
+    acc44 = np.zeros((ny, nx)); acc99 = np.zeros((ny, nx)); acc49 = np.zeros((ny, nx))
+    M = 300
+    for t in range(M):
+        x4, x9 = O.correlated_noise_fields(cfg, t)
+        a4, a9 = _paper_fourier(x4), _paper_fourier(x9)
+        acc44 += np.abs(a4) ** 2
+        acc99 += np.abs(a9) ** 2
+        acc49 += (a4 * np.conj(a9)).real
+    kxv = 2 * np.pi * np.fft.fftfreq(nx)
+    kyv = 2 * np.pi * np.fft.fftfreq(ny)
+    r44, r99, d49 = [], [], []
+    for iy, ky in enumerate(kyv):
+        for ix, kx in enumerate(kxv):
+            X = th.noise_matrix_fdt(kx, ky, lam, cs2, 1.0, cfg["kappa"], cfg["kT"]).real
+            r44.append(acc44[iy, ix] / M / X[3, 3])
+            r99.append(acc99[iy, ix] / M / X[8, 8])
+            d49.append((acc49[iy, ix] / M - X[3, 8]) / np.sqrt(X[3, 3] * X[8, 8]))
+    r44, r99, d49 = map(np.array, (r44, r99, d49))
+    # per k the mean of M chi-square(2)/2 draws: sd 1/sqrt(M); over all k far smaller
+    assert abs(r44.mean() - 1) < 0.02 and abs(r99.mean() - 1) < 0.02
+    assert np.abs(r44 - 1).max() < 6 / np.sqrt(M) and np.abs(r99 - 1).max() < 6 / np.sqrt(M)
+    assert abs(d49.mean()) < 0.02 and np.abs(d49).max() < 6 / np.sqrt(M)
+    # the k dependence is real: at the zone corner Xi_44 differs from Xi_44(0) by > 10%
+    X0 = th.noise_matrix_closed(0, 0, lam, cs2, 1.0, 0.0, cfg["kT"])
+    Xc = th.noise_matrix_closed(np.pi, np.pi, lam, cs2, 1.0, cfg["kappa"], cfg["kT"])
+    assert abs(Xc[3, 3] / X0[3, 3] - 1) > 0.1
+
+
+def test_equipartition_with_correlated_noise_matches_paper_G():
+    """With the exact Xi(k) every mode equilibrates to the paper's G(k) (eq. g-mat-yeo) at all k
+    (Sec. V.A, Fig. 3 parameters: kappa = 0.08, c_s = 0.265, tau = 1)."""
+    nx = ny = 16
+    cfg = W.e3(nx, ny, kT=1e-6, seed=9)
+    o = O.Oracle(cfg)
+    o.step(300)
+    acc = np.zeros((9, ny, nx // 2 + 1))
+    ns = 1500
+    for _ in range(ns):
+        o.step(3)
+        acc += O.power_spectrum(o.moments())
+    S = acc / ns
+    cs2 = _cs2(cfg)
+    kyv = 2 * np.pi * np.fft.fftfreq(ny)
+    kxv = 2 * np.pi * np.fft.rfftfreq(nx)
+    ratios = [[] for _ in range(9)]
+    for iy, ky in enumerate(kyv):
+        for ix, kx in enumerate(kxv):
+            if ix == 0 and iy == 0:
+                continue
+            G = np.diag(th.equilibrium_correlations(kx, ky, cs2, 1.0, cfg["kappa"], cfg["kT"])).real
+            for a in range(9):
+                if (a == 1 and abs(kx) == np.pi and ky == 0) or (a == 2 and kx == 0 and abs(ky) == np.pi):
+                    continue
+                ratios[a].append(S[a, iy, ix] / G[a])
+    for a in range(9):
+        r = np.array(ratios[a])
+        assert abs(r.mean() - 1) < 0.02, (a, r.mean())
