@@ -11,9 +11,12 @@
  *   - equilibrium moments: Table II with the Galilean terms C_n = 0;
  *   - square-gradient terms: Laplacian of App. B; the gradient (the paper gives none)
  *     is the isotropic d_a rho = 3 sum_i w_i c_ia rho(r + c_i);
- *   - noise: spatially uncorrelated, covariance Xi(0) of eq. (noise-yeo) at k = 0,
- *     evaluated with the local density and sound speed (Sec. IV, Sec. V.B), realised
- *     as xi = L nu with L the Cholesky factor of the modes-4..9 block (Sec. IV);
+ *   - noise: by default spatially uncorrelated, covariance Xi(0) of eq. (noise-yeo) at
+ *     k = 0, evaluated with the local density and sound speed (Sec. IV, Sec. V.B),
+ *     realised as xi = L nu with L the Cholesky factor of the modes-4..9 block (Sec. IV);
+ *     optionally spatially correlated with the exact Xi(k) of the homogeneous state
+ *     (Sec. IV, last paragraph): modes 4 and 9 from white fields filtered in Fourier space
+ *     by the Cholesky factor of their 2x2 block of Xi(k), modes 5..8 white;
  *   - nu: unit normals from Philox4x32-10 (Salmon et al., SC'11) keyed by the seed, with
  *     counter (node = y*nx + x, replica, t_lo, t_hi); the 128 bits give six 21-bit
  *     uniforms u = (b + 1/2) 2^-21 paired by Box-Muller (nu_4, nu_5), (nu_6, nu_7), (nu_8, nu_9).
@@ -70,6 +73,13 @@ enum {
                              u = (a5 + a3 cos th, a4 cos th) */
 };
 
+/* noise model of a replica (lb_params.noise_kind) */
+enum {
+    LB_NOISE_K0 = 0,          /* Xi(0) at the local rho and c_s^2(rho), uncorrelated in space */
+    LB_NOISE_CORRELATED = 1   /* exact Xi(k) at (rho0, c_s^2(rho0)); needs nx, ny powers of two
+                                 in [4, 8192] and Xi(k) positive semi-definite at every lattice k */
+};
+
 /* optional features (bit mask for lb_workspace_size / lb_init) */
 enum {
     LB_FEATURE_STRUCTURE_FACTOR = 1   /* reserve FFT buffers and S(k) accumulators */
@@ -101,8 +111,11 @@ typedef struct lb_params {
     double tau_bulk, tau_shear, tau_q, tau_eps;  /* each > 1/2 */
     double kT;                 /* >= 0; 0 gives the deterministic model */
     uint64_t seed;             /* Philox key */
-    uint32_t replica;          /* Philox counter word 1: independent streams per replica */
+    uint32_t replica;          /* Philox counter word 1: independent streams per replica, < 2^31
+                                  (the white fields of correlated noise use replica | 2^31) */
     int32_t init_kind;         /* LB_INIT_* */
+    int32_t noise_kind;        /* LB_NOISE_* */
+    int32_t reserved;          /* must be 0 */
     double init_arg[6];
 } lb_params;
 
@@ -117,14 +130,17 @@ lb_status lb_workspace_size(const lb_params *p, int32_t n_rep, int32_t precision
  * lb_workspace_size, 256-byte aligned), upload per-replica constants and write the
  * initial state f(r, 0) of every replica.  `stream` is a hipStream_t (NULL = default
  * stream).  Rejects: n_rep < 1, nx or ny < 3, rho0 <= 0, any tau <= 1/2, kT < 0,
- * unknown precision or init kind (LB_EINVAL); Xi(0) at rho0 not PSD (LB_ENOTPSD).
+ * unknown precision, init or noise kind, replica >= 2^31, correlated noise on a lattice
+ * whose sides are not powers of two in [4, 8192] (LB_EINVAL); Xi(0) at rho0 not PSD, or for
+ * correlated noise Xi(k) not PSD at some lattice k (LB_ENOTPSD).
  * Synchronous.  On success *out owns host memory only; release it with lb_free. */
 lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t features,
                   void *d_workspace, size_t bytes, void *stream, lb_handle **out);
 
 /* Advance every replica by nsteps >= 0 time steps (collision with noise, then
  * streaming: eq. gen-lbe-m / fluct-lin-lbe).  Enqueued on the stream; long runs replay
- * a captured HIP graph of the fused step kernel. */
+ * a captured HIP graph of the fused step kernel (preceded, for replicas with correlated
+ * noise, by the kernels that build that step's noise fields). */
 lb_status lb_step(lb_handle *h, int64_t nsteps);
 
 /* Moments of the current state of replica rep: if d_m9 != NULL it receives the nine

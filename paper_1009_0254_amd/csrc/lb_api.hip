@@ -44,6 +44,8 @@ size_t elem_size(int precision) { return precision == LB_FP64 ? sizeof(double) :
 struct Layout {
     size_t fbuf[2], reps, tiles, tdev, flags, partials, tot, rho_tmp;
     size_t twx, twy, work_a, work_b, acc;
+    size_t xi, cn_a, cn_b, cn_tw;     // correlated noise
+    long long cn_nodes, cn_max_n, cn_tw_elems;
     size_t total;
     long long nodes;      // sum of nx*ny
     long long max_n;      // largest replica
@@ -74,6 +76,28 @@ bool xi0_psd(const lb_params &q)
     return diag_ok && a44 >= -tol && a99 >= -tol && a44 * a99 - a49 * a49 >= -tol * (fabs(a44) + fabs(a99));
 }
 
+// Xi(k) of eq. (noise-yeo) at every k of the lattice: only the (4,9) block depends on k,
+// through c_s^2(k) = c_s^2 + rho0 kappa k^2 with the App. B Laplacian (Sec. III.C, Fig. 2)
+bool xik_psd(const lb_params &q)
+{
+    const double lb = -1.0 / q.tau_bulk, le = -1.0 / q.tau_eps;
+    const double x = q.rho0 - q.rhoc;
+    const double cs2 = q.c0sq + q.rho0 * (q.A + 3 * q.B * x * x);
+    const double PI = 3.14159265358979323846;
+    for (int ix = 0; ix <= q.nx / 2; ++ix)
+        for (int iy = 0; iy <= q.ny / 2; ++iy) {
+            const double cx = cos(2 * PI * ix / q.nx), cy = cos(2 * PI * iy / q.ny);
+            const double k2 = -3.0 * ((4.0 / 9.0) * (cx + cy) + (2.0 / 9.0) * cx * cy - 10.0 / 9.0);
+            const double c2k = cs2 + q.rho0 * q.kappa * k2;
+            const double a44 = -4.0 * lb * (2 + lb) * (2 - 3 * c2k);
+            const double a49 = -12.0 * (lb + le + lb * le) * (c2k - 1.0 / 3.0);
+            const double a99 = -16.0 * le * (2 + le) * (1.25 - 0.75 * c2k);
+            const double tol = 1e-14 * (fabs(a44) + fabs(a99) + 1e-300);
+            if (a44 < -tol || a99 < -tol || a44 * a99 - a49 * a49 < -tol * (fabs(a44) + fabs(a99))) return false;
+        }
+    return true;
+}
+
 lb_status validate(const lb_params *p, int32_t n_rep, int32_t precision)
 {
     if (!p || n_rep < 1) return LB_EINVAL;
@@ -91,7 +115,13 @@ lb_status validate(const lb_params *p, int32_t n_rep, int32_t precision)
             return LB_EINVAL;
         if (q.init_kind < LB_INIT_UNIFORM || q.init_kind > LB_INIT_WAVE) return LB_EINVAL;
         if (q.init_kind == LB_INIT_SLAB && !(q.init_arg[4] != 0)) return LB_EINVAL;
+        if (q.noise_kind != LB_NOISE_K0 && q.noise_kind != LB_NOISE_CORRELATED) return LB_EINVAL;
+        if (q.reserved != 0 || q.replica >= 0x80000000u) return LB_EINVAL;
+        if (q.noise_kind == LB_NOISE_CORRELATED &&
+            (!is_pow2(q.nx) || !is_pow2(q.ny) || q.nx < 4 || q.ny < 4 || q.nx > SK_MAX || q.ny > SK_MAX))
+            return LB_EINVAL;
         if (!xi0_psd(q)) return LB_ENOTPSD;
+        if (q.noise_kind == LB_NOISE_CORRELATED && !xik_psd(q)) return LB_ENOTPSD;
     }
     return LB_OK;
 }
@@ -112,6 +142,14 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
         L.acc_elems += (size_t)9 * p[r].ny * (p[r].nx / 2 + 1);
     }
     L.max_tiles = max_tiles_for(p, n_rep);
+    L.cn_nodes = L.cn_max_n = L.cn_tw_elems = 0;
+    for (int r = 0; r < n_rep; ++r)
+        if (p[r].noise_kind == LB_NOISE_CORRELATED && p[r].kT > 0) {
+            const long long n = (long long)p[r].nx * p[r].ny;
+            L.cn_nodes += n;
+            L.cn_max_n = std::max(L.cn_max_n, n);
+            L.cn_tw_elems += p[r].nx / 2 + p[r].ny / 2;
+        }
     size_t o = 0;
     const size_t fb = align_up((size_t)9 * L.nodes * elem_size(precision));
     L.fbuf[0] = o; o += fb;
@@ -130,6 +168,12 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
         L.work_a = o; o += cplx;
         L.work_b = o; o += cplx;
         L.acc = o; o += align_up(sizeof(double) * L.acc_elems);
+    }
+    if (L.cn_nodes > 0) {
+        L.xi = o; o += align_up((size_t)2 * L.cn_nodes * elem_size(precision));
+        L.cn_a = o; o += align_up(sizeof(double) * 2 * (size_t)L.cn_max_n);
+        L.cn_b = o; o += align_up(sizeof(double) * 2 * (size_t)L.cn_max_n);
+        L.cn_tw = o; o += align_up(sizeof(double) * 2 * (size_t)L.cn_tw_elems);
     }
     L.total = o;
     return L;
@@ -161,6 +205,10 @@ struct lb_handle {
     bool sk_ready = false;
     int sk_nx = 0, sk_ny = 0;
     double *twx = nullptr, *twy = nullptr, *work_a = nullptr, *work_b = nullptr, *acc = nullptr;
+    // correlated noise
+    std::vector<int> cn_reps;
+    void *xi = nullptr;
+    double *cn_a = nullptr, *cn_b = nullptr, *cn_tw = nullptr;
 };
 
 namespace {
@@ -191,6 +239,9 @@ template <typename R> void fill_consts(Consts<R> &c, const lb_params &q, const d
     c.l66 = (R)sqrt(-N[5] * lts);
     c.l77 = (R)sqrt(-N[6] * ltq);
     c.l88 = (R)sqrt(-N[7] * ltq);
+    c.sq0 = (R)sqrt(3.0 * q.kT * q.rho0);
+    const double x0 = q.rho0 - q.rhoc;
+    c.cs2_0 = (R)(q.c0sq + q.rho0 * (q.A + 3.0 * q.B * x0 * x0));
     for (int i = 0; i < 9; ++i) c.sub[i] = (R)sub[i];
 }
 
@@ -204,7 +255,11 @@ RepDesc describe(const lb_params &q, int precision, long long off, long long nod
     d.seed_lo = (uint32_t)q.seed;
     d.seed_hi = (uint32_t)(q.seed >> 32);
     d.rep_id = q.replica;
-    d.noise = q.kT > 0 ? 1u : 0u;
+    d.noise = q.kT > 0 ? (q.noise_kind == LB_NOISE_CORRELATED ? 2u : 1u) : 0u;
+    d.lognx = ilog2(q.nx);
+    d.logny = ilog2(q.ny);
+    d.xi_off = 0;
+    d.tw_off = 0;
     const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     double sub[9];
     for (int i = 0; i < 9; ++i) {
@@ -318,7 +373,13 @@ lb_status set_tiles(lb_handle *h, int bx, int rows)
 
 hipError_t step_once(lb_handle *h, int par, int toff, hipStream_t s)
 {
+    for (int r : h->cn_reps) {
+        hipError_t e = launch_correlated_noise(h->precision, h->reps_d, h->reps[r], r, h->cn_a, h->cn_b, h->cn_tw,
+                                               h->xi, h->tdev, toff, s);
+        if (e != hipSuccess) return e;
+    }
     StepLaunch a;
+    a.xi = h->xi;
     a.fin = h->fbuf[par];
     a.fout = h->fbuf[par ^ 1];
     a.reps = h->reps_d;
@@ -469,10 +530,23 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
     h->tot = (double *)(h->ws + L.tot);
     h->rho_tmp = (double *)(h->ws + L.rho_tmp);
 
-    long long off = 0, node_off = 0;
+    if (L.cn_nodes > 0) {
+        h->xi = h->ws + L.xi;
+        h->cn_a = (double *)(h->ws + L.cn_a);
+        h->cn_b = (double *)(h->ws + L.cn_b);
+        h->cn_tw = (double *)(h->ws + L.cn_tw);
+    }
+    long long off = 0, node_off = 0, xi_off = 0, tw_off = 0;
     size_t acc_off = 0;
     for (int r = 0; r < n_rep; ++r) {
         h->reps.push_back(describe(p[r], precision, off, node_off));
+        if (h->reps.back().noise == 2) {
+            h->reps.back().xi_off = xi_off;
+            h->reps.back().tw_off = tw_off;
+            xi_off += (long long)p[r].nx * p[r].ny;
+            tw_off += p[r].nx / 2 + p[r].ny / 2;
+            h->cn_reps.push_back(r);
+        }
         h->acc_off.push_back(acc_off);
         h->nsamples.push_back(0);
         const long long n = (long long)p[r].nx * p[r].ny;
@@ -493,6 +567,22 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
     if (e != hipSuccess) {
         delete h;
         return LB_EDEVICE;
+    }
+    if (e == hipSuccess && !h->cn_reps.empty()) {
+        int maxline = 0;
+        for (int r : h->cn_reps) {
+            const RepDesc &d = h->reps[r];
+            maxline = std::max(maxline, std::max(d.nx, d.ny));
+            double *tw = h->cn_tw + 2 * d.tw_off;
+            if (e == hipSuccess) e = launch_twiddles(tw, d.nx, h->stream);
+            if (e == hipSuccess) e = launch_twiddles(tw + 2 * (d.nx / 2), d.ny, h->stream);
+        }
+        if (e == hipSuccess) e = set_fft_lds_limit(maxline);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) {
+            delete h;
+            return LB_EDEVICE;
+        }
     }
     if ((st = autotune(h)) != LB_OK || (e = hipStreamSynchronize(h->stream)) != hipSuccess) {
         delete h;

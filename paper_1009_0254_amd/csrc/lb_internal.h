@@ -21,6 +21,8 @@ template <typename R> struct Consts {
     R k44, k49, k99; // Xi(0)/(3 rho kT): (4,4) = k44 (2 - 3 c_s^2), (4,9) = k49 (c_s^2 - 1/3),
                      // (9,9) = k99 (5/4 - 3 c_s^2 / 4)
     R l55, l66, l77, l88;   // sqrt of Xi(0)_aa / (3 rho kT), a = 5..8
+    R sq0;           // sqrt(3 kT rho0): noise scale of the homogeneous state (correlated noise)
+    R cs2_0;         // c_s^2(rho0)
     R sub[9];        // df_i = s_i - sub_i (see RepDesc)
 };
 
@@ -34,7 +36,11 @@ struct RepDesc {
     int32_t nx, ny;
     int64_t off;          // element offset of plane 0 in a population buffer
     int64_t node_off;     // node offset of this replica in replica-concatenated node arrays
-    uint32_t seed_lo, seed_hi, rep_id, noise;
+    uint32_t seed_lo, seed_hi, rep_id;
+    uint32_t noise;       // 0: none (kT = 0); 1: Xi(0) at the local state; 2: correlated Xi(k)
+    int32_t lognx, logny; // for correlated noise (powers of two)
+    int64_t xi_off;       // correlated noise: offset (in pairs) of this replica's xi_4 + i xi_9 plane
+    int64_t tw_off;       // correlated noise: offset (in double2) of its twiddles [nx/2 | ny/2]
     Consts<double> cd;
     Consts<float> cf;
     double shift[Q];
@@ -77,6 +83,7 @@ struct Tile {
 };
 
 struct StepLaunch {
+    const void *xi;     // correlated-noise planes (pairs of the storage type) or nullptr
     const void *fin;
     void *fout;
     const RepDesc *reps;
@@ -109,6 +116,11 @@ struct SkPlan {
     double *twx, *twy;      // twiddles exp(-2 pi i k / n), k < n/2, as (re, im) pairs
 };
 hipError_t launch_twiddles(double *tw, int n, hipStream_t s);
+// correlated noise of one replica for step time tdev[0] + toff: fills its xi plane
+hipError_t launch_correlated_noise(int precision, const RepDesc *d_reps, const RepDesc &h_rep, int rep_index,
+                                   double *work_a, double *work_b, const double *tw_base, void *xi_base,
+                                   const unsigned long long *tdev, int toff, hipStream_t s);
+hipError_t set_fft_lds_limit(int max_line);
 hipError_t launch_sk_sample(int precision, const void *f, const RepDesc *d_reps, const RepDesc &h_rep,
                             int rep_index, const SkPlan &plan, double *work_a, double *work_b,
                             double *acc, hipStream_t s);

@@ -14,85 +14,12 @@
 // flight stream whole rows (HBM page locality).  Stores bypass the caches (nontemporal).
 
 #include "lb_internal.h"
+#include "lb_rng.h"
 
 #include <math.h>
 
 namespace lbf {
 
-// ------------------------------------------------------------------ Philox4x32-10
-// Salmon, Moraes, Dror & Shaw, SC'11: 10 rounds of two 32x32->64 products with the
-// multipliers 0xD2511F53 / 0xCD9E8D57 and a Weyl key schedule 0x9E3779B9 / 0xBB67AE85.
-__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const unsigned long long p0 = (unsigned long long)0xD2511F53u * c.x;
-        const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c.z;
-        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
-    }
-    return c;
-}
-
-// the six 21-bit integers of one Philox block: the top 21 bits of each word, then the
-// low 11 bits of words (0,1) and (2,3) joined (dropping one bit of words 1 and 3)
-__device__ __forceinline__ void bits21(uint4 x, uint32_t b[6])
-{
-    b[0] = x.x >> 11;
-    b[1] = x.y >> 11;
-    b[2] = x.z >> 11;
-    b[3] = x.w >> 11;
-    b[4] = ((x.x & 0x7FFu) << 10) | ((x.y & 0x7FFu) >> 1);
-    b[5] = ((x.z & 0x7FFu) << 10) | ((x.w & 0x7FFu) >> 1);
-}
-
-// Box-Muller on u = (b + 1/2) 2^-21 (exact in float and double)
-template <typename R> struct Gauss;
-
-template <> struct Gauss<float> {
-    static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, float &a, float &b)
-    {
-        const float ue = ((float)be + 0.5f) * 0x1p-21f;
-        const float uo = ((float)bo + 0.5f) * 0x1p-21f;
-        // -2 ln u = -2 ln(2) log2(u); v_log_f32 is log2, v_sin/v_cos take revolutions
-        const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ue));
-        a = r * __builtin_amdgcn_cosf(uo);
-        b = r * __builtin_amdgcn_sinf(uo);
-    }
-};
-
-template <> struct Gauss<double> {
-    static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, double &a, double &b)
-    {
-        const double ue = ((double)be + 0.5) * 0x1p-21;
-        const double uo = ((double)bo + 0.5) * 0x1p-21;
-        const double r = sqrt(-2.0 * log(ue));
-        double s, c;
-        sincospi(2.0 * uo, &s, &c);
-        a = r * c;
-        b = r * s;
-    }
-};
-
-template <typename R>
-__device__ __forceinline__ void normals6(uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
-                                         uint32_t k1, R nu[6])
-{
-    const uint4 x = philox10(make_uint4(node, rep, (uint32_t)t, (uint32_t)(t >> 32)), k0, k1);
-    uint32_t b[6];
-    bits21(x, b);
-    Gauss<R>::pair(b[0], b[1], nu[0], nu[1]);
-    Gauss<R>::pair(b[2], b[3], nu[2], nu[3]);
-    Gauss<R>::pair(b[4], b[5], nu[4], nu[5]);
-}
-
-// element at a 32-bit byte offset from a uniform base (lets the compiler address with an
-// SGPR base and one 32-bit VGPR offset)
 template <typename S> __device__ __forceinline__ S ld_at(const S *base, unsigned byte_off)
 {
     return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + byte_off);
@@ -116,7 +43,7 @@ template <> __device__ __forceinline__ double fsqrt<double>(double v) { return s
 template <typename R>
 __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Consts<R> &c, uint32_t noise,
                                             uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
-                                            uint32_t k1)
+                                            uint32_t k1, R xi4, R xi9)
 {
     // m = T f (Table I rows, eq. Tmat), sharing the axis / diagonal partial sums
     const R sa = (f[1] + f[2]) + (f[3] + f[4]);
@@ -162,7 +89,17 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
     R s8 = m8 + lq * m8;
     R s9 = m9 + le * (m9 - e9);
 
-    if (noise) {
+    if (noise == 2) {
+        // correlated noise: modes 4 and 9 from the filtered fields, modes 5..8 white at rho0
+        R nu[6];
+        normals6<R>(node, rep, t, k0, k1, nu);
+        s4 += xi4;
+        s9 += xi9;
+        s5 += c.sq0 * c.l55 * nu[1];
+        s6 += c.sq0 * c.l66 * nu[2];
+        s7 += c.sq0 * c.l77 * nu[3];
+        s8 += c.sq0 * c.l88 * nu[4];
+    } else if (noise) {
         // xi = L nu, L L^T = Xi(0) at the local rho and c_s^2 (eq. noise-yeo at k = 0)
         R nu[6];
         normals6<R>(node, rep, t, k0, k1, nu);
@@ -225,7 +162,7 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
 // ------------------------------------------------------------------ fused step kernel
 
 template <typename S, typename R, bool PLAIN>
-__global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__restrict__ fout,
+__global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S *__restrict__ fin, S *__restrict__ fout,
                                               const RepDesc *__restrict__ reps, const Tile *__restrict__ tiles,
                                               const unsigned long long *__restrict__ tdev,
                                               unsigned *__restrict__ flags, int toff)
@@ -304,7 +241,14 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ fin, S *__re
 #pragma unroll
             for (int i = 0; i < Q; ++i) cur[i] -= c.sub[i];
         }
-        st |= collide<R>(cur, lap, gx, gy, c, d.noise, (unsigned)y * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi);
+        R xi4 = 0, xi9 = 0;
+        if (d.noise == 2) {
+            const S *__restrict__ xr = xi + 2 * (d.xi_off + (long long)y * nx + xw);
+            xi4 = (R)xr[0];
+            xi9 = (R)xr[1];
+        }
+        st |= collide<R>(cur, lap, gx, gy, c, d.noise, (unsigned)y * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi,
+                         xi4, xi9);
         if (store) {
             S *__restrict__ o = Qo + (unsigned long long)(unsigned)y * pitch;
 #pragma unroll
@@ -569,8 +513,8 @@ static void launch_step_t(const StepLaunch &a, hipStream_t s)
 {
     const dim3 grid(a.ntiles), block(a.bx);
     const size_t lds = 4 * (a.bx + 2) * sizeof(R);
-    hipLaunchKernelGGL((k_step<S, R, PLAIN>), grid, block, lds, s, (const S *)a.fin, (S *)a.fout, a.reps, a.tiles,
-                       a.tdev, a.flags, a.toff);
+    hipLaunchKernelGGL((k_step<S, R, PLAIN>), grid, block, lds, s, (const S *)a.xi, (const S *)a.fin, (S *)a.fout,
+                       a.reps, a.tiles, a.tdev, a.flags, a.toff);
 }
 
 hipError_t launch_step(int precision, const StepLaunch &a, hipStream_t s)

@@ -1,0 +1,84 @@
+// Device random numbers of the library (private): Philox4x32-10 and Box-Muller.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace lbf {
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror & Shaw, SC'11: 10 rounds of two 32x32->64 products with the
+// multipliers 0xD2511F53 / 0xCD9E8D57 and a Weyl key schedule 0x9E3779B9 / 0xBB67AE85.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const unsigned long long p0 = (unsigned long long)0xD2511F53u * c.x;
+        const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// the six 21-bit integers of one Philox block: the top 21 bits of each word, then the
+// low 11 bits of words (0,1) and (2,3) joined (dropping one bit of words 1 and 3)
+__device__ __forceinline__ void bits21(uint4 x, uint32_t b[6])
+{
+    b[0] = x.x >> 11;
+    b[1] = x.y >> 11;
+    b[2] = x.z >> 11;
+    b[3] = x.w >> 11;
+    b[4] = ((x.x & 0x7FFu) << 10) | ((x.y & 0x7FFu) >> 1);
+    b[5] = ((x.z & 0x7FFu) << 10) | ((x.w & 0x7FFu) >> 1);
+}
+
+// Box-Muller on u = (b + 1/2) 2^-21 (exact in float and double)
+template <typename R> struct Gauss;
+
+template <> struct Gauss<float> {
+    static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, float &a, float &b)
+    {
+        const float ue = ((float)be + 0.5f) * 0x1p-21f;
+        const float uo = ((float)bo + 0.5f) * 0x1p-21f;
+        // -2 ln u = -2 ln(2) log2(u); v_log_f32 is log2, v_sin/v_cos take revolutions
+        const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ue));
+        a = r * __builtin_amdgcn_cosf(uo);
+        b = r * __builtin_amdgcn_sinf(uo);
+    }
+};
+
+template <> struct Gauss<double> {
+    static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, double &a, double &b)
+    {
+        const double ue = ((double)be + 0.5) * 0x1p-21;
+        const double uo = ((double)bo + 0.5) * 0x1p-21;
+        const double r = sqrt(-2.0 * log(ue));
+        double s, c;
+        sincospi(2.0 * uo, &s, &c);
+        a = r * c;
+        b = r * s;
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ void normals6(uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
+                                         uint32_t k1, R nu[6])
+{
+    const uint4 x = philox10(make_uint4(node, rep, (uint32_t)t, (uint32_t)(t >> 32)), k0, k1);
+    uint32_t b[6];
+    bits21(x, b);
+    Gauss<R>::pair(b[0], b[1], nu[0], nu[1]);
+    Gauss<R>::pair(b[2], b[3], nu[2], nu[3]);
+    Gauss<R>::pair(b[4], b[5], nu[4], nu[5]);
+}
+
+// element at a 32-bit byte offset from a uniform base (lets the compiler address with an
+// SGPR base and one 32-bit VGPR offset)
+}  // namespace lbf

@@ -20,6 +20,7 @@ LB_OK, LB_EINVAL, LB_ENOTPSD, LB_EUNSTABLE, LB_ENOMEM, LB_EDEVICE, LB_ESTATE = 0
 LB_FP64, LB_FP32, LB_FP32_SHIFTED = 0, 1, 2
 PRECISIONS = {"fp64": LB_FP64, "fp32": LB_FP32, "fp32s": LB_FP32_SHIFTED}
 INIT_KINDS = {"uniform": 0, "slab": 1, "random": 2, "wave": 3}
+NOISE_KINDS = {"k0": 0, "correlated": 1}
 LB_FEATURE_STRUCTURE_FACTOR = 1
 LB_SK_RESET, LB_SK_SAMPLE, LB_SK_READ = 0, 1, 2
 LB_FLAG_CLAMPED_PIVOT, LB_FLAG_NONPOSITIVE_RHO, LB_FLAG_NAN = 1, 2, 4
@@ -37,6 +38,8 @@ class LbParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("replica", ctypes.c_uint32),
         ("init_kind", ctypes.c_int32),
+        ("noise_kind", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("init_arg", ctypes.c_double * 6),
     ]
 
@@ -103,6 +106,7 @@ def make_params(cfg: dict) -> LbParams:
     p.seed = int(cfg.get("seed", 1))
     p.replica = int(cfg.get("replica", 0))
     p.init_kind = INIT_KINDS[cfg.get("init", "uniform")]
+    p.noise_kind = NOISE_KINDS[cfg.get("noise", "k0")]
     args = list(cfg.get("init_arg", [])) + [0.0] * 6
     for k in range(6):
         p.init_arg[k] = float(args[k])

@@ -86,6 +86,10 @@ def test_workspace_size_counts_both_population_buffers():
     (dict(kT=-1e-6), L.LB_EINVAL),
     (dict(A=0.5), L.LB_ENOTPSD),          # c_s^2 = 0.83 > 2/3 makes Xi_44 negative
     (dict(c0sq=1.0), L.LB_ENOTPSD),
+    (dict(noise="correlated", nx=48), L.LB_EINVAL),        # correlated noise needs powers of two
+    (dict(replica=0x80000000), L.LB_EINVAL),              # top bit names the correlated stream
+    # Xi(k) not PSD at large k: kappa large enough that c_s^2(k) > 2/3 near the zone corner
+    (dict(noise="correlated", kappa=0.1), L.LB_ENOTPSD),
 ])
 def test_validation_rejects(over, code):
     c = W.single_phase(16, 16)
@@ -109,7 +113,7 @@ def test_validation_rejects_bad_precision_and_count():
 
 
 def test_all_workloads_validate():
-    for cfg in (W.cfg1(), W.cfg2(), W.cfg3(), W.cfg5(), W.e4()):
+    for cfg in (W.cfg1(), W.cfg2(), W.cfg3(), W.cfg5(), W.e4(), W.e3()):
         assert L.lb_workspace_size([cfg], L.LB_FP32_SHIFTED) > 0
     reps = W.cfg4()
     assert len(reps) == 336
