@@ -82,21 +82,25 @@ enum {
 
 /* optional features (bit mask for lb_workspace_size / lb_init) */
 enum {
-    LB_FEATURE_STRUCTURE_FACTOR = 1   /* reserve FFT buffers and S(k) accumulators */
+    LB_FEATURE_STRUCTURE_FACTOR = 1   /* reserve FFT buffers and S(k) accumulators; every
+                                         replica's nx and ny must be powers of two in [4, 16384] */
 };
 
 /* lb_structure_factor operations */
 enum {
     LB_SK_RESET = 0,      /* zero the accumulators of replica rep (or all, rep = -1) */
     LB_SK_SAMPLE = 1,     /* add |m_a(k)|^2 of the current state of rep (or all, rep = -1) */
-    LB_SK_READ = 2        /* copy <|m_a(k)|^2> (accumulated sum / nsamples) of rep to out */
+    LB_SK_READ = 2,       /* copy <|m_a(k)|^2> (accumulated sum / nsamples) of rep to out */
+    LB_SK_SNAPSHOT = 3    /* radially binned |rho(k)|^2 of the current state of rep (no averaging) */
 };
 
 /* device-side status flags (lb_status_flags) */
 enum {
     LB_FLAG_CLAMPED_PIVOT = 1u,  /* a local Cholesky pivot of Xi(0) was negative and clamped to 0 */
     LB_FLAG_NONPOSITIVE_RHO = 2u,/* a node had rho <= 0 (its noise was set to zero) */
-    LB_FLAG_NAN = 4u             /* a node had a non-finite density */
+    LB_FLAG_NAN = 4u,            /* a node had a non-finite density */
+    LB_FLAG_LOW_MACH = 8u        /* set by lb_init: some replica has kT >= 0.01 rho0 / 3, outside the
+                                    small-fluctuation bound kT << sigma_s^2 rho0 of eq. (low-mach) */
 };
 
 /* One replica: a periodic nx*ny lattice with its own parameters.  The free energy
@@ -155,9 +159,25 @@ lb_status lb_moments(lb_handle *h, int32_t rep, double *d_m9, double *h_totals);
  * notation), for k on the half plane kx = 0..nx/2, ky = 0..ny-1, to FP64 accumulators;
  * LB_SK_READ copies the mean, [9][ny][nx/2+1] FP64, to the device pointer out and the
  * sample count to *nsamples (synchronous); LB_SK_RESET zeroes.  rep = -1 addresses every
- * replica for RESET and SAMPLE.  Needs LB_FEATURE_STRUCTURE_FACTOR at lb_init and nx, ny
- * powers of two <= 8192 (LB_ESTATE / LB_EINVAL otherwise). */
+ * replica for RESET and SAMPLE (one batched pass over all of them).
+ * LB_SK_SNAPSHOT (rep >= 0; synchronous) bins |rho(k)|^2 of the current state radially (an
+ * isotropic average of S_rho(k), e.g. to follow density modes growing after a quench to
+ * c_s^2 < 0, where M(k) of eq. lb-lang-ft has eigenvalues above 1): with L = min(nx, ny) and the shell
+ * spacing 2 pi / L, k = (2 pi kx / nx, 2 pi ky / ny) falls in shell b = floor(|k| L / 2 pi + 1/2)
+ * (decided in exact integer arithmetic).  *nsamples receives the number of shells nb (the
+ * corner (pi, pi) lies in the last); if out != NULL (device pointer, 2 nb doubles) it
+ * receives the mean of |rho(k)|^2 over each shell of the full k plane without k = 0, then
+ * the number of k points in each shell.  It uses the sampler's scratch only; accumulators
+ * and sample counts are untouched.
+ * Needs LB_FEATURE_STRUCTURE_FACTOR at lb_init (LB_ESTATE otherwise). */
 lb_status lb_structure_factor(lb_handle *h, int32_t op, int32_t rep, double *out, int64_t *nsamples);
+
+/* S(k) sampling inside lb_step: from now on, each time lb_step brings the state to a time
+ * t >= first_step with (t - first_step) divisible by every, it adds a sample of every
+ * replica (as LB_SK_SAMPLE with rep = -1).  Intervals up to 256 steps are replayed as one
+ * captured graph of the steps and the sample.  every = 0 switches sampling off.  Needs
+ * LB_FEATURE_STRUCTURE_FACTOR for every > 0 (LB_ESTATE); every, first_step >= 0. */
+lb_status lb_set_sampling(lb_handle *h, int64_t every, int64_t first_step);
 
 /* Accumulated LB_FLAG_* bits since lb_init and the current time step t.  Synchronous. */
 lb_status lb_status_flags(lb_handle *h, uint32_t *flags, int64_t *step);

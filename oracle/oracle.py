@@ -239,3 +239,41 @@ def power_spectrum(m: np.ndarray) -> np.ndarray:
     n = m.shape[-1] * m.shape[-2]
     F = np.fft.rfft2(m, axes=(-2, -1))
     return (F.real ** 2 + F.imag ** 2) / n
+
+
+def radial_shell(kx, ky, nx: int, ny: int):
+    """Shell index of the lattice wave vector k = (2 pi kx / nx, 2 pi ky / ny) (integer kx, ky,
+    any sign): b = floor(|k| L / 2 pi + 1/2) with L = min(nx, ny), i.e. shells of width
+    2 pi / L centred on multiples of it.
+
+    Exact: with q = (|k| L / 2 pi)^2 = (kx L / nx)^2 + (ky L / ny)^2 (a rational number),
+    b - 1/2 <= sqrt(q) is (2b - 1)^2 <= 4 q, so b = (isqrt(floor(4 q)) + 1) // 2."""
+    L = min(nx, ny)
+    px, py = nx // L, ny // L
+    kx = np.asarray(kx, dtype=np.int64)
+    ky = np.asarray(ky, dtype=np.int64)
+    den = (px * py) ** 2
+    f4q = (4 * (kx * kx * py * py + ky * ky * px * px)) // den
+    s = np.floor(np.sqrt(f4q.astype(np.float64))).astype(np.int64)
+    s = np.where(s * s > f4q, s - 1, s)
+    s = np.where((s + 1) * (s + 1) <= f4q, s + 1, s)
+    return (s + 1) // 2
+
+
+def radial_spectrum(rho: np.ndarray):
+    """Isotropic average of S_rho(k) = |rho(k)|^2 (rho(k) = n^-1/2 sum_r e^{ik.r} rho(r),
+    Sec. III notation) over the shells of radial_shell, on the full k plane without k = 0.
+    Returns (mean per shell, number of k points per shell); the corner (pi, pi) lies in the
+    last shell."""
+    ny, nx = rho.shape
+    F = np.fft.fft2(rho)
+    S = (F.real ** 2 + F.imag ** 2) / (nx * ny)
+    kx = np.rint(np.fft.fftfreq(nx, 1.0 / nx)).astype(np.int64)
+    ky = np.rint(np.fft.fftfreq(ny, 1.0 / ny)).astype(np.int64)
+    KX, KY = np.meshgrid(kx, ky)
+    b = radial_shell(KX, KY, nx, ny)
+    keep = ~((KX == 0) & (KY == 0))
+    nb = int(radial_shell(nx // 2, ny // 2, nx, ny)) + 1
+    sums = np.bincount(b[keep], weights=S[keep], minlength=nb)
+    counts = np.bincount(b[keep], minlength=nb)
+    return np.where(counts > 0, sums / np.maximum(counts, 1), 0.0), counts

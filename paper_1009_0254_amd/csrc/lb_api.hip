@@ -26,7 +26,8 @@ constexpr size_t ALIGN = 256;
 constexpr int MAX_RED_BLOCKS = 1024;
 constexpr int GRAPH_STEPS = 32;   // steps per captured graph (even: buffers return to place)
 constexpr int MIN_BX = 64, MIN_H = 8;
-constexpr int SK_MAX = 8192;
+constexpr int CN_MAX = 8192;        // longest side with correlated noise
+constexpr int SAMPLE_GRAPH_MAX = 256;   // longest sampling interval captured as one graph
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -43,7 +44,9 @@ size_t elem_size(int precision) { return precision == LB_FP64 ? sizeof(double) :
 
 struct Layout {
     size_t fbuf[2], reps, tiles, tdev, flags, partials, tot, rho_tmp;
-    size_t twx, twy, work_a, work_b, acc;
+    size_t sk_tw, sk_reps, spec, acc;   // structure factor
+    int sk_G, sk_nmax;
+    long long sk_ptot;
     size_t xi, cn_a, cn_b, cn_tw;     // correlated noise
     long long cn_nodes, cn_max_n, cn_tw_elems;
     size_t total;
@@ -118,11 +121,33 @@ lb_status validate(const lb_params *p, int32_t n_rep, int32_t precision)
         if (q.noise_kind != LB_NOISE_K0 && q.noise_kind != LB_NOISE_CORRELATED) return LB_EINVAL;
         if (q.reserved != 0 || q.replica >= 0x80000000u) return LB_EINVAL;
         if (q.noise_kind == LB_NOISE_CORRELATED &&
-            (!is_pow2(q.nx) || !is_pow2(q.ny) || q.nx < 4 || q.ny < 4 || q.nx > SK_MAX || q.ny > SK_MAX))
+            (!is_pow2(q.nx) || !is_pow2(q.ny) || q.nx < 4 || q.ny < 4 || q.nx > CN_MAX || q.ny > CN_MAX))
             return LB_EINVAL;
         if (!xi0_psd(q)) return LB_ENOTPSD;
         if (q.noise_kind == LB_NOISE_CORRELATED && !xik_psd(q)) return LB_ENOTPSD;
     }
+    return LB_OK;
+}
+
+// modes per sampling pass: the row kernel holds G half-length transforms of the widest
+// row in LDS, at most 128 KiB
+int sk_modes_per_pass(int max_nx) { return std::max(1, std::min(9, SK_LINE_MAX * 2 / std::max(max_nx, 4))); }
+
+// rows per row workgroup: narrow rows are grouped to 512 complex points
+int sk_rows_per_block(int nx, int ny) { return std::max(1, std::min(ny, 1024 / nx)); }
+
+// adjacent kx columns per column workgroup: up to 4096 points (64 KiB) of short columns
+int sk_cols_per_block(int nx, int ny) { return ny >= 4096 ? 1 : std::min(4096 / ny, nx / 2 + 1); }
+
+// the S(k) feature needs power-of-two sides in [4, SK_MAX] on every replica
+lb_status validate_features(const lb_params *p, int32_t n_rep, uint32_t features)
+{
+    if (features & ~(uint32_t)LB_FEATURE_STRUCTURE_FACTOR) return LB_EINVAL;
+    if (features & LB_FEATURE_STRUCTURE_FACTOR)
+        for (int r = 0; r < n_rep; ++r)
+            if (!is_pow2(p[r].nx) || !is_pow2(p[r].ny) || p[r].nx < 4 || p[r].ny < 4 || p[r].nx > SK_MAX ||
+                p[r].ny > SK_MAX)
+                return LB_EINVAL;
     return LB_OK;
 }
 
@@ -162,11 +187,13 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
     L.tot = o; o += ALIGN;
     L.rho_tmp = o; o += align_up(sizeof(double) * L.max_n);
     if (features & LB_FEATURE_STRUCTURE_FACTOR) {
-        L.twx = o; o += align_up(sizeof(double) * 2 * (L.max_nx / 2 + 1));
-        L.twy = o; o += align_up(sizeof(double) * 2 * (L.max_ny / 2 + 1));
-        const size_t cplx = align_up(sizeof(double) * 2 * (size_t)L.max_ny * (L.max_nx / 2 + 1));
-        L.work_a = o; o += cplx;
-        L.work_b = o; o += cplx;
+        L.sk_nmax = std::max(L.max_nx, L.max_ny);
+        L.sk_G = sk_modes_per_pass(L.max_nx);
+        L.sk_ptot = 0;
+        for (int r = 0; r < n_rep; ++r) L.sk_ptot += (long long)p[r].ny * (p[r].nx / 2 + 1);
+        L.sk_tw = o; o += align_up(sizeof(double) * 2 * (size_t)(L.sk_nmax / 2));
+        L.sk_reps = o; o += align_up(sizeof(SkRep) * n_rep);
+        L.spec = o; o += align_up(sizeof(double) * 2 * 9 * (size_t)L.sk_ptot);
         L.acc = o; o += align_up(sizeof(double) * L.acc_elems);
     }
     if (L.cn_nodes > 0) {
@@ -201,10 +228,14 @@ struct lb_handle {
     unsigned *flags = nullptr;
     double *partials = nullptr, *tot = nullptr, *rho_tmp = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    unsigned init_flags = 0;
     // structure factor
-    bool sk_ready = false;
-    int sk_nx = 0, sk_ny = 0;
-    double *twx = nullptr, *twy = nullptr, *work_a = nullptr, *work_b = nullptr, *acc = nullptr;
+    std::vector<SkRep> sk;
+    SkRep *sk_d = nullptr;
+    long long sk_rows = 0, sk_cols = 0;   // totals over all replicas
+    double *sk_tw = nullptr, *spec = nullptr, *acc = nullptr;
+    long long sample_every = 0, sample_first = 0;
+    hipGraphExec_t sgraph[2] = {nullptr, nullptr};      // sample_every steps + one sample
     // correlated noise
     std::vector<int> cn_reps;
     void *xi = nullptr;
@@ -393,6 +424,15 @@ hipError_t step_once(lb_handle *h, int par, int toff, hipStream_t s)
     return launch_step(h->precision, a, s);
 }
 
+void drop_sample_graphs(lb_handle *h)
+{
+    for (int k = 0; k < 2; ++k)
+        if (h->sgraph[k]) {
+            (void)hipGraphExecDestroy(h->sgraph[k]);
+            h->sgraph[k] = nullptr;
+        }
+}
+
 void drop_graphs(lb_handle *h)
 {
     for (int k = 0; k < 2; ++k)
@@ -400,6 +440,49 @@ void drop_graphs(lb_handle *h)
             (void)hipGraphExecDestroy(h->graph[k]);
             h->graph[k] = nullptr;
         }
+    drop_sample_graphs(h);
+}
+
+// one sampling pass over replicas [r0, r1) reading population buffer `par`
+SkLaunch sk_launch(const lb_handle *h, int r0, int r1, int par)
+{
+    SkLaunch a{};
+    a.f = h->fbuf[par];
+    a.reps = h->reps_d;
+    a.sk = h->sk_d;
+    a.r0 = r0;
+    a.r1 = r1;
+    const SkRep &q0 = h->sk[r0];
+    a.row_base = q0.row0;
+    a.col_base = q0.col0;
+    a.rows = (r1 < h->n_rep ? h->sk[r1].row0 : h->sk_rows) - q0.row0;
+    a.cols = (r1 < h->n_rep ? h->sk[r1].col0 : h->sk_cols) - q0.col0;
+    a.lds_rows = a.lds_cols = 0;
+    for (int r = r0; r < r1; ++r) {
+        a.lds_rows = std::max(a.lds_rows, h->sk[r].rpb * h->sk[r].nx);
+        a.lds_cols = std::max(a.lds_cols, h->sk[r].cpb * (h->sk[r].ny / h->sk[r].split));
+    }
+    a.G = h->L.sk_G;
+    a.Ptot = h->L.sk_ptot;
+    a.spec = h->spec;
+    a.acc = h->acc;
+    a.tw = h->sk_tw;
+    a.nmax = h->L.sk_nmax;
+    return a;
+}
+
+// shells of the radial spectrum (k_sk_bins): P = max(nx, ny) / min(nx, ny); the corner
+// (nx/2, ny/2) lies in the last one
+void radial_metric(int nx, int ny, int *P, int *xwide, int *nbins)
+{
+    *xwide = nx >= ny;
+    *P = nx >= ny ? nx / ny : ny / nx;
+    const long long wx = *xwide ? 1 : (long long)*P * *P, wy = *xwide ? (long long)*P * *P : 1;
+    const long long r2 = wx * (nx / 2) * (long long)(nx / 2) + wy * (ny / 2) * (long long)(ny / 2);
+    long long s = (long long)sqrt((double)(4 * r2));
+    while (s * s > 4 * r2) --s;
+    while ((s + 1) * (s + 1) <= 4 * r2) ++s;
+    *nbins = (int)((s + *P) / (2 * *P)) + 1;
 }
 
 // time a few steps of each candidate (strip width, rows per tile) and keep the fastest;
@@ -447,7 +530,8 @@ lb_status autotune(lb_handle *h)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (hipMemsetAsync(h->flags, 0, sizeof(unsigned), h->stream) != hipSuccess) return LB_EDEVICE;
+    if (hipMemcpyAsync(h->flags, &h->init_flags, sizeof(unsigned), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return LB_EDEVICE;
     return set_tiles(h, bbx, brows);
 }
 
@@ -474,6 +558,54 @@ lb_status capture_graph(lb_handle *h, int par)
     return st;
 }
 
+// sample_every steps followed by one S(k) sample of every replica
+lb_status capture_sample_graph(lb_handle *h, int par)
+{
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LB_EDEVICE;
+    hipGraph_t g = nullptr;
+    lb_status st = LB_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return LB_EDEVICE;
+    }
+    int p = par;
+    for (long long k = 0; k < h->sample_every; ++k) {
+        if (step_once(h, p, (int)k, cs) != hipSuccess) st = LB_EDEVICE;
+        p ^= 1;
+    }
+    if (launch_advance_time(h->tdev, h->sample_every, cs) != hipSuccess) st = LB_EDEVICE;
+    if (launch_sk_sample(h->precision, sk_launch(h, 0, h->n_rep, p), cs) != hipSuccess) st = LB_EDEVICE;
+    if (hipStreamEndCapture(cs, &g) != hipSuccess) st = LB_EDEVICE;
+    if (st == LB_OK && hipGraphInstantiate(&h->sgraph[par], g, nullptr, nullptr, 0) != hipSuccess) st = LB_EDEVICE;
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    return st;
+}
+
+lb_status run_steps(lb_handle *h, long long nsteps)
+{
+    long long left = nsteps;
+    while (left >= GRAPH_STEPS) {
+        if (!h->graph[h->par]) {
+            lb_status st = capture_graph(h, h->par);
+            if (st != LB_OK) return st;
+        }
+        if (hipGraphLaunch(h->graph[h->par], h->stream) != hipSuccess) return LB_EDEVICE;
+        left -= GRAPH_STEPS;
+        h->t += GRAPH_STEPS;
+    }
+    if (left > 0) {
+        for (int k = 0; k < left; ++k) {
+            if (step_once(h, h->par, k, h->stream) != hipSuccess) return LB_EDEVICE;
+            h->par ^= 1;
+        }
+        if (launch_advance_time(h->tdev, left, h->stream) != hipSuccess) return LB_EDEVICE;
+        h->t += left;
+    }
+    return LB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -496,6 +628,7 @@ lb_status lb_workspace_size(const lb_params *p, int32_t n_rep, int32_t precision
 {
     if (!bytes) return LB_EINVAL;
     lb_status st = validate(p, n_rep, precision);
+    if (st == LB_OK) st = validate_features(p, n_rep, features);
     if (st != LB_OK) return st;
     *bytes = make_layout(p, n_rep, precision, features).total;
     return LB_OK;
@@ -507,6 +640,7 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
     if (!out) return LB_EINVAL;
     *out = nullptr;
     lb_status st = validate(p, n_rep, precision);
+    if (st == LB_OK) st = validate_features(p, n_rep, features);
     if (st != LB_OK) return st;
     if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0) return LB_EINVAL;
     const Layout L = make_layout(p, n_rep, precision, features);
@@ -557,7 +691,10 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
 
     hipError_t e = hipMemcpyAsync(h->reps_d, h->reps.data(), sizeof(RepDesc) * n_rep, hipMemcpyHostToDevice, h->stream);
     const unsigned long long zero64 = 0;
-    const unsigned zero32[4] = {0, 0, 0, 0};
+    // eq. (low-mach): the fluctuations stay small only for kT << sigma_s^2 rho0; flag kT >= 1% of it
+    for (int r = 0; r < n_rep; ++r)
+        if (p[r].kT >= 0.01 * p[r].rho0 / 3.0) h->init_flags |= LB_FLAG_LOW_MACH;
+    const unsigned zero32[4] = {h->init_flags, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(h->tdev, &zero64, sizeof(zero64), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h->flags, zero32, sizeof(zero32), hipMemcpyHostToDevice, h->stream);
     for (int r = 0; r < n_rep && e == hipSuccess; ++r) {
@@ -589,12 +726,39 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
         return st != LB_OK ? st : LB_EDEVICE;
     }
     if (features & LB_FEATURE_STRUCTURE_FACTOR) {
-        h->twx = (double *)(h->ws + L.twx);
-        h->twy = (double *)(h->ws + L.twy);
-        h->work_a = (double *)(h->ws + L.work_a);
-        h->work_b = (double *)(h->ws + L.work_b);
+        h->sk_tw = (double *)(h->ws + L.sk_tw);
+        h->sk_d = (SkRep *)(h->ws + L.sk_reps);
+        h->spec = (double *)(h->ws + L.spec);
         h->acc = (double *)(h->ws + L.acc);
-        e = launch_fill(h->acc, (int64_t)L.acc_elems, 0.0, h->stream);
+        long long rows = 0, cols = 0, soff = 0;
+        int max_col = 0, max_row = 0;
+        for (int r = 0; r < n_rep; ++r) {
+            SkRep q{};
+            q.nx = p[r].nx;
+            q.ny = p[r].ny;
+            q.lognx = ilog2(q.nx);
+            q.logny = ilog2(q.ny);
+            q.split = q.ny > SK_LINE_MAX ? 2 : 1;
+            q.cpb = sk_cols_per_block(q.nx, q.ny);
+            q.rpb = sk_rows_per_block(q.nx, q.ny);
+            const int nh = q.nx / 2 + 1;
+            q.row0 = rows;
+            q.col0 = cols;
+            q.soff = soff;
+            q.acc_off = (int64_t)h->acc_off[r];
+            rows += (q.ny + q.rpb - 1) / q.rpb;
+            max_row = std::max(max_row, q.rpb * q.nx);
+            cols += (long long)q.split * ((nh + q.cpb - 1) / q.cpb);
+            soff += (long long)q.ny * nh;
+            max_col = std::max(max_col, q.cpb * (q.ny / q.split));
+            h->sk.push_back(q);
+        }
+        h->sk_rows = rows;
+        h->sk_cols = cols;
+        e = hipMemcpyAsync(h->sk_d, h->sk.data(), sizeof(SkRep) * n_rep, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = launch_twiddles(h->sk_tw, L.sk_nmax, h->stream);
+        if (e == hipSuccess) e = set_sk_lds_limits(L.sk_G, max_row, max_col);
+        if (e == hipSuccess) e = launch_fill(h->acc, (int64_t)L.acc_elems, 0.0, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) {
             delete h;
@@ -608,24 +772,42 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
 lb_status lb_step(lb_handle *h, int64_t nsteps)
 {
     if (!h || nsteps < 0) return LB_EINVAL;
+    if (h->sample_every <= 0) return run_steps(h, nsteps);
     long long left = nsteps;
-    while (left >= GRAPH_STEPS) {
-        if (!h->graph[h->par]) {
-            lb_status st = capture_graph(h, h->par);
+    while (left > 0) {
+        // next sampling time after the current one
+        const long long ts = h->t < h->sample_first
+                                 ? h->sample_first
+                                 : h->sample_first + ((h->t - h->sample_first) / h->sample_every + 1) * h->sample_every;
+        const long long d = ts - h->t;
+        if (d > left) return run_steps(h, left);
+        if (d == h->sample_every && d <= SAMPLE_GRAPH_MAX) {
+            if (!h->sgraph[h->par]) {
+                lb_status st = capture_sample_graph(h, h->par);
+                if (st != LB_OK) return st;
+            }
+            if (hipGraphLaunch(h->sgraph[h->par], h->stream) != hipSuccess) return LB_EDEVICE;
+            h->t += d;
+            h->par ^= (int)(d & 1);
+        } else {
+            lb_status st = run_steps(h, d);
             if (st != LB_OK) return st;
+            if (launch_sk_sample(h->precision, sk_launch(h, 0, h->n_rep, h->par), h->stream) != hipSuccess)
+                return LB_EDEVICE;
         }
-        if (hipGraphLaunch(h->graph[h->par], h->stream) != hipSuccess) return LB_EDEVICE;
-        left -= GRAPH_STEPS;
-        h->t += GRAPH_STEPS;
+        for (auto &n : h->nsamples) ++n;
+        left -= d;
     }
-    if (left > 0) {
-        for (int k = 0; k < left; ++k) {
-            if (step_once(h, h->par, k, h->stream) != hipSuccess) return LB_EDEVICE;
-            h->par ^= 1;
-        }
-        if (launch_advance_time(h->tdev, left, h->stream) != hipSuccess) return LB_EDEVICE;
-        h->t += left;
-    }
+    return LB_OK;
+}
+
+lb_status lb_set_sampling(lb_handle *h, int64_t every, int64_t first_step)
+{
+    if (!h || every < 0 || first_step < 0) return LB_EINVAL;
+    if (every > 0 && !(h->features & LB_FEATURE_STRUCTURE_FACTOR)) return LB_ESTATE;
+    drop_sample_graphs(h);
+    h->sample_every = every;
+    h->sample_first = first_step;
     return LB_OK;
 }
 
@@ -650,37 +832,16 @@ lb_status lb_structure_factor(lb_handle *h, int32_t op, int32_t rep, double *out
     if (!(h->features & LB_FEATURE_STRUCTURE_FACTOR)) return LB_ESTATE;
     if (rep < -1 || rep >= h->n_rep) return LB_EINVAL;
     const int r0 = rep < 0 ? 0 : rep, r1 = rep < 0 ? h->n_rep : rep + 1;
-    for (int r = r0; r < r1; ++r) {
-        const RepDesc &d = h->reps[r];
-        if (!is_pow2(d.nx) || !is_pow2(d.ny) || d.nx > SK_MAX || d.ny > SK_MAX || d.nx < 4 || d.ny < 4)
-            return LB_EINVAL;
-    }
     switch (op) {
-    case LB_SK_RESET:
-        for (int r = r0; r < r1; ++r) {
-            const RepDesc &d = h->reps[r];
-            if (launch_fill(h->acc + h->acc_off[r], (int64_t)9 * d.ny * (d.nx / 2 + 1), 0.0, h->stream) != hipSuccess)
-                return LB_EDEVICE;
-            h->nsamples[r] = 0;
-        }
+    case LB_SK_RESET: {
+        const size_t a = h->acc_off[r0], b = r1 < h->n_rep ? h->acc_off[r1] : h->L.acc_elems;
+        if (launch_fill(h->acc + a, (int64_t)(b - a), 0.0, h->stream) != hipSuccess) return LB_EDEVICE;
+        for (int r = r0; r < r1; ++r) h->nsamples[r] = 0;
         return LB_OK;
+    }
     case LB_SK_SAMPLE:
-        for (int r = r0; r < r1; ++r) {
-            const RepDesc &d = h->reps[r];
-            if (d.nx != h->sk_nx) {
-                if (launch_twiddles(h->twx, d.nx, h->stream) != hipSuccess) return LB_EDEVICE;
-                h->sk_nx = d.nx;
-            }
-            if (d.ny != h->sk_ny) {
-                if (launch_twiddles(h->twy, d.ny, h->stream) != hipSuccess) return LB_EDEVICE;
-                h->sk_ny = d.ny;
-            }
-            SkPlan plan{d.nx, d.ny, ilog2(d.nx), ilog2(d.ny), h->twx, h->twy};
-            if (launch_sk_sample(h->precision, h->fbuf[h->par], h->reps_d, d, r, plan, h->work_a, h->work_b,
-                                 h->acc + h->acc_off[r], h->stream) != hipSuccess)
-                return LB_EDEVICE;
-            h->nsamples[r] += 1;
-        }
+        if (launch_sk_sample(h->precision, sk_launch(h, r0, r1, h->par), h->stream) != hipSuccess) return LB_EDEVICE;
+        for (int r = r0; r < r1; ++r) h->nsamples[r] += 1;
         return LB_OK;
     case LB_SK_READ: {
         if (rep < 0 || !out) return LB_EINVAL;
@@ -688,6 +849,18 @@ lb_status lb_structure_factor(lb_handle *h, int32_t op, int32_t rep, double *out
         const double inv = h->nsamples[rep] > 0 ? 1.0 / (double)h->nsamples[rep] : 0.0;
         if (launch_sk_read(h->acc + h->acc_off[rep], out, d.nx, d.ny, inv, h->stream) != hipSuccess) return LB_EDEVICE;
         if (nsamples) *nsamples = h->nsamples[rep];
+        return hip_ok(hipStreamSynchronize(h->stream));
+    }
+    case LB_SK_SNAPSHOT: {
+        if (rep < 0) return LB_EINVAL;
+        const RepDesc &d = h->reps[rep];
+        int P = 1, xwide = 1, nbins = 0;
+        radial_metric(d.nx, d.ny, &P, &xwide, &nbins);
+        if (nsamples) *nsamples = nbins;
+        if (!out) return LB_OK;
+        if (launch_sk_snapshot(h->precision, sk_launch(h, rep, rep + 1, h->par), d.nx, d.ny, nbins, P, xwide, out,
+                               h->stream) != hipSuccess)
+            return LB_EDEVICE;
         return hip_ok(hipStreamSynchronize(h->stream));
     }
     default:

@@ -1,15 +1,8 @@
-// Static structure factor of the nine LB modes, the equilibration measurement of
-// arXiv:1009.0254, Sec. V.A: <|m_a(k)|^2> with a(k) = n^-1/2 sum_r exp(i k.r) a(r)
-// (Sec. III notation).  For a real field |a(k)|^2 = |a(-k)|^2, so the transform below
-// uses exp(-2 pi i k x / n) and keeps the half plane kx = 0..nx/2.
-//
-// Per sample and mode a:
-//   1. row pass: one workgroup per row y pulls the pre-collision populations, forms
-//      m_a in FP64 and transforms the row in LDS (radix-2, bit-reversed input);
-//   2. LDS-tiled transpose of the [ny][nx/2+1] half spectrum;
-//   3. column pass: one workgroup per kx transforms along y and adds |X|^2 / n to the
-//      FP64 accumulator, stored transposed as [9][nx/2+1][ny] (read back transposed).
+// Fourier-space helpers: twiddle tables, a fill kernel, and the spatially correlated
+// noise of arXiv:1009.0254, Sec. IV (last paragraph), built each step by filtering white
+// fields with the Cholesky factor of Xi(k).
 
+#include "lb_fftcore.h"
 #include "lb_internal.h"
 #include "lb_rng.h"
 
@@ -35,70 +28,6 @@ __global__ void k_fill(double *p, long long n, double v)
         p[k] = v;
 }
 
-__device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return __brev(v) >> (32 - bits); }
-
-// in-place radix-2 decimation-in-time transform of X (already in bit-reversed order);
-// INV uses the conjugate twiddles exp(+2 pi i k / n) (no 1/n)
-template <bool INV = false>
-__device__ void fft_lds(double2 *X, int n, int logn, const double2 *__restrict__ tw)
-{
-    const int nb = n >> 1;
-    for (int s = 1; s <= logn; ++s) {
-        const int half = 1 << (s - 1);
-        const int stride = n >> s;   // twiddle index step: exp(-2 pi i pos / (2 half)) = tw[pos * n / (2 half)]
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const int grp = b >> (s - 1), pos = b & (half - 1);
-            const int i0 = (grp << s) + pos, i1 = i0 + half;
-            double2 w = tw[pos * stride];
-            if (INV) w.y = -w.y;
-            const double2 u = X[i0], v = X[i1];
-            const double2 t = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
-            X[i0] = make_double2(u.x + t.x, u.y + t.y);
-            X[i1] = make_double2(u.x - t.x, u.y - t.y);
-        }
-        __syncthreads();
-    }
-}
-
-__device__ __forceinline__ double moment_row(int a, const double g[9])
-{
-    const double sa = (g[1] + g[2]) + (g[3] + g[4]);
-    const double sd = (g[5] + g[6]) + (g[7] + g[8]);
-    const double ax = g[1] - g[3], ay = g[2] - g[4], d68 = g[5] - g[7], d97 = g[8] - g[6];
-    switch (a) {
-    case 0: return g[0] + sa + sd;
-    case 1: return ax + d68 + d97;
-    case 2: return ay + d68 - d97;
-    case 3: return -2 * g[0] + sa + 4 * sd;
-    case 4: return (g[1] + g[3]) - (g[2] + g[4]);
-    case 5: return (g[5] + g[7]) - (g[6] + g[8]);
-    case 6: return -ax + 2 * (d68 + d97);
-    case 7: return -ay + 2 * (d68 - d97);
-    default: return 2 * g[0] - 4 * sa + 8 * sd;
-    }
-}
-
-template <typename S>
-__global__ void __launch_bounds__(FFT_THREADS) k_sk_rows(const S *__restrict__ f, const RepDesc *__restrict__ reps,
-                                                         int rep_index, int a, int lognx,
-                                                         const double2 *__restrict__ twx, double2 *__restrict__ out)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double2 *X = reinterpret_cast<double2 *>(smem_raw);
-    const RepDesc &d = reps[rep_index];
-    const int nx = d.nx, ny = d.ny, nh = nx / 2 + 1;
-    const S *P = f + d.off;
-    const int y = blockIdx.x;
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        double g[9];
-        pull_node(P, nx, ny, x, y, d.shift, g);
-        X[bitrev((unsigned)x, lognx)] = make_double2(moment_row(a, g), 0.0);
-    }
-    __syncthreads();
-    fft_lds(X, nx, lognx, twx);
-    for (int k = threadIdx.x; k < nh; k += blockDim.x) out[(long long)y * nh + k] = X[k];
-}
-
 // [rows][cols] -> [cols][rows], 32x32 tiles through LDS
 __global__ void __launch_bounds__(256) k_transpose(const double2 *__restrict__ in, double2 *__restrict__ out, int rows,
                                                    int cols)
@@ -114,36 +43,6 @@ __global__ void __launch_bounds__(256) k_transpose(const double2 *__restrict__ i
     for (int j = ty; j < 32; j += 8) {
         const int c = bx + j, r = by + tx;
         if (r < rows && c < cols) out[(long long)c * rows + r] = tile[tx][j];
-    }
-}
-
-__global__ void __launch_bounds__(FFT_THREADS) k_sk_cols(const double2 *__restrict__ in, int ny, int logny,
-                                                         const double2 *__restrict__ twy, double *__restrict__ acc,
-                                                         double inv_n)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double2 *X = reinterpret_cast<double2 *>(smem_raw);
-    const int kx = blockIdx.x;
-    const double2 *line = in + (long long)kx * ny;
-    for (int y = threadIdx.x; y < ny; y += blockDim.x) X[bitrev((unsigned)y, logny)] = line[y];
-    __syncthreads();
-    fft_lds(X, ny, logny, twy);
-    double *A = acc + (long long)kx * ny;
-    for (int k = threadIdx.x; k < ny; k += blockDim.x) {
-        const double2 v = X[k];
-        A[k] += (v.x * v.x + v.y * v.y) * inv_n;
-    }
-}
-
-__global__ void k_sk_read(const double *__restrict__ acc, double *__restrict__ out, int nx, int ny, double inv_ns)
-{
-    const int nh = nx / 2 + 1;
-    const long long per = (long long)nh * ny;
-    const long long total = 9 * per;
-    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < total; k += (long long)gridDim.x * blockDim.x) {
-        const long long a = k / per, rem = k - a * per;
-        const long long ky = rem / nh, kx = rem - ky * nh;
-        out[k] = acc[a * per + kx * ny + ky] * inv_ns;
     }
 }
 
@@ -173,11 +72,13 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_lines(double2 *__restrict__
                                                            const double2 *__restrict__ tw)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ TwCache T;
     double2 *X = reinterpret_cast<double2 *>(smem_raw);
     double2 *line = data + (long long)blockIdx.x * L;
+    tw_cache_load(T, tw, L);
     for (int i = threadIdx.x; i < L; i += blockDim.x) X[bitrev((unsigned)i, logL)] = line[i];
     __syncthreads();
-    fft_lds<INV>(X, L, logL, tw);
+    fft_lds<INV>(X, L, logL, 1, T, L);
     for (int i = threadIdx.x; i < L; i += blockDim.x) line[i] = X[i];
 }
 
@@ -275,48 +176,6 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s)
     if (g > 65536) g = 65536;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(256), 0, s, p, (long long)n, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_sk_sample(int precision, const void *f, const RepDesc *d_reps, const RepDesc &h_rep, int rep_index,
-                            const SkPlan &plan, double *work_a, double *work_b, double *acc, hipStream_t s)
-{
-    const int nx = plan.nx, ny = plan.ny, nh = nx / 2 + 1;
-    const size_t lds_x = sizeof(double2) * nx, lds_y = sizeof(double2) * ny;
-    hipError_t e;
-    if (precision == 0)
-        e = hipFuncSetAttribute((const void *)k_sk_rows<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_x);
-    else
-        e = hipFuncSetAttribute((const void *)k_sk_rows<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_x);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_sk_cols, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_y);
-    if (e != hipSuccess) return e;
-    const double inv_n = 1.0 / ((double)nx * (double)ny);
-    const long long per = (long long)nh * ny;
-    for (int a = 0; a < 9; ++a) {
-        if (precision == 0)
-            hipLaunchKernelGGL(k_sk_rows<double>, dim3(ny), dim3(FFT_THREADS), lds_x, s, (const double *)f, d_reps,
-                               rep_index, a, plan.lognx, (const double2 *)plan.twx, (double2 *)work_a);
-        else
-            hipLaunchKernelGGL(k_sk_rows<float>, dim3(ny), dim3(FFT_THREADS), lds_x, s, (const float *)f, d_reps,
-                               rep_index, a, plan.lognx, (const double2 *)plan.twx, (double2 *)work_a);
-        hipLaunchKernelGGL(k_transpose, dim3((nh + 31) / 32, (ny + 31) / 32), dim3(256), 0, s, (const double2 *)work_a,
-                           (double2 *)work_b, ny, nh);
-        hipLaunchKernelGGL(k_sk_cols, dim3(nh), dim3(FFT_THREADS), lds_y, s, (const double2 *)work_b, ny, plan.logny,
-                           (const double2 *)plan.twy, acc + a * per, inv_n);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    (void)h_rep;
-    return hipSuccess;
-}
-
-hipError_t launch_sk_read(const double *acc, double *out, int nx, int ny, double inv_ns, hipStream_t s)
-{
-    const long long total = 9ll * (nx / 2 + 1) * ny;
-    long long g = (total + 255) / 256;
-    if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_sk_read, dim3((unsigned)g), dim3(256), 0, s, acc, out, nx, ny, inv_ns);
     return hipGetLastError();
 }
 

@@ -1,0 +1,89 @@
+// Private: the in-LDS FFT shared by the structure-factor sampler and the correlated-noise
+// filter.  Twiddles w^t = exp(-2 pi i t / N), t < N/2, come from a table in global memory
+// (tw[t]) through a 3 KiB two-level copy in LDS: w^t = hi[t / 64] lo[t % 64] with
+// lo[l] = w^l and hi[h] = w^(64 h).  A transform of length n <= N uses every (N/n)-th.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lbf {
+
+__device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return bits > 0 ? __brev(v) >> (32 - bits) : 0u; }
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+constexpr int TW_LO = 64, TW_HI = 128;   // N <= 2 * 64 * 128 = 16384
+
+struct TwCache {
+    double2 lo[TW_LO];
+    double2 hi[TW_HI];
+};
+
+// fill T from tw (N/2 entries); the caller's next barrier publishes it
+__device__ __forceinline__ void tw_cache_load(TwCache &T, const double2 *__restrict__ tw, int N)
+{
+    const int half = N >> 1, nhi = N >= 2 * TW_LO ? N / (2 * TW_LO) : 1;
+    for (int i = threadIdx.x; i < TW_LO; i += blockDim.x) T.lo[i] = i < half ? tw[i] : make_double2(1.0, 0.0);
+    for (int h = threadIdx.x; h < nhi; h += blockDim.x) T.hi[h] = tw[h * TW_LO];
+}
+
+__device__ __forceinline__ double2 twiddle(const TwCache &T, int t) { return cmul(T.hi[t >> 6], T.lo[t & (TW_LO - 1)]); }
+
+// `count` independent in-place decimation-in-time transforms of length n = 2^logn (n >= 2)
+// stored back to back in X, each already in bit-reversed order, with the twiddles of an
+// N-point table in T.  Pairs of radix-2 stages are fused into radix-4 passes (the second
+// stage's odd twiddle is the first's times w_4 = -i), with one radix-2 pass when logn is
+// odd.  INV uses the conjugate twiddles exp(+2 pi i k / n) and does not scale.  Ends with
+// a barrier.
+template <bool INV>
+__device__ void fft_lds(double2 *X, int n, int logn, int count, const TwCache &T, int N)
+{
+    int s = 1;
+    for (; s + 1 <= logn; s += 2) {
+        const int lq = s - 1, q = 1 << lq;
+        const int st1 = N >> s, st2 = N >> (s + 1);   // N / 2q and N / 4q
+        const int n4 = n >> 2, total = n4 * count;
+        for (int b = threadIdx.x; b < total; b += blockDim.x) {
+            const int g = b >> (logn - 2), bb = b & (n4 - 1);
+            const int pos = bb & (q - 1);
+            const int base = g * n + ((bb >> lq) << (lq + 2)) + pos;
+            double2 w1 = twiddle(T, pos * st1), w2 = twiddle(T, pos * st2);
+            if (INV) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+            }
+            const double2 a = X[base], bv = X[base + q], c = X[base + 2 * q], d = X[base + 3 * q];
+            const double2 b1 = cmul(w1, bv), d1 = cmul(w1, d);
+            const double2 a1 = cadd(a, b1), bq = csub(a, b1), c1 = cadd(c, d1), dq = csub(c, d1);
+            const double2 c2 = cmul(w2, c1);
+            double2 d2 = cmul(w2, dq);
+            d2 = INV ? make_double2(-d2.y, d2.x) : make_double2(d2.y, -d2.x);   // times +i / -i
+            X[base] = cadd(a1, c2);
+            X[base + 2 * q] = csub(a1, c2);
+            X[base + q] = cadd(bq, d2);
+            X[base + 3 * q] = csub(bq, d2);
+        }
+        __syncthreads();
+    }
+    if (s == logn) {
+        const int half = 1 << (s - 1), st = N >> s, nb = n >> 1, total = nb * count;
+        for (int b = threadIdx.x; b < total; b += blockDim.x) {
+            const int g = b >> (logn - 1), bb = b & (nb - 1);
+            const int pos = bb & (half - 1);
+            const int i0 = g * n + ((bb >> (s - 1)) << s) + pos, i1 = i0 + half;
+            double2 w = twiddle(T, pos * st);
+            if (INV) w.y = -w.y;
+            const double2 u = X[i0], t = cmul(X[i1], w);
+            X[i0] = cadd(u, t);
+            X[i1] = csub(u, t);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace lbf

@@ -109,21 +109,54 @@ hipError_t launch_normals(uint64_t seed, uint32_t replica, uint64_t t, int64_t n
 hipError_t launch_philox(uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, int64_t n,
                          uint32_t *d_out, hipStream_t s);
 
-// structure factor (lb_fft.hip)
-struct SkPlan {
-    int nx, ny;
-    int lognx, logny;
-    double *twx, *twy;      // twiddles exp(-2 pi i k / n), k < n/2, as (re, im) pairs
-};
+// twiddles exp(-2 pi i j / n), j < n/2, as (re, im) pairs (lb_fft.hip)
 hipError_t launch_twiddles(double *tw, int n, hipStream_t s);
 // correlated noise of one replica for step time tdev[0] + toff: fills its xi plane
 hipError_t launch_correlated_noise(int precision, const RepDesc *d_reps, const RepDesc &h_rep, int rep_index,
                                    double *work_a, double *work_b, const double *tw_base, void *xi_base,
                                    const unsigned long long *tdev, int toff, hipStream_t s);
 hipError_t set_fft_lds_limit(int max_line);
-hipError_t launch_sk_sample(int precision, const void *f, const RepDesc *d_reps, const RepDesc &h_rep,
-                            int rep_index, const SkPlan &plan, double *work_a, double *work_b,
-                            double *acc, hipStream_t s);
+
+// structure factor (lb_sk.hip).  Replicas are sampled together: every pass covers a range
+// [r0, r1) of replicas with one launch per kernel, whatever their sizes.
+constexpr int SK_MAX = 16384;       // largest side the sampler transforms
+constexpr int SK_LINE_MAX = 8192;   // longest complex line held in LDS (128 KiB of double2)
+
+struct SkRep {
+    int32_t nx, ny, lognx, logny;
+    int32_t split;      // column blocks per kx: 1 if ny <= SK_LINE_MAX, else 2 (one per output parity)
+    int32_t cpb;        // adjacent kx columns per column block (1 when split)
+    int32_t rpb;        // rows per row block
+    int32_t pad_;
+    int64_t row0;       // first row block of this replica (prefix of ceil(ny / rpb))
+    int64_t col0;       // first column block (prefix of split * ceil(nh / cpb)), nh = nx/2 + 1
+    int64_t soff;       // offset (double2) of its [ny][nh] spectrum inside one mode slot
+    int64_t acc_off;    // offset (double) of its [9][nh][ny] accumulators
+};
+
+struct SkLaunch {
+    const void *f;            // current population buffer
+    const RepDesc *reps;
+    const SkRep *sk;          // device copy of the table
+    int32_t r0, r1;           // replica range
+    int64_t row_base, rows;   // row blocks of the range
+    int64_t col_base, cols;
+    int32_t lds_rows;         // most row points per block in the range (rpb * nx)
+    int32_t lds_cols;         // most column points per block in the range (cpb * ny, or ny/2 if split)
+    int32_t G;                // modes per transform group of the row kernel
+    int64_t Ptot;             // double2 per mode slot (sum of ny * nh over all replicas)
+    double *spec;             // nine mode slots of row spectra
+    double *acc;
+    const double *tw;         // exp(-2 pi i j / nmax), j < nmax/2
+    int32_t nmax;
+};
+hipError_t set_sk_lds_limits(int G, int max_nx, int max_col);
+// add |m_a(k)|^2 / n, a = 0..8, of every replica in the range to its accumulators
+hipError_t launch_sk_sample(int precision, const SkLaunch &a, hipStream_t s);
+// |rho(k)|^2 / n of replica a.r0 (a one-replica range), radially binned into out[0..nbins)
+// (means) and out[nbins..2 nbins) (counts); P, xwide describe the bin metric
+hipError_t launch_sk_snapshot(int precision, const SkLaunch &a, int nx, int ny, int nbins, int P, int xwide,
+                              double *out, hipStream_t s);
 hipError_t launch_sk_read(const double *acc, double *out, int nx, int ny, double inv_ns, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
 

@@ -1,0 +1,391 @@
+// Static structure factor of the nine LB modes, the equilibration measurement of
+// arXiv:1009.0254, Sec. V.A: <|m_a(k)|^2> with a(k) = n^-1/2 sum_r exp(i k.r) a(r)
+// (Sec. III notation).  For a real field |a(k)|^2 = |a(-k)|^2, so the transforms below
+// use exp(-2 pi i k x / n) and keep the half plane kx = 0..nx/2.
+//
+// A sample covers a range of replicas of any sizes with two launches, whatever their sizes:
+//   1. rows: one workgroup per lattice row of any replica in the range.  It pulls the
+//      pre-collision populations, forms G of the nine moments in FP64 and turns each real
+//      row of length nx into its half spectrum with one complex transform of length nx/2
+//      (even samples as real part, odd as imaginary, then the standard split); it repeats
+//      this for the next G modes until all nine are done (the repeated pulls of the same
+//      row hit the caches), writing mode a to slot a of the spectra, [ny][nx/2+1] each;
+//   2. columns: one workgroup per kx and mode reads its column of the row spectra in place
+//      (consecutive kx share cache lines and are kept on one XCD), transforms along y
+//      (lines longer than 8192 are split by one decimation-in-frequency stage into two
+//      half-length transforms, one per output parity) and adds |X|^2 / n to the FP64
+//      accumulators [9][nx/2+1][ny].
+// The radially binned density spectrum (the isotropic average of S_rho(k), used to follow
+// density modes after a quench to c_s^2 < 0, where M(k) of eq. (lb-lang-ft) has growing
+// eigenvalues) reuses 1-3 for mode 0 of one replica and bins |rho(k)|^2 / n with integer
+// shell arithmetic.
+
+#include "lb_fftcore.h"
+#include "lb_internal.h"
+
+namespace lbf {
+
+namespace {
+
+constexpr int SK_THREADS = 1024;   // upper bound; launches use fewer for short lines
+
+// long lines get a full CU (one workgroup fits in LDS); short ones 256 lanes
+int sk_threads(int line) { return line >= 4096 ? 1024 : 256; }
+
+template <int F> __device__ __forceinline__ long long sk_key(const SkRep &q)
+{
+    return F == 0 ? q.row0 : q.col0;
+}
+
+// replica of global block g: the last r in [r0, r1) whose prefix is <= g
+template <int F> __device__ __forceinline__ int sk_find(const SkRep *__restrict__ sk, int r0, int r1, long long g)
+{
+    int lo = r0, hi = r1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sk_key<F>(sk[mid]) <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Workgroups are dealt to the 8 XCDs round robin; give each XCD a contiguous range of
+// logical indices so that neighbouring rows / columns share its L2.  Returns -1 for the
+// padding workgroups of the last range.
+__device__ __forceinline__ long long xcd_logical(long long total)
+{
+    const long long g = blockIdx.x, per = (total + 7) >> 3;
+    const long long l = (g & 7) * per + (g >> 3);
+    return l < total ? l : -1;
+}
+
+// the nine stored values that the pull of node (x, y) reads (pull_node without the shift)
+template <typename S>
+__device__ __forceinline__ void load_pull(const S *__restrict__ P, int nx, int ny, int x, int y, S v[9])
+{
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    v[0] = P[pop_at(nx, 0, x, y)];
+    v[1] = P[pop_at(nx, 1, xm, y)];
+    v[2] = P[pop_at(nx, 2, x, ym)];
+    v[3] = P[pop_at(nx, 3, xp, y)];
+    v[4] = P[pop_at(nx, 4, x, yp)];
+    v[5] = P[pop_at(nx, 5, xm, ym)];
+    v[6] = P[pop_at(nx, 6, xp, ym)];
+    v[7] = P[pop_at(nx, 7, xp, yp)];
+    v[8] = P[pop_at(nx, 8, xm, yp)];
+}
+
+// m = T f with the integer rows of the moment basis of Table I
+__device__ __forceinline__ void moments9(const double g[9], double m[9])
+{
+    const double sa = (g[1] + g[2]) + (g[3] + g[4]);
+    const double sd = (g[5] + g[6]) + (g[7] + g[8]);
+    const double ax = g[1] - g[3], ay = g[2] - g[4], d68 = g[5] - g[7], d97 = g[8] - g[6];
+    m[0] = g[0] + sa + sd;
+    m[1] = ax + d68 + d97;
+    m[2] = ay + d68 - d97;
+    m[3] = -2 * g[0] + sa + 4 * sd;
+    m[4] = (g[1] + g[3]) - (g[2] + g[4]);
+    m[5] = (g[5] + g[7]) - (g[6] + g[8]);
+    m[6] = -ax + 2 * (d68 + d97);
+    m[7] = -ay + 2 * (d68 - d97);
+    m[8] = 2 * g[0] - 4 * sa + 8 * sd;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(SK_THREADS)
+    k_sk_rows(const S *__restrict__ f, const RepDesc *__restrict__ reps, const SkRep *__restrict__ sk, int r0, int r1,
+              long long row_base, long long nrows, int a_first, int a_count, int G, long long Ptot,
+              double2 *__restrict__ spec, const double2 *__restrict__ tw, int nmax)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ TwCache T;
+    double2 *X = reinterpret_cast<double2 *>(smem_raw);
+    const long long lr = xcd_logical(nrows);
+    if (lr < 0) return;
+    tw_cache_load(T, tw, nmax);
+    const long long gr = row_base + lr;
+    const int r = sk_find<0>(sk, r0, r1, gr);
+    const SkRep &q = sk[r];
+    const RepDesc &d = reps[r];
+    const int nx = q.nx, ny = q.ny, M = nx >> 1, logM = q.lognx - 1, nh = M + 1;
+    const int y0 = (int)(gr - q.row0) * q.rpb;
+    const int R = min(q.rpb, ny - y0);          // rows of this block; transform (c, rr) at X[(c R + rr) M]
+    const int pairs = R * M;
+    const S *P = f + d.off;
+    const int wstride = nmax / nx;
+    for (int a0 = a_first; a0 < a_first + a_count; a0 += G) {
+        const int gcount = min(G, a_first + a_count - a0);
+        // two pairs of nodes per lane and iteration, all 36 loads issued before use
+        for (int e0 = threadIdx.x; e0 < pairs; e0 += 2 * blockDim.x) {
+            const int e1 = e0 + blockDim.x < pairs ? e0 + blockDim.x : e0;
+            const int rr0 = e0 / M, n0 = e0 - rr0 * M, rr1 = e1 / M, n1 = e1 - rr1 * M;
+            S v[4][9];
+            load_pull(P, nx, ny, 2 * n0, y0 + rr0, v[0]);
+            load_pull(P, nx, ny, 2 * n0 + 1, y0 + rr0, v[1]);
+            load_pull(P, nx, ny, 2 * n1, y0 + rr1, v[2]);
+            load_pull(P, nx, ny, 2 * n1 + 1, y0 + rr1, v[3]);
+            for (int p = 0; p < 2; ++p) {
+                double ge[9], go[9], me[9], mo[9];
+                for (int i = 0; i < 9; ++i) {
+                    ge[i] = (double)v[2 * p][i] + d.shift[i];
+                    go[i] = (double)v[2 * p + 1][i] + d.shift[i];
+                }
+                moments9(ge, me);
+                moments9(go, mo);
+                const int rr = p ? rr1 : rr0;
+                const unsigned j = bitrev((unsigned)(p ? n1 : n0), logM);
+                for (int c = 0; c < gcount; ++c) X[(c * R + rr) * M + j] = make_double2(me[a0 + c], mo[a0 + c]);
+            }
+        }
+        __syncthreads();
+        fft_lds<false>(X, M, logM, gcount * R, T, nmax);
+        // X_k = E_k + W^k O_k with E = (Z_k + conj Z_{M-k}) / 2, O = (Z_k - conj Z_{M-k}) / 2i,
+        // W = exp(-2 pi i / nx), for k = 0..M (Z has period M)
+        for (int idx = threadIdx.x; idx < gcount * R * nh; idx += blockDim.x) {
+            const int t = idx / nh, k = idx - t * nh;     // t = c R + rr
+            const int c = t / R, rr = t - c * R;
+            const double2 Zk = X[t * M + (k & (M - 1))];
+            const double2 Zm = X[t * M + ((M - k) & (M - 1))];
+            const double2 E = make_double2(0.5 * (Zk.x + Zm.x), 0.5 * (Zk.y - Zm.y));
+            const double2 O = make_double2(0.5 * (Zk.y + Zm.y), -0.5 * (Zk.x - Zm.x));
+            const double2 W = k < M ? twiddle(T, k * wstride) : make_double2(-1.0, 0.0);
+            const double2 WO = cmul(W, O);
+            spec[(a0 + c) * Ptot + q.soff + (long long)(y0 + rr) * nh + k] = make_double2(E.x + WO.x, E.y + WO.y);
+        }
+        __syncthreads();   // X is reused by the next group
+    }
+}
+
+// column transforms of every replica in the range, reading the row spectra in place;
+// mode a = a_first + blockIdx.y.  A block takes cpb adjacent kx (reads coalesced along kx)
+// or, for split lines, one kx and one output parity.  SNAP writes |X|^2 / n to plane
+// ([nh][ny], one replica), otherwise adds it to the accumulators.
+template <bool SNAP>
+__global__ void __launch_bounds__(SK_THREADS)
+    k_sk_cols(const double2 *__restrict__ spec, const SkRep *__restrict__ sk, int r0, int r1, long long col_base,
+              long long ncols, long long Ptot, int a_first, double *__restrict__ acc, double *__restrict__ plane,
+              const double2 *__restrict__ tw, int nmax)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ TwCache T;
+    double2 *X = reinterpret_cast<double2 *>(smem_raw);
+    const long long lc = xcd_logical(ncols);
+    if (lc < 0) return;
+    tw_cache_load(T, tw, nmax);
+    __syncthreads();
+    const long long gc = col_base + lc;
+    const int r = sk_find<2>(sk, r0, r1, gc);
+    const SkRep &q = sk[r];
+    const int ny = q.ny, nh = q.nx / 2 + 1, split = q.split;
+    const int local = (int)(gc - q.col0);
+    const int grp = local / split, par = local - grp * split;
+    const int kx0 = grp * q.cpb;
+    const int C = min(q.cpb, nh - kx0);          // columns of this block
+    const int a = a_first + blockIdx.y;
+    const double2 *S0 = spec + a * Ptot + q.soff + kx0;    // (y, c) at S0[y * nh + c]
+    const double inv_n = 1.0 / ((double)q.nx * (double)ny);
+    int L, logL;
+    if (split == 1) {
+        L = ny;
+        logL = q.logny;
+        const int tot = C * ny;
+        for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * blockDim.x) {
+            double2 v[4];
+            for (int u = 0; u < 4; ++u) {
+                const int e = min(e0 + u * (int)blockDim.x, tot - 1), y = e / C, c = e - y * C;
+                v[u] = S0[(long long)y * nh + c];
+            }
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * (int)blockDim.x;
+                if (e < tot) {
+                    const int y = e / C, c = e - y * C;
+                    X[c * ny + bitrev((unsigned)y, logL)] = v[u];
+                }
+            }
+        }
+    } else {
+        // X_{2k+p} = sum_n [x_n + (-1)^p x_{n+L}] W^{pn} exp(-2 pi i n k / L), W = exp(-2 pi i / ny)
+        L = ny >> 1;
+        logL = q.logny - 1;
+        const int wstride = nmax / ny;
+        for (int n = threadIdx.x; n < L; n += blockDim.x) {
+            const double2 u = S0[(long long)n * nh], v = S0[(long long)(n + L) * nh];
+            const double2 w = par == 0 ? make_double2(u.x + v.x, u.y + v.y)
+                                       : cmul(make_double2(u.x - v.x, u.y - v.y), twiddle(T, n * wstride));
+            X[bitrev((unsigned)n, logL)] = w;
+        }
+    }
+    __syncthreads();
+    fft_lds<false>(X, L, logL, split == 1 ? C : 1, T, nmax);
+    const int tot = (split == 1 ? C : 1) * L;
+    if (SNAP) {
+        double *D = plane + (long long)kx0 * ny;
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int c = e / L, k = e - c * L;
+            const double2 v = X[e];
+            D[(long long)c * ny + k * split + par] = (v.x * v.x + v.y * v.y) * inv_n;
+        }
+    } else {
+        double *A = acc + q.acc_off + (long long)a * nh * ny + (long long)kx0 * ny;
+        for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * blockDim.x) {
+            double old[4];
+            for (int u = 0; u < 4; ++u) {
+                const int e = min(e0 + u * (int)blockDim.x, tot - 1), c = e / L, k = e - c * L;
+                old[u] = A[(long long)c * ny + k * split + par];
+            }
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * (int)blockDim.x;
+                if (e < tot) {
+                    const int c = e / L, k = e - c * L;
+                    const double2 v = X[e];
+                    A[(long long)c * ny + k * split + par] = old[u] + (v.x * v.x + v.y * v.y) * inv_n;
+                }
+            }
+        }
+    }
+}
+
+// smallest t >= 0 with m t^2 >= v (m > 0)
+__device__ __forceinline__ long long ceil_root(long long v, long long m)
+{
+    if (v <= 0) return 0;
+    long long t = (long long)ceil(sqrt((double)v / (double)m));
+    while (t > 0 && m * (t - 1) * (t - 1) >= v) --t;
+    while (m * t * t < v) ++t;
+    return t;
+}
+
+// Shell b of the radial spectrum: with L = min(nx, ny), P = max(nx, ny) / L and
+// R2 = wx kx^2 + wy ky^2 ((wx, wy) = (1, P^2) if nx >= ny, else (P^2, 1)), |k| / (2 pi / L)
+// = sqrt(R2) / P, and k lies in shell b = floor(sqrt(R2) / P + 1/2), i.e.
+// ((2b - 1) P)^2 <= 4 R2 < ((2b + 1) P)^2.  Means over the full k plane without k = 0;
+// the half plane stands for its mirror image with weight 2 except at kx = 0 and nx/2.
+__global__ void __launch_bounds__(256) k_sk_bins(const double *__restrict__ plane, int nx, int ny, int P, int xwide,
+                                                 int nbins, double *__restrict__ out)
+{
+    __shared__ double ss[256], sc[256];
+    const int b = blockIdx.x;
+    const long long wx = xwide ? 1 : (long long)P * P, wy = xwide ? (long long)P * P : 1;
+    const long long lo = b > 0 ? (long long)(2 * b - 1) * P * (2 * b - 1) * P : 0;
+    const long long hi = (long long)(2 * b + 1) * P * (2 * b + 1) * P;
+    const int hx = nx / 2, hy = ny / 2;
+    double s = 0, c = 0;
+    for (int kx = threadIdx.x; kx <= hx; kx += blockDim.x) {
+        const long long ax = 4 * wx * (long long)kx * kx;
+        if (ax >= hi) break;
+        const long long y0 = ceil_root(lo - ax, 4 * wy);
+        const long long y1 = min(ceil_root(hi - ax, 4 * wy), (long long)hy + 1);
+        const double w = (kx == 0 || kx == hx) ? 1.0 : 2.0;
+        const double *D = plane + (long long)kx * ny;
+        for (long long ky = y0; ky < y1; ++ky) {
+            if (kx == 0 && ky == 0) continue;
+            s += w * D[ky];
+            c += w;
+            if (ky >= 1 && ky < hy) {
+                s += w * D[ny - ky];
+                c += w;
+            }
+        }
+    }
+    ss[threadIdx.x] = s;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            ss[threadIdx.x] += ss[threadIdx.x + h];
+            sc[threadIdx.x] += sc[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[b] = sc[0] > 0 ? ss[0] / sc[0] : 0.0;
+        out[nbins + b] = sc[0];
+    }
+}
+
+__global__ void k_sk_read(const double *__restrict__ acc, double *__restrict__ out, int nx, int ny, double inv_ns)
+{
+    const int nh = nx / 2 + 1;
+    const long long per = (long long)nh * ny;
+    const long long total = 9 * per;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < total; k += (long long)gridDim.x * blockDim.x) {
+        const long long a = k / per, rem = k - a * per;
+        const long long ky = rem / nh, kx = rem - ky * nh;
+        out[k] = acc[a * per + kx * ny + ky] * inv_ns;
+    }
+}
+
+unsigned xcd_grid(long long total) { return (unsigned)(((total + 7) >> 3) << 3); }
+
+hipError_t launch_rows(int precision, const SkLaunch &a, int a_first, int a_count, hipStream_t s)
+{
+    const int G = a_count < a.G ? a_count : a.G;
+    const size_t lds = sizeof(double) * (size_t)G * a.lds_rows;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_sk_rows<double>, dim3(xcd_grid(a.rows)), dim3(sk_threads(a.lds_rows)), lds, s,
+                           (const double *)a.f,
+                           a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
+                           (long long)a.Ptot, (double2 *)a.spec, (const double2 *)a.tw, a.nmax);
+    else
+        hipLaunchKernelGGL(k_sk_rows<float>, dim3(xcd_grid(a.rows)), dim3(sk_threads(a.lds_rows)), lds, s,
+                           (const float *)a.f,
+                           a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
+                           (long long)a.Ptot, (double2 *)a.spec, (const double2 *)a.tw, a.nmax);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t set_sk_lds_limits(int G, int max_nx, int max_col)
+{
+    const int rows = (int)sizeof(double) * G * max_nx, cols = (int)sizeof(double2) * max_col;
+    hipError_t e = hipFuncSetAttribute((const void *)k_sk_rows<double>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_sk_rows<float>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_sk_cols<false>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_sk_cols<true>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
+    return e;
+}
+
+hipError_t launch_sk_sample(int precision, const SkLaunch &a, hipStream_t s)
+{
+    hipError_t e = launch_rows(precision, a, 0, 9, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sk_cols<false>, dim3(xcd_grid(a.cols), 9), dim3(sk_threads(a.lds_cols)), sizeof(double2) * a.lds_cols, s,
+                       (const double2 *)a.spec, a.sk, a.r0, a.r1, (long long)a.col_base, (long long)a.cols,
+                       (long long)a.Ptot, 0, a.acc, (double *)nullptr, (const double2 *)a.tw, a.nmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_sk_snapshot(int precision, const SkLaunch &a, int nx, int ny, int nbins, int P, int xwide,
+                              double *out, hipStream_t s)
+{
+    hipError_t e = launch_rows(precision, a, 0, 1, s);
+    if (e != hipSuccess) return e;
+    // the density's |X|^2 / n goes to spectrum slot 1 (unused here) as [nh][ny] doubles
+    double *plane = a.spec + 2 * a.Ptot;
+    hipLaunchKernelGGL(k_sk_cols<true>, dim3(xcd_grid(a.cols), 1), dim3(sk_threads(a.lds_cols)), sizeof(double2) * a.lds_cols, s,
+                       (const double2 *)a.spec, a.sk, a.r0, a.r1, (long long)a.col_base, (long long)a.cols,
+                       (long long)a.Ptot, 0, (double *)nullptr, plane, (const double2 *)a.tw, a.nmax);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sk_bins, dim3((unsigned)nbins), dim3(256), 0, s, (const double *)plane, nx, ny, P, xwide,
+                       nbins, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sk_read(const double *acc, double *out, int nx, int ny, double inv_ns, hipStream_t s)
+{
+    const long long total = 9ll * (nx / 2 + 1) * ny;
+    long long g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_sk_read, dim3((unsigned)g), dim3(256), 0, s, acc, out, nx, ny, inv_ns);
+    return hipGetLastError();
+}
+
+}  // namespace lbf

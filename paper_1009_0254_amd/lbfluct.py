@@ -22,8 +22,8 @@ PRECISIONS = {"fp64": LB_FP64, "fp32": LB_FP32, "fp32s": LB_FP32_SHIFTED}
 INIT_KINDS = {"uniform": 0, "slab": 1, "random": 2, "wave": 3}
 NOISE_KINDS = {"k0": 0, "correlated": 1}
 LB_FEATURE_STRUCTURE_FACTOR = 1
-LB_SK_RESET, LB_SK_SAMPLE, LB_SK_READ = 0, 1, 2
-LB_FLAG_CLAMPED_PIVOT, LB_FLAG_NONPOSITIVE_RHO, LB_FLAG_NAN = 1, 2, 4
+LB_SK_RESET, LB_SK_SAMPLE, LB_SK_READ, LB_SK_SNAPSHOT = 0, 1, 2, 3
+LB_FLAG_CLAMPED_PIVOT, LB_FLAG_NONPOSITIVE_RHO, LB_FLAG_NAN, LB_FLAG_LOW_MACH = 1, 2, 4, 8
 
 
 class LbParams(ctypes.Structure):
@@ -68,6 +68,7 @@ def lib() -> ctypes.CDLL:
         L.lb_step.argtypes = [vp, ctypes.c_int64]
         L.lb_moments.argtypes = [vp, ctypes.c_int32, vp, dp]
         L.lb_structure_factor.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int64)]
+        L.lb_set_sampling.argtypes = [vp, ctypes.c_int64, ctypes.c_int64]
         L.lb_status_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int64)]
         L.lb_noise_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64,
                                        ctypes.c_int32, vp, vp]
@@ -78,7 +79,7 @@ def lib() -> ctypes.CDLL:
         L.lb_strerror.argtypes = [ctypes.c_int32]
         L.lb_strerror.restype = ctypes.c_char_p
         for fn in ("lb_workspace_size", "lb_init", "lb_step", "lb_moments", "lb_structure_factor",
-                   "lb_status_flags", "lb_noise_normals", "lb_philox", "lb_tuning"):
+                   "lb_set_sampling", "lb_status_flags", "lb_noise_normals", "lb_philox", "lb_tuning"):
             getattr(L, fn).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -175,6 +176,12 @@ class Lattice:
         return m, np.array(tot[:])
 
     def lb_structure_factor(self, op: int, rep: int = -1):
+        if op == LB_SK_SNAPSHOT:
+            nb = ctypes.c_int64(0)
+            _check("lb_structure_factor", lib().lb_structure_factor(self._h, op, rep, None, ctypes.byref(nb)))
+            out = torch.empty((2, nb.value), dtype=torch.float64, device=self.device)
+            _check("lb_structure_factor", lib().lb_structure_factor(self._h, op, rep, out.data_ptr(), ctypes.byref(nb)))
+            return out
         if op == LB_SK_READ:
             c = self.cfgs[rep]
             out = torch.empty((9, c["ny"], c["nx"] // 2 + 1), dtype=torch.float64, device=self.device)
@@ -183,6 +190,9 @@ class Lattice:
             return out, ns.value
         _check("lb_structure_factor", lib().lb_structure_factor(self._h, op, rep, None, None))
         return None
+
+    def lb_set_sampling(self, every: int, first_step: int = 0):
+        _check("lb_set_sampling", lib().lb_set_sampling(self._h, int(every), int(first_step)))
 
     def lb_status_flags(self):
         f = ctypes.c_uint32(0)

@@ -65,13 +65,14 @@ def test_strerror():
 
 
 def test_workspace_size_counts_both_population_buffers():
-    c = W.single_phase(64, 48)
-    n = 64 * 48
+    c = W.single_phase(64, 32)
+    n = 64 * 32
     b64 = L.lb_workspace_size([c], L.LB_FP64)
     b32 = L.lb_workspace_size([c], L.LB_FP32_SHIFTED)
     assert b64 >= 2 * 9 * n * 8 and b32 >= 2 * 9 * n * 4 and b64 > b32
     bsk = L.lb_workspace_size([c], L.LB_FP32_SHIFTED, L.LB_FEATURE_STRUCTURE_FACTOR)
-    assert bsk >= b32 + 9 * 48 * 33 * 8
+    # accumulators [9][33][32] plus the row spectra of all nine modes
+    assert bsk >= b32 + 9 * 32 * 33 * 8 + 9 * 32 * 33 * 16
     two = L.lb_workspace_size([c, W.single_phase(128, 128)], L.LB_FP32_SHIFTED)
     assert two >= b32 + 2 * 9 * 128 * 128 * 4
 
@@ -119,3 +120,23 @@ def test_all_workloads_validate():
     assert len(reps) == 336
     assert sum(r["nx"] * r["ny"] for r in reps) == 12_582_912
     assert L.lb_workspace_size(reps, L.LB_FP32_SHIFTED) > 2 * 9 * 12_582_912 * 4
+
+
+def test_structure_factor_feature_size_rules():
+    F = L.LB_FEATURE_STRUCTURE_FACTOR
+    for nx, ny in [(16384, 16), (16, 16384), (4, 4), (256, 128)]:
+        assert L.lb_workspace_size([W.single_phase(nx, ny)], L.LB_FP32_SHIFTED, F) > 0
+    for nx, ny in [(48, 32), (32768, 4), (2, 8), (64, 3)]:
+        with pytest.raises(L.LbError) as e:
+            L.lb_workspace_size([W.single_phase(nx, ny)], L.LB_FP32_SHIFTED, F)
+        assert e.value.status == L.LB_EINVAL
+    # unknown feature bits
+    with pytest.raises(L.LbError) as e:
+        L.lb_workspace_size([W.single_phase(16, 16)], L.LB_FP32_SHIFTED, 2)
+    assert e.value.status == L.LB_EINVAL
+    # the 16384^2 workspace: two FP32 population buffers, the FP64 initial density, the
+    # accumulators and the row spectra of the nine modes
+    n = 16384 * 16384
+    want = 2 * 9 * n * 4 + n * 8 + 9 * 16384 * 8193 * 8 + 9 * 16384 * 8193 * 16
+    b = L.lb_workspace_size([W.cfg5()], L.LB_FP32_SHIFTED, F)
+    assert want <= b < want + (64 << 20)

@@ -300,13 +300,29 @@ def test_status_flags_clean_and_clamp():
 # ------------------------------------------------------------------ structure factor
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (2, 1e-4)])
-def test_structure_factor_matches_oracle_fft(precision, tol):
+def fp64_spectrum_tol(n, smax):
+    """FP64 FFT rounding: the k = 0 coefficient (sum of a moment, ~ n) spreads errors of
+    ~ eps log2(n) n over every output; relative to sqrt(n S_max) that bounds the error of
+    S(k) / S_max, with a factor 8 of margin."""
+    eps = 2.2e-16
+    return 1e-10 + 8 * 2 * eps * np.log2(n) * n / np.sqrt(n * smax)
+
+
+SK_SHAPES = [(64, 32), (16384, 16), (16, 16384), (2048, 8), (4, 4)]
+
+
+@pytest.mark.parametrize("shape", SK_SHAPES, ids=[f"{a}x{b}" for a, b in SK_SHAPES])
+@pytest.mark.parametrize("precision", [0, 2])
+def test_structure_factor_matches_oracle_fft(precision, shape):
+    """All nine |m_a(k)|^2 against numpy's FFT of the oracle's moments: rows of length 16384
+    (real-to-complex split), columns of 16384 (one decimation-in-frequency stage), several
+    modes per pass (2048 wide: 8 + 1) and the smallest lattice."""
     L = _L()
-    cfg = W.single_phase(64, 32, kT=1e-5, seed=31)
+    nx, ny = shape
+    cfg = W.single_phase(nx, ny, kT=1e-5, seed=31)
     lat = L.Lattice(cfg, precision=precision, structure_factor=True)
     ora = O.Oracle(cfg)
-    acc = np.zeros((9, 32, 33))
+    acc = np.zeros((9, ny, nx // 2 + 1))
     for _ in range(5):
         lat.step(7)
         ora.step(7)
@@ -319,12 +335,134 @@ def test_structure_factor_matches_oracle_fft(precision, tol):
     mask = np.ones_like(want, dtype=bool)
     mask[:, 0, 0] = False                     # k = 0 carries the conserved totals
     err = np.abs(S - want)[mask].max() / want[mask].max()
-    say("S(k) precision", precision, "err", err)
+    tol = fp64_spectrum_tol(nx * ny, want[mask].max()) if precision == 0 else 1e-4
+    say("S(k)", shape, "precision", precision, "err", err, "tol", tol)
     assert err < tol
     lat.lb_structure_factor(L.LB_SK_RESET, -1)
     S2, ns2 = lat.lb_structure_factor(L.LB_SK_READ, 0)
     assert ns2 == 0 and float(S2.abs().max()) == 0.0
     lat.close()
+
+
+def test_ensemble_sample_is_batched_and_bitwise_per_replica():
+    """One batched sample of replicas of different sizes equals sampling each alone, bit
+    for bit, and the oracle's spectrum."""
+    L = _L()
+    cfgs = [W.single_phase(64, 32, kT=1e-5, seed=1), W.single_phase(128, 128, kT=2e-5, seed=2),
+            dict(W.single_phase(16, 64, kT=1e-5, seed=3), replica=5), W.single_phase(256, 8, kT=1e-5, seed=4)]
+    a = L.Lattice(cfgs, precision=2, structure_factor=True)
+    b = L.Lattice(cfgs, precision=2, structure_factor=True)
+    for _ in range(3):
+        a.step(5)
+        b.step(5)
+        a.lb_structure_factor(L.LB_SK_SAMPLE, -1)
+        for r in range(len(cfgs)):
+            b.lb_structure_factor(L.LB_SK_SAMPLE, r)
+    for r, c in enumerate(cfgs):
+        Sa, na = a.lb_structure_factor(L.LB_SK_READ, r)
+        Sb, nb = b.lb_structure_factor(L.LB_SK_READ, r)
+        assert na == nb == 3
+        assert torch.equal(Sa, Sb), r
+    o = O.Oracle(cfgs[1])
+    acc = np.zeros((9, 128, 65))
+    for _ in range(3):
+        o.step(5)
+        acc += O.power_spectrum(o.moments())
+    S1 = a.lb_structure_factor(L.LB_SK_READ, 1)[0].cpu().numpy()
+    mask = np.ones_like(acc, dtype=bool)
+    mask[:, 0, 0] = False
+    err = np.abs(S1 - acc / 3)[mask].max() / (acc / 3)[mask].max()
+    say("batched S(k) err", err)
+    assert err < 1e-4
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("every,first,steps", [(7, 5, 60), (300, 0, 700), (32, 64, 200)])
+def test_sampling_inside_lb_step_equals_manual_sampling(every, first, steps):
+    """lb_set_sampling: graphs of `every` steps plus a sample (every <= 256) and the eager
+    path (every > 256) both equal stepping and sampling by hand, bit for bit."""
+    L = _L()
+    cfgs = [W.single_phase(64, 32, kT=1e-5, seed=8), W.single_phase(32, 32, kT=1e-5, seed=9)]
+    a = L.Lattice(cfgs, precision=2, structure_factor=True)
+    b = L.Lattice(cfgs, precision=2, structure_factor=True)
+    a.lb_set_sampling(every, first)
+    a.step(steps // 3)
+    a.step(steps - steps // 3)
+    t = 0
+    times = [ts for ts in range(first, steps + 1, every) if ts > 0]
+    for ts in times:
+        b.step(ts - t)
+        b.lb_structure_factor(L.LB_SK_SAMPLE, -1)
+        t = ts
+    b.step(steps - t)
+    for r in range(2):
+        Sa, na = a.lb_structure_factor(L.LB_SK_READ, r)
+        Sb, nb = b.lb_structure_factor(L.LB_SK_READ, r)
+        say("in-step sampling", every, first, steps, "samples", na, nb)
+        assert na == nb == len(times)
+        assert torch.equal(Sa, Sb)
+        assert np.array_equal(a.moments(r), b.moments(r))
+    a.lb_set_sampling(0)
+    a.step(every + 1)
+    assert a.lb_structure_factor(L.LB_SK_READ, 0)[1] == len(times)
+    a.close()
+    b.close()
+
+
+SNAP_SHAPES = [(64, 64), (128, 32), (16384, 16), (16, 16384)]
+
+
+@pytest.mark.parametrize("shape", SNAP_SHAPES, ids=[f"{a}x{b}" for a, b in SNAP_SHAPES])
+@pytest.mark.parametrize("precision", [0, 2])
+def test_radial_density_snapshot_matches_oracle(precision, shape):
+    L = _L()
+    nx, ny = shape
+    cfg = W.spinodal(nx, ny, kT=1e-6, amp=1e-3, seed=21)
+    lat = L.Lattice(cfg, precision=precision, structure_factor=True)
+    ora = O.Oracle(cfg)
+    lat.step(12)
+    ora.step(12)
+    out = lat.lb_structure_factor(L.LB_SK_SNAPSHOT, 0).cpu().numpy()
+    mean, counts = O.radial_spectrum(ora.moments()[0])
+    assert out.shape == (2, len(mean))
+    assert np.array_equal(out[1], counts.astype(np.float64))
+    err = np.abs(out[0] - mean).max() / mean.max()
+    tol = fp64_spectrum_tol(nx * ny, mean.max()) if precision == 0 else 1e-4
+    say("snapshot", shape, precision, "err", err, "tol", tol)
+    assert err < tol
+    lat.close()
+
+
+def test_radial_snapshot_16384_plane_wave_closed_form():
+    """The 16384^2 quench lattice in FP32-shifted storage: a density wave at (kx, ky) =
+    (3, 4) puts |rho(+-k)|^2 = a^2 n / 4 into shell 5 and nothing elsewhere.
+
+    Floor: with c0sq = 0 the rest population holds most of the mass, so the stored
+    f_0 - w_0 rho0 is ~0.556 (FP32 ulp 6e-8); the wave has only 16384 distinct phases, over
+    which that rounding projects onto the amplitude as ~ 6e-8 / sqrt(12) sqrt(2 / 16384) 2 / a
+    = 3.8e-10 / a relative in S (one sigma): 2e-8 at a = 0.02, gated at 1e-6."""
+    L = _L()
+    nx = ny = 16384
+    a = 0.02
+    cfg = W.wave(W.cfg5(), 3, 4, a)
+    say("snapshot 16384^2 wave")
+    lat = L.Lattice(cfg, precision=2, structure_factor=True)
+    out = lat.lb_structure_factor(L.LB_SK_SNAPSHOT, 0).cpu().numpy()
+    lat.close()
+    nb = out.shape[1]
+    assert nb == int(O.radial_shell(nx // 2, ny // 2, nx, ny)) + 1
+    assert out[1].sum() == nx * ny - 1
+    # the inner shells, counted by the oracle's shell function on a window around k = 0
+    kk = np.arange(-12, 13)
+    KX, KY = np.meshgrid(kk, kk)
+    b = O.radial_shell(KX, KY, nx, ny)
+    inner = np.bincount(b[(KX != 0) | (KY != 0)], minlength=12)[:11]
+    assert np.array_equal(out[1][:11], inner.astype(np.float64))
+    want = 2 * a * a * nx * ny / 4 / out[1][5]
+    say("shell 5", out[0][5], "want", want, "others max", np.delete(out[0], 5).max())
+    assert abs(out[0][5] / want - 1) < 1e-6
+    assert np.delete(out[0], 5).max() < 1e-12 * want
 
 
 # ------------------------------------------------------------------ full size, sampled

@@ -480,3 +480,75 @@ def test_equipartition_with_correlated_noise_matches_paper_G():
     for a in range(9):
         r = np.array(ratios[a])
         assert abs(r.mean() - 1) < 0.02, (a, r.mean())
+
+
+# ------------------------------------------------------------------ radial density spectrum
+
+
+@pytest.mark.parametrize("nx,ny", [(8, 8), (16, 4), (4, 32), (32, 32)])
+def test_radial_shell_matches_exact_definition(nx, ny):
+    """Brute force with exact rationals: b is the integer with (b - 1/2)^2 <= q < (b + 1/2)^2,
+    q = (|k| L / 2 pi)^2."""
+    from fractions import Fraction
+    L = min(nx, ny)
+    for kx in range(-nx // 2, nx // 2 + 1):
+        for ky in range(-ny // 2, ny // 2 + 1):
+            q = Fraction(kx * L, nx) ** 2 + Fraction(ky * L, ny) ** 2
+            b = 0
+            while not (Fraction(2 * b - 1, 2) ** 2 <= q < Fraction(2 * b + 1, 2) ** 2 or (b == 0 and q < Fraction(1, 4))):
+                b += 1
+            assert int(O.radial_shell(kx, ky, nx, ny)) == b, (kx, ky)
+
+
+def test_radial_spectrum_parseval_and_counts():
+    rng = np.random.default_rng(5)
+    for nx, ny in [(64, 64), (128, 16), (8, 64)]:
+        rho = 1.0 + 0.01 * rng.standard_normal((ny, nx))
+        mean, counts = O.radial_spectrum(rho)
+        assert counts.sum() == nx * ny - 1
+        assert counts[-1] > 0
+        # Parseval: the power off k = 0 is the variance sum
+        assert np.isclose((mean * counts).sum(), ((rho - rho.mean()) ** 2).sum(), rtol=1e-12)
+
+
+def test_radial_spectrum_of_a_plane_wave():
+    nx = ny = 64
+    a = 1e-3
+    y, x = np.mgrid[0:ny, 0:nx]
+    rho = 1.0 + a * np.cos(2 * np.pi * (3 * x / nx + 4 * y / ny))
+    mean, counts = O.radial_spectrum(rho)
+    # |rho(+-k)|^2 = (a n / 2)^2 / n at the two points of shell 5, nothing elsewhere
+    want = 2 * a * a * nx * ny / 4 / counts[5]
+    assert np.isclose(mean[5], want, rtol=1e-12)
+    others = np.delete(mean, 5)
+    assert np.abs(others).max() < 1e-20 * want * nx * ny
+
+
+def test_quench_density_spectrum_follows_linear_theory():
+    """A quench to c_s^2 = -0.01 (c0sq = 0, A = -0.01, rho0 = rhoc): from a 1e-7 random
+    density, every k evolves as dm(k, t) = M(k)^t dm(k, 0) (eq. lb-lang-ft) while the
+    amplitude stays small; the radially binned S_rho follows, unstable shells growing."""
+    nx = ny = 64
+    steps = 150
+    cfg = W.spinodal(nx, ny, kT=0.0, amp=1e-7, seed=3)
+    o = O.Oracle(cfg)
+    m0 = o.moments()
+    n = nx * ny
+    A0 = n * np.fft.ifft2(m0, axes=(-2, -1))      # a(k) = sum_r exp(+i k.r) a(r)
+    o.step(steps)
+    got, counts = O.radial_spectrum(o.moments()[0])
+    rho_t = np.zeros((ny, nx), dtype=complex)
+    lam, cs2 = _lam(cfg), _cs2(cfg)
+    assert cs2 < 0
+    for iy in range(ny):
+        for ix in range(nx):
+            M = th.step_matrix(2 * np.pi * ix / nx, 2 * np.pi * iy / ny, lam, cs2, cfg["rho0"], cfg["kappa"])
+            rho_t[iy, ix] = (np.linalg.matrix_power(M, steps) @ A0[:, iy, ix])[0]
+    S = np.abs(rho_t) ** 2 / n
+    KX, KY = np.meshgrid(np.rint(np.fft.fftfreq(nx, 1.0 / nx)).astype(int), np.rint(np.fft.fftfreq(ny, 1.0 / ny)).astype(int))
+    b = O.radial_shell(KX, KY, nx, ny)
+    keep = ~((KX == 0) & (KY == 0))
+    want = np.bincount(b[keep], weights=S[keep], minlength=len(got)) / np.maximum(counts, 1)
+    assert np.abs(got - want).max() <= 1e-4 * want.max()
+    s0, _ = O.radial_spectrum(m0[0])
+    assert (got / np.maximum(s0, 1e-300)).max() > 30      # the most unstable shells grew
