@@ -27,8 +27,10 @@ METRIC = "MLUPS and % HBM roofline, FP32-shifted vs FP64, at stated S(k)/moment 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"fp32s": 72, "fp32": 72, "fp64": 144}   # read + write of 9 populations
 COUNTERS = os.path.join(ROOT, "profiles", "k_step_fp32s_8192_counters.json")
-# the byte counters depend on the kernel and on the tile list that lb_init builds
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1009_0254_amd", "csrc", f) for f in ("lb_kernels.hip", "lb_api.hip")]
+# the byte counters depend on the step kernel (its source, RNG and shared structs) and on the
+# tile list that lb_init builds
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1009_0254_amd", "csrc", f)
+               for f in ("lb_kernels.hip", "lb_rng.h", "lb_internal.h", "lb_tiles.hip")]
 
 
 def log(*a):
@@ -63,15 +65,18 @@ def time_precision(torch, L, cfg, precision, steps, warmup):
     return wall, ev_ms, flags, tune
 
 
-def traffic_from_counters():
+def traffic_from_counters(tile=None):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
     scaled by the same counters' reading of a plain copy of known size; null when the
-    kernel source has changed since the counters were taken."""
+    kernel source has changed since the counters were taken, or when this run's tile shape
+    (strip width, rows) is not the one profiled."""
     try:
         c = json.load(open(COUNTERS))
     except (OSError, ValueError):
         return None
     if c.get("kernel_src_sha") != kernel_sha():
+        return None
+    if tile is not None and c.get("tile") != "%d,%d" % tile:
         return None
     return c.get("hbm_bytes_per_launch")
 
@@ -113,6 +118,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-sk", action="store_true", help="skip timing one S(k) sample")
+    ap.add_argument("--no-correlated", action="store_true",
+                    help="skip timing the same lattice with spatially correlated noise")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after timing, copy this many bytes once with a plain device copy "
                          "(calibrates profiler byte counters)")
@@ -158,8 +165,9 @@ def main():
                    "nx": reps[0]["nx"], "ny": reps[0]["ny"], "precision": prec, "parallelism": "single GPU",
                    "tile": {"strip_width": tune[0], "rows": tune[1], "tiles": tune[2]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters(),
-                     "kernel": "k_step<float,float>", "bytes_per_update": BYTES_PER_UPDATE[prec]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters((tune[0], tune[1])),
+                     "kernel": "k_step<float,float,false,false>", "tile": "%d,%d" % (tune[0], tune[1]),
+                     "bytes_per_update": BYTES_PER_UPDATE[prec]},
         "status_flags": flags,
     }
     if not args.no_fp64:
@@ -172,6 +180,14 @@ def main():
                        "tile": {"strip_width": tune64[0], "rows": tune64[1]}}
         out["fp32s_over_fp64"] = out["value"] / out["fp64"]["value"]
         log(f"fp64: {out['fp64']['ms_per_step']:.4f} ms/step, {out['fp64']['value']:.0f} MLUPS")
+    if (not args.no_correlated and len(reps) == 1 and max(cfg["nx"], cfg["ny"]) <= 8192
+            and cfg["nx"] & (cfg["nx"] - 1) == 0 and cfg["ny"] & (cfg["ny"] - 1) == 0 and cfg["kT"] > 0):
+        # the same lattice with the exact Xi(k) noise: per step the FFT noise filter + the step
+        sc = max(args.steps // 3, 10)
+        wc, ec, fc, tc = time_precision(torch, L, [dict(cfg, noise="correlated")], prec, sc, args.warmup // 3 + 1)
+        out["correlated_noise"] = {"ms_per_step": wc * 1e3 / sc, "MLUPS": n * sc / wc / 1e6,
+                                   "time_over_k0_noise": (wc * 1e3 / sc) / ms, "status_flags": fc}
+        log(f"correlated noise: {wc * 1e3 / sc:.4f} ms/step ({(wc * 1e3 / sc) / ms:.2f}x the k=0 noise step)")
     if not args.no_sk:
         # one S(k) sample of all nine modes of every replica (one batched pass), and one
         # radially binned density snapshot of replica 0

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace lbf {
 
 constexpr int Q = 9;
@@ -95,6 +97,9 @@ struct StepLaunch {
     int32_t bx;
     int32_t plain;   // 1: stored values are f_i (sub_i = w_i rho0); 0: stored f_i - w_i rho0
 };
+
+// the fused step's tiles for strips of bx lanes and tiles of about h rows (lb_tiles.hip)
+std::vector<Tile> make_tiles(const std::vector<RepDesc> &reps, int bx, double h);
 
 // launchers (lb_kernels.hip); all return hipSuccess or the launch error
 hipError_t launch_step(int precision, const StepLaunch &a, hipStream_t s);

@@ -40,7 +40,8 @@ template <> __device__ __forceinline__ double fsqrt<double>(double v) { return s
 // ------------------------------------------------------------------ the collision
 // Deviations df_i = f_i - w_i rho0 in, post-collision deviations out.  Stencil values
 // are of drho = rho - rho0.  Returns status bits (LB_FLAG_*).
-template <typename R>
+// CN: the replica set has correlated noise (noise == 2 possible)
+template <typename R, bool CN>
 __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Consts<R> &c, uint32_t noise,
                                             uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
                                             uint32_t k1, R xi4, R xi9)
@@ -89,7 +90,7 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
     R s8 = m8 + lq * m8;
     R s9 = m9 + le * (m9 - e9);
 
-    if (noise == 2) {
+    if (CN && noise == 2) {
         // correlated noise: modes 4 and 9 from the filtered fields, modes 5..8 white at rho0
         R nu[6];
         normals6<R>(node, rep, t, k0, k1, nu);
@@ -161,7 +162,7 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
 
 // ------------------------------------------------------------------ fused step kernel
 
-template <typename S, typename R, bool PLAIN>
+template <typename S, typename R, bool PLAIN, bool CN>
 __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S *__restrict__ fin, S *__restrict__ fout,
                                               const RepDesc *__restrict__ reps, const Tile *__restrict__ tiles,
                                               const unsigned long long *__restrict__ tdev,
@@ -242,12 +243,12 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
             for (int i = 0; i < Q; ++i) cur[i] -= c.sub[i];
         }
         R xi4 = 0, xi9 = 0;
-        if (d.noise == 2) {
+        if (CN && d.noise == 2) {
             const S *__restrict__ xr = xi + 2 * (d.xi_off + (long long)y * nx + xw);
             xi4 = (R)xr[0];
             xi9 = (R)xr[1];
         }
-        st |= collide<R>(cur, lap, gx, gy, c, d.noise, (unsigned)y * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi,
+        st |= collide<R, CN>(cur, lap, gx, gy, c, d.noise, (unsigned)y * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi,
                          xi4, xi9);
         if (store) {
             S *__restrict__ o = Qo + (unsigned long long)(unsigned)y * pitch;
@@ -508,23 +509,25 @@ static int grid_for(long long n, int threads, int cap = 65536)
     return (int)g;
 }
 
-template <typename S, typename R, bool PLAIN>
+template <typename S, typename R, bool PLAIN, bool CN>
 static void launch_step_t(const StepLaunch &a, hipStream_t s)
 {
     const dim3 grid(a.ntiles), block(a.bx);
     const size_t lds = 4 * (a.bx + 2) * sizeof(R);
-    hipLaunchKernelGGL((k_step<S, R, PLAIN>), grid, block, lds, s, (const S *)a.xi, (const S *)a.fin, (S *)a.fout,
+    hipLaunchKernelGGL((k_step<S, R, PLAIN, CN>), grid, block, lds, s, (const S *)a.xi, (const S *)a.fin, (S *)a.fout,
                        a.reps, a.tiles, a.tdev, a.flags, a.toff);
 }
 
 hipError_t launch_step(int precision, const StepLaunch &a, hipStream_t s)
 {
+    // the correlated-noise read is compiled only into the variant for handles that have it
+    const bool cn = a.xi != nullptr;
     if (precision == 0)
-        launch_step_t<double, double, false>(a, s);
+        cn ? launch_step_t<double, double, false, true>(a, s) : launch_step_t<double, double, false, false>(a, s);
     else if (a.plain)
-        launch_step_t<float, float, true>(a, s);
+        cn ? launch_step_t<float, float, true, true>(a, s) : launch_step_t<float, float, true, false>(a, s);
     else
-        launch_step_t<float, float, false>(a, s);
+        cn ? launch_step_t<float, float, false, true>(a, s) : launch_step_t<float, float, false, false>(a, s);
     return hipGetLastError();
 }
 
