@@ -111,23 +111,36 @@ def make_params(cfg: dict) -> LboParams:
 
 
 def correlated_noise_fields(cfg: dict, t: int):
-    """xi_4(r), xi_9(r) with <xi_a(k) xi_b(-k)> = Xi_ab(k) of eq. (noise-yeo) for a, b in {4, 9}.
+    """xi_4(r), xi_9(r) with <xi_a(k) xi_b(-k)> = Xi_ab(k) of eq. (noise-yeo) for a, b in {4, 9},
+    built in Fourier space as Sec. IV (last paragraph) describes.
 
-    White unit normals w_4, w_9 per node (Philox, counter (node, replica | 2^31, t), the
-    first two normals of the block) are transformed with the unitary FFT, multiplied by
-    the lower Cholesky factor L(k) of the (4,9) block of Xi(k) at the homogeneous state
-    (rho0, c_s^2(rho0)), with c_s^2(k) = c_s^2 + rho0 kappa k^2 and k^2 minus the App. B
-    Laplacian symbol (eq. sound-speed-k), and transformed back.  Sec. IV (last paragraph)."""
+    At every lattice k: xi(k) = L(k) nu(k), with L(k) the lower Cholesky factor of the (4,9)
+    block of Xi(k) at the homogeneous state (rho0, c_s^2(rho0)), c_s^2(k) = c_s^2 + rho0 kappa k^2
+    and k^2 minus the App. B Laplacian symbol (eq. sound-speed-k), and nu(k) unit Gaussians with
+    nu(-k) = conj(nu(k)) so that the fields are real: complex (g0 + i g1) / sqrt(2) for nu_4 and
+    (g2 + i g3) / sqrt(2) for nu_9 where k != -k, real g0 and g1 at the four points k = -k.
+    The pair k, -k takes the g's of the Philox block of the one with the smaller index
+    ky nx + kx (counter (that index, replica | 2^31, t)), the other member its conjugate.
+    Then one transform back to real space: xi(r) = n^-1/2 sum_k exp(-i k.r) xi(k), done for
+    both fields at once as xi_4 + i xi_9 = n^-1/2 FFT(xi_4(k) + i xi_9(k))."""
     nx, ny = int(cfg["nx"]), int(cfg["ny"])
     n = nx * ny
     rep = int(cfg.get("replica", 0)) | CORRELATED_STREAM
     z = normals_batch(int(cfg.get("seed", 1)), rep, t, n)
-    w4 = z[:, 0].reshape(ny, nx)
-    w9 = z[:, 1].reshape(ny, nx)
-    W4 = np.fft.fft2(w4) / np.sqrt(n)
-    W9 = np.fft.fft2(w9) / np.sqrt(n)
-    kx = 2 * np.pi * np.fft.fftfreq(nx)[None, :]
-    ky = 2 * np.pi * np.fft.fftfreq(ny)[:, None]
+    ix = np.arange(nx)[None, :]
+    iy = np.arange(ny)[:, None]
+    idx = iy * nx + ix
+    midx = ((ny - iy) % ny) * nx + (nx - ix) % nx
+    canon = np.minimum(idx, midx)
+    g = z[canon.reshape(-1)].reshape(ny, nx, 6)
+    selfconj = idx == midx
+    nu4 = np.where(selfconj, g[..., 0], (g[..., 0] + 1j * g[..., 1]) / np.sqrt(2.0))
+    nu9 = np.where(selfconj, g[..., 1], (g[..., 2] + 1j * g[..., 3]) / np.sqrt(2.0))
+    mirror = idx > midx
+    nu4 = np.where(mirror, np.conj(nu4), nu4)
+    nu9 = np.where(mirror, np.conj(nu9), nu9)
+    kx = 2 * np.pi * ix / nx
+    ky = 2 * np.pi * iy / ny
     lap = ((4.0 / 9.0) * (np.cos(kx) + np.cos(ky)) + (2.0 / 9.0) * np.cos(kx) * np.cos(ky) - 10.0 / 9.0) * 3.0
     rho0 = cfg.get("rho0", 1.0)
     x = rho0 - cfg.get("rhoc", 1.0)
@@ -142,9 +155,9 @@ def correlated_noise_fields(cfg: dict, t: int):
     l44 = np.sqrt(np.maximum(x44, 0.0))
     l94 = np.where(l44 > 0, x49 / np.where(l44 > 0, l44, 1.0), 0.0)
     l99 = np.sqrt(np.maximum(x99 - l94 * l94, 0.0))
-    xi4 = np.fft.ifft2(l44 * W4) * np.sqrt(n)
-    xi9 = np.fft.ifft2(l94 * W4 + l99 * W9) * np.sqrt(n)
-    return np.ascontiguousarray(xi4.real), np.ascontiguousarray(xi9.real)
+    Z = l44 * nu4 + 1j * (l94 * nu4 + l99 * nu9)
+    out = np.fft.fft2(Z) / np.sqrt(n)
+    return np.ascontiguousarray(out.real), np.ascontiguousarray(out.imag)
 
 
 class Oracle:

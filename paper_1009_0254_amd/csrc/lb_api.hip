@@ -47,7 +47,7 @@ struct Layout {
     size_t sk_tw, sk_reps, spec, acc;   // structure factor
     int sk_G, sk_nmax;
     long long sk_ptot;
-    size_t xi, cn_a, cn_b, cn_tw;     // correlated noise
+    size_t xi, cn_a, cn_tw;     // correlated noise
     long long cn_nodes, cn_max_n, cn_tw_elems;
     size_t total;
     long long nodes;      // sum of nx*ny
@@ -199,7 +199,6 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
     if (L.cn_nodes > 0) {
         L.xi = o; o += align_up((size_t)2 * L.cn_nodes * elem_size(precision));
         L.cn_a = o; o += align_up(sizeof(double) * 2 * (size_t)L.cn_max_n);
-        L.cn_b = o; o += align_up(sizeof(double) * 2 * (size_t)L.cn_max_n);
         L.cn_tw = o; o += align_up(sizeof(double) * 2 * (size_t)L.cn_tw_elems);
     }
     L.total = o;
@@ -239,7 +238,7 @@ struct lb_handle {
     // correlated noise
     std::vector<int> cn_reps;
     void *xi = nullptr;
-    double *cn_a = nullptr, *cn_b = nullptr, *cn_tw = nullptr;
+    double *cn_a = nullptr, *cn_tw = nullptr;
 };
 
 namespace {
@@ -335,7 +334,7 @@ lb_status set_tiles(lb_handle *h, int bx, double rows)
 hipError_t step_once(lb_handle *h, int par, int toff, hipStream_t s)
 {
     for (int r : h->cn_reps) {
-        hipError_t e = launch_correlated_noise(h->precision, h->reps_d, h->reps[r], r, h->cn_a, h->cn_b, h->cn_tw,
+        hipError_t e = launch_correlated_noise(h->precision, h->reps_d, h->reps[r], r, h->cn_a, h->cn_tw,
                                                h->xi, h->tdev, toff, s);
         if (e != hipSuccess) return e;
     }
@@ -600,7 +599,6 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
     if (L.cn_nodes > 0) {
         h->xi = h->ws + L.xi;
         h->cn_a = (double *)(h->ws + L.cn_a);
-        h->cn_b = (double *)(h->ws + L.cn_b);
         h->cn_tw = (double *)(h->ws + L.cn_tw);
     }
     long long off = 0, node_off = 0, xi_off = 0, tw_off = 0;
@@ -639,15 +637,16 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
         return LB_EDEVICE;
     }
     if (e == hipSuccess && !h->cn_reps.empty()) {
-        int maxline = 0;
+        int max_nx = 0, max_cp = 0;
         for (int r : h->cn_reps) {
             const RepDesc &d = h->reps[r];
-            maxline = std::max(maxline, std::max(d.nx, d.ny));
+            max_nx = std::max(max_nx, d.nx);
+            max_cp = std::max(max_cp, cn_col_points(d.nx, d.ny));
             double *tw = h->cn_tw + 2 * d.tw_off;
             if (e == hipSuccess) e = launch_twiddles(tw, d.nx, h->stream);
             if (e == hipSuccess) e = launch_twiddles(tw + 2 * (d.nx / 2), d.ny, h->stream);
         }
-        if (e == hipSuccess) e = set_fft_lds_limit(maxline);
+        if (e == hipSuccess) e = set_fft_lds_limit(max_nx, max_cp);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) {
             delete h;

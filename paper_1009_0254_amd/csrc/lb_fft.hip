@@ -10,7 +10,6 @@
 
 namespace lbf {
 
-constexpr int FFT_THREADS = 256;
 
 __global__ void k_twiddles(double2 *tw, int n)
 {
@@ -28,138 +27,149 @@ __global__ void k_fill(double *p, long long n, double v)
         p[k] = v;
 }
 
-// [rows][cols] -> [cols][rows], 32x32 tiles through LDS
-__global__ void __launch_bounds__(256) k_transpose(const double2 *__restrict__ in, double2 *__restrict__ out, int rows,
-                                                   int cols)
-{
-    __shared__ double2 tile[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    for (int j = ty; j < 32; j += 8) {
-        const int r = by + j, c = bx + tx;
-        if (r < rows && c < cols) tile[j][tx] = in[(long long)r * cols + c];
-    }
-    __syncthreads();
-    for (int j = ty; j < 32; j += 8) {
-        const int c = bx + j, r = by + tx;
-        if (r < rows && c < cols) out[(long long)c * rows + r] = tile[tx][j];
-    }
-}
-
 // ------------------------------------------------------------------ correlated noise
-// Sec. IV (last paragraph): for each step, white fields w4, w9 -> z = w4 + i w9 ->
-// Z = FFT(z) -> Y(k) = a(k) Z(k) + b(k) conj(Z(-k)) -> xi4 + i xi9 = IFFT(Y) / n, with
-// a = (L44 + L99 + i L94)/2, b = (L44 - L99 + i L94)/2 and L the lower Cholesky factor of
-// the (4,9) block of Xi(k) (eq. noise-yeo) at the homogeneous state.  Since
-// Z + conj(Z(-k)) = 2 W4 and Z - conj(Z(-k)) = 2i W9, Y = L44 W4 + i (L94 W4 + L99 W9).
+// Sec. IV (last paragraph): the noise is built in Fourier space and transformed back once
+// per step.  At every lattice k, xi(k) = L(k) nu(k) with L the lower Cholesky factor of the
+// (4,9) block of Xi(k) (eq. noise-yeo at the homogeneous state; modes 5..8 do not depend on
+// k and stay per node in the step kernel) and nu(k) unit Gaussians with nu(-k) = conj nu(k):
+// complex (g0 + i g1)/sqrt2, (g2 + i g3)/sqrt2 where k != -k, real g0, g1 where k = -k.  The
+// pair k, -k uses the Philox block of the member with the smaller index ky nx + kx (counter
+// (index, replica | 2^31, t)); the other member takes the conjugate.  Both real fields go
+// back in one complex transform: xi_4 + i xi_9 = n^-1/2 sum_k exp(-i k.r) (xi_4(k) + i xi_9(k)).
 
-__global__ void k_cn_white(double2 *__restrict__ z, const RepDesc *__restrict__ reps, int rep_index,
-                           const unsigned long long *__restrict__ tdev, int toff)
-{
-    const RepDesc &d = reps[rep_index];
-    const long long n = (long long)d.nx * d.ny;
-    const unsigned long long t = tdev[0] + (unsigned long long)toff;
-    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
-        double nu[6];
-        normals6<double>((uint32_t)k, d.rep_id | 0x80000000u, t, d.seed_lo, d.seed_hi, nu);
-        z[k] = make_double2(nu[0], nu[1]);
-    }
-}
+constexpr int CN_THREADS = 1024;
+constexpr int CN_COL_POINTS = 4096;   // points per column block when columns are short
 
-// transform every line of length L (lines are contiguous) in place
-template <bool INV>
-__global__ void __launch_bounds__(FFT_THREADS) k_fft_lines(double2 *__restrict__ data, int L, int logL,
-                                                           const double2 *__restrict__ tw)
+int cn_threads(int points) { return points >= 4096 ? 1024 : 256; }
+
+// columns per column block: adjacent x, up to CN_COL_POINTS points (one column if longer)
+int cn_cols_per_block(int nx, int ny) { return ny >= CN_COL_POINTS ? 1 : (CN_COL_POINTS / ny < nx ? CN_COL_POINTS / ny : nx); }
+
+// rows: generate xi(k) of row ky, transform along kx, store the row [ky][x] to A
+template <typename R>
+__global__ void __launch_bounds__(CN_THREADS) k_cn_rows(double2 *__restrict__ A, const RepDesc *__restrict__ reps,
+                                                        int rep_index, const double2 *__restrict__ twx,
+                                                        const unsigned long long *__restrict__ tdev, int toff)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ TwCache T;
     double2 *X = reinterpret_cast<double2 *>(smem_raw);
-    double2 *line = data + (long long)blockIdx.x * L;
-    tw_cache_load(T, tw, L);
-    for (int i = threadIdx.x; i < L; i += blockDim.x) X[bitrev((unsigned)i, logL)] = line[i];
-    __syncthreads();
-    fft_lds<INV>(X, L, logL, 1, T, L);
-    for (int i = threadIdx.x; i < L; i += blockDim.x) line[i] = X[i];
-}
-
-// A, B in the transposed layout [kx][ky]
-__global__ void k_cn_combine(const double2 *__restrict__ A, double2 *__restrict__ B, const RepDesc *__restrict__ reps,
-                             int rep_index)
-{
     const RepDesc &d = reps[rep_index];
     const Consts<double> &c = d.cd;
-    const int nx = d.nx, ny = d.ny;
-    const long long n = (long long)nx * ny;
-    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
-        const int kx = (int)(k / ny), ky = (int)(k - (long long)kx * ny);
-        const int mx = (nx - kx) & (nx - 1), my = (ny - ky) & (ny - 1);
-        const double2 Z = A[k], Zm = A[(long long)mx * ny + my];
+    const int nx = d.nx, ny = d.ny, ky = blockIdx.x;
+    const unsigned long long t = tdev[0] + (unsigned long long)toff;
+    tw_cache_load(T, twx, nx);
+    const int my = (ny - ky) & (ny - 1);
+    const double cy = cospi(2.0 * ky / ny);
+    const double pre = c.kT3 * c.rho0;
+    const double rs = 0.70710678118654752440;   // 1/sqrt(2)
+    for (int kx = threadIdx.x; kx < nx; kx += blockDim.x) {
+        const int mx = (nx - kx) & (nx - 1);
+        const unsigned idx = (unsigned)ky * nx + kx, midx = (unsigned)my * nx + mx;
+        R g[6];
+        normals6<R>(idx < midx ? idx : midx, d.rep_id | 0x80000000u, t, d.seed_lo, d.seed_hi, g);
+        double n4r, n4i, n9r, n9i;
+        if (idx == midx) {
+            n4r = (double)g[0];
+            n9r = (double)g[1];
+            n4i = n9i = 0.0;
+        } else {
+            const double sg = idx < midx ? 1.0 : -1.0;
+            n4r = rs * (double)g[0];
+            n4i = sg * rs * (double)g[1];
+            n9r = rs * (double)g[2];
+            n9i = sg * rs * (double)g[3];
+        }
         // minus the App. B Laplacian symbol, and c_s^2(k) = c_s^2 + rho0 kappa k^2
-        const double cx = cospi(2.0 * kx / nx), cy = cospi(2.0 * ky / ny);
+        const double cx = cospi(2.0 * kx / nx);
         const double k2 = -3.0 * ((4.0 / 9.0) * (cx + cy) + (2.0 / 9.0) * cx * cy - 10.0 / 9.0);
         const double cs2k = c.cs2_0 + c.rho0 * c.kappa * k2;
-        const double pre = c.kT3 * c.rho0;
         const double x44 = pre * c.k44 * (2.0 - 3.0 * cs2k);
         const double x49 = pre * c.k49 * (cs2k - 1.0 / 3.0);
         const double x99 = pre * c.k99 * (1.25 - 0.75 * cs2k);
         const double l44 = sqrt(fmax(x44, 0.0));
         const double l94 = l44 > 0 ? x49 / l44 : 0.0;
         const double l99 = sqrt(fmax(x99 - l94 * l94, 0.0));
-        const double ar = 0.5 * (l44 + l99), br = 0.5 * (l44 - l99), ai = 0.5 * l94;
-        // Y = (ar + i ai) Z + (br + i ai) conj(Zm)
-        const double yr = ar * Z.x - ai * Z.y + br * Zm.x + ai * Zm.y;
-        const double yi = ar * Z.y + ai * Z.x - br * Zm.y + ai * Zm.x;
-        B[k] = make_double2(yr, yi);
+        // Z = xi_4(k) + i xi_9(k), xi_4 = l44 nu_4, xi_9 = l94 nu_4 + l99 nu_9
+        const double x4r = l44 * n4r, x4i = l44 * n4i;
+        const double x9r = l94 * n4r + l99 * n9r, x9i = l94 * n4i + l99 * n9i;
+        X[bitrev((unsigned)kx, d.lognx)] = make_double2(x4r - x9i, x4i + x9r);
     }
+    __syncthreads();
+    fft_lds<false>(X, nx, d.lognx, 1, T, nx);
+    double2 *row = A + (long long)ky * nx;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) row[x] = X[x];
 }
 
+// columns: transform C adjacent columns of A along ky, scale by n^-1/2, store xi_4, xi_9
 template <typename S>
-__global__ void k_cn_store(const double2 *__restrict__ A, S *__restrict__ xi, long long n, double inv_n)
+__global__ void __launch_bounds__(CN_THREADS) k_cn_cols(const double2 *__restrict__ A, S *__restrict__ xi,
+                                                        const RepDesc *__restrict__ reps, int rep_index, int cpb,
+                                                        const double2 *__restrict__ twy)
 {
-    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
-        const double2 v = A[k];
-        xi[2 * k] = (S)(v.x * inv_n);
-        xi[2 * k + 1] = (S)(v.y * inv_n);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ TwCache T;
+    double2 *X = reinterpret_cast<double2 *>(smem_raw);
+    const RepDesc &d = reps[rep_index];
+    const int nx = d.nx, ny = d.ny;
+    const long long lb = xcd_logical((nx + cpb - 1) / cpb);
+    if (lb < 0) return;
+    const int x0 = (int)lb * cpb, C = min(cpb, nx - x0);
+    tw_cache_load(T, twy, ny);
+    const int tot = C * ny;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int y = e / C, cc = e - y * C;
+        X[cc * ny + bitrev((unsigned)y, d.logny)] = A[(long long)y * nx + x0 + cc];
+    }
+    __syncthreads();
+    fft_lds<false>(X, ny, d.logny, C, T, ny);
+    const double s = rsqrt((double)nx * (double)ny);
+    S *out = xi + 2 * d.xi_off;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int y = e / C, cc = e - y * C;
+        const double2 v = X[cc * ny + y];
+        const long long o = 2 * ((long long)y * nx + x0 + cc);
+        out[o] = (S)(v.x * s);
+        out[o + 1] = (S)(v.y * s);
     }
 }
 
-hipError_t set_fft_lds_limit(int max_line)
+hipError_t set_fft_lds_limit(int max_nx, int max_col_points)
 {
-    const int bytes = (int)sizeof(double2) * max_line;
-    hipError_t e = hipFuncSetAttribute((const void *)k_fft_lines<false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const int rows = (int)sizeof(double2) * max_nx, cols = (int)sizeof(double2) * max_col_points;
+    hipError_t e = hipFuncSetAttribute((const void *)k_cn_rows<double>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_fft_lines<true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        e = hipFuncSetAttribute((const void *)k_cn_rows<float>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_cn_cols<double>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_cn_cols<float>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
     return e;
 }
 
+int cn_col_points(int nx, int ny) { return cn_cols_per_block(nx, ny) * ny; }
+
 hipError_t launch_correlated_noise(int precision, const RepDesc *d_reps, const RepDesc &h_rep, int rep_index,
-                                   double *work_a, double *work_b, const double *tw_base, void *xi_base,
+                                   double *work, const double *tw_base, void *xi_base,
                                    const unsigned long long *tdev, int toff, hipStream_t s)
 {
     const int nx = h_rep.nx, ny = h_rep.ny;
-    const long long n = (long long)nx * ny;
     const double2 *twx = (const double2 *)tw_base + h_rep.tw_off;
     const double2 *twy = twx + nx / 2;
-    double2 *A = (double2 *)work_a, *B = (double2 *)work_b;
-    long long g = (n + 255) / 256;
-    if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_cn_white, dim3((unsigned)g), dim3(256), 0, s, A, d_reps, rep_index, tdev, toff);
-    // forward along x (rows of [ny][nx]), then along y in the transposed layout [nx][ny]
-    hipLaunchKernelGGL(k_fft_lines<false>, dim3(ny), dim3(FFT_THREADS), sizeof(double2) * nx, s, A, nx, h_rep.lognx, twx);
-    hipLaunchKernelGGL(k_transpose, dim3((nx + 31) / 32, (ny + 31) / 32), dim3(256), 0, s, (const double2 *)A, B, ny, nx);
-    hipLaunchKernelGGL(k_fft_lines<false>, dim3(nx), dim3(FFT_THREADS), sizeof(double2) * ny, s, B, ny, h_rep.logny, twy);
-    hipLaunchKernelGGL(k_cn_combine, dim3((unsigned)g), dim3(256), 0, s, (const double2 *)B, A, d_reps, rep_index);
-    // inverse along y, back to [ny][nx], inverse along x
-    hipLaunchKernelGGL(k_fft_lines<true>, dim3(nx), dim3(FFT_THREADS), sizeof(double2) * ny, s, A, ny, h_rep.logny, twy);
-    hipLaunchKernelGGL(k_transpose, dim3((ny + 31) / 32, (nx + 31) / 32), dim3(256), 0, s, (const double2 *)A, B, nx, ny);
-    hipLaunchKernelGGL(k_fft_lines<true>, dim3(ny), dim3(FFT_THREADS), sizeof(double2) * nx, s, B, nx, h_rep.lognx, twx);
-    const double inv_n = 1.0 / (double)n;
-    if (precision == 0)
-        hipLaunchKernelGGL(k_cn_store<double>, dim3((unsigned)g), dim3(256), 0, s, (const double2 *)B,
-                           (double *)xi_base + 2 * h_rep.xi_off, n, inv_n);
-    else
-        hipLaunchKernelGGL(k_cn_store<float>, dim3((unsigned)g), dim3(256), 0, s, (const double2 *)B,
-                           (float *)xi_base + 2 * h_rep.xi_off, n, inv_n);
+    double2 *A = (double2 *)work;
+    const int cpb = cn_cols_per_block(nx, ny);
+    const unsigned ncb = (unsigned)((nx + cpb - 1) / cpb);
+    if (precision == 0) {
+        hipLaunchKernelGGL(k_cn_rows<double>, dim3(ny), dim3(cn_threads(nx)), sizeof(double2) * nx, s, A, d_reps,
+                           rep_index, twx, tdev, toff);
+        hipLaunchKernelGGL(k_cn_cols<double>, dim3(xcd_grid(ncb)), dim3(cn_threads(cpb * ny)), sizeof(double2) * cpb * ny, s,
+                           (const double2 *)A, (double *)xi_base, d_reps, rep_index, cpb, twy);
+    } else {
+        hipLaunchKernelGGL(k_cn_rows<float>, dim3(ny), dim3(cn_threads(nx)), sizeof(double2) * nx, s, A, d_reps,
+                           rep_index, twx, tdev, toff);
+        hipLaunchKernelGGL(k_cn_cols<float>, dim3(xcd_grid(ncb)), dim3(cn_threads(cpb * ny)), sizeof(double2) * cpb * ny, s,
+                           (const double2 *)A, (float *)xi_base, d_reps, rep_index, cpb, twy);
+    }
     return hipGetLastError();
 }
 

@@ -17,6 +17,17 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
+// Workgroups are dealt to the 8 XCDs round robin; give each XCD a contiguous range of
+// logical indices so that neighbouring rows / columns share its L2.  Returns -1 for the
+// padding workgroups of the last range (launch xcd_grid(total) workgroups).
+__device__ __forceinline__ long long xcd_logical(long long total)
+{
+    const long long g = blockIdx.x, per = (total + 7) >> 3;
+    const long long l = (g & 7) * per + (g >> 3);
+    return l < total ? l : -1;
+}
+inline unsigned xcd_grid(long long total) { return (unsigned)(((total + 7) >> 3) << 3); }
+
 constexpr int TW_LO = 64, TW_HI = 128;   // N <= 2 * 64 * 128 = 16384
 
 struct TwCache {

@@ -116,11 +116,14 @@ hipError_t launch_philox(uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uin
 
 // twiddles exp(-2 pi i j / n), j < n/2, as (re, im) pairs (lb_fft.hip)
 hipError_t launch_twiddles(double *tw, int n, hipStream_t s);
-// correlated noise of one replica for step time tdev[0] + toff: fills its xi plane
+// correlated noise of one replica for step time tdev[0] + toff: fills its xi plane, using
+// `work` (nx ny complex doubles) as scratch
 hipError_t launch_correlated_noise(int precision, const RepDesc *d_reps, const RepDesc &h_rep, int rep_index,
-                                   double *work_a, double *work_b, const double *tw_base, void *xi_base,
+                                   double *work, const double *tw_base, void *xi_base,
                                    const unsigned long long *tdev, int toff, hipStream_t s);
-hipError_t set_fft_lds_limit(int max_line);
+// LDS limits of the correlated-noise kernels: widest row, most column points per block
+hipError_t set_fft_lds_limit(int max_nx, int max_col_points);
+int cn_col_points(int nx, int ny);
 
 // structure factor (lb_sk.hip).  Replicas are sampled together: every pass covers a range
 // [r0, r1) of replicas with one launch per kernel, whatever their sizes.

@@ -51,16 +51,6 @@ template <int F> __device__ __forceinline__ int sk_find(const SkRep *__restrict_
     return lo;
 }
 
-// Workgroups are dealt to the 8 XCDs round robin; give each XCD a contiguous range of
-// logical indices so that neighbouring rows / columns share its L2.  Returns -1 for the
-// padding workgroups of the last range.
-__device__ __forceinline__ long long xcd_logical(long long total)
-{
-    const long long g = blockIdx.x, per = (total + 7) >> 3;
-    const long long l = (g & 7) * per + (g >> 3);
-    return l < total ? l : -1;
-}
-
 // the nine stored values that the pull of node (x, y) reads (pull_node without the shift)
 template <typename S>
 __device__ __forceinline__ void load_pull(const S *__restrict__ P, int nx, int ny, int x, int y, S v[9])
@@ -318,8 +308,6 @@ __global__ void k_sk_read(const double *__restrict__ acc, double *__restrict__ o
         out[k] = acc[a * per + kx * ny + ky] * inv_ns;
     }
 }
-
-unsigned xcd_grid(long long total) { return (unsigned)(((total + 7) >> 3) << 3); }
 
 hipError_t launch_rows(int precision, const SkLaunch &a, int a_first, int a_count, hipStream_t s)
 {
