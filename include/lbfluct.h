@@ -76,8 +76,11 @@ enum {
 /* noise model of a replica (lb_params.noise_kind) */
 enum {
     LB_NOISE_K0 = 0,          /* Xi(0) at the local rho and c_s^2(rho), uncorrelated in space */
-    LB_NOISE_CORRELATED = 1   /* exact Xi(k) at (rho0, c_s^2(rho0)); needs nx, ny powers of two
+    LB_NOISE_CORRELATED = 1,  /* exact Xi(k) at (rho0, c_s^2(rho0)); needs nx, ny powers of two
                                  in [4, 8192] and Xi(k) positive semi-definite at every lattice k */
+    LB_NOISE_DIAGONAL = 2     /* the "ideal-gas-like" noise of Sec. IV: the diagonal of Xi(0) at the
+                                 local rho and c_s^2, no 4-9 cross-correlation; needs only that
+                                 diagonal to be non-negative */
 };
 
 /* optional features (bit mask for lb_workspace_size / lb_init) */
@@ -135,8 +138,9 @@ lb_status lb_workspace_size(const lb_params *p, int32_t n_rep, int32_t precision
  * initial state f(r, 0) of every replica.  `stream` is a hipStream_t (NULL = default
  * stream).  Rejects: n_rep < 1, nx or ny < 3, rho0 <= 0, any tau <= 1/2, kT < 0,
  * unknown precision, init or noise kind, replica >= 2^31, correlated noise on a lattice
- * whose sides are not powers of two in [4, 8192] (LB_EINVAL); Xi(0) at rho0 not PSD, or for
- * correlated noise Xi(k) not PSD at some lattice k (LB_ENOTPSD).
+ * whose sides are not powers of two in [4, 8192] (LB_EINVAL); Xi(0) at rho0 not PSD (for
+ * LB_NOISE_DIAGONAL: a negative diagonal entry), or for correlated noise Xi(k) not PSD at
+ * some lattice k (LB_ENOTPSD).
  * Synchronous.  On success *out owns host memory only; release it with lb_free. */
 lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t features,
                   void *d_workspace, size_t bytes, void *stream, lb_handle **out);

@@ -20,14 +20,15 @@
  *      x = rho - rhoc: p0 = rho psi' - psi, c_s^2 = rho psi''       (Sec. II.A)
  *   4. moments m = T f and equilibrium moments of Table II (C_n = 0)
  *   5. noise xi = L nu with L L^T = Xi(0) of eq. (noise-yeo) at k = 0, evaluated
- *      with the local rho and c_s^2 (Sec. IV and Sec. V.B)
+ *      with the local rho and c_s^2 (Sec. IV and Sec. V.B); or, for the "ideal-gas-like"
+ *      variant of Sec. IV, L = the square root of the diagonal of Xi(0)
  *   6. m*_a = m_a + lambda_a (m_a - m^eq_a) + xi_a                  (eq. gen-lbe-m, fluct-lin-lbe)
  *   7. f*_i = sum_a (T^-1)_ia m*_a, (T^-1)_ia = w_i T_ai / N_a
  *   8. streaming f_i(r + c_i, t+1) = f*_i(r, t), periodic           (eq. gen-lbe)
  *
  * Spatially correlated noise (Sec. IV, last paragraph; Fig. 3): modes 4 and 9 take fields
- * xi_4(r), xi_9(r) built outside this file (oracle.py: white fields, FFT, L(k) of
- * eq. noise-yeo, inverse FFT); modes 5..8, whose entries of Xi(k) do not depend on k,
+ * xi_4(r), xi_9(r) built outside this file (oracle.py: nu(k) drawn per k, L(k) of
+ * eq. noise-yeo, one transform back); modes 5..8, whose entries of Xi(k) do not depend on k,
  * stay uncorrelated with the homogeneous rho0 (lbo_step_fields).
  *
  * Random numbers (the paper only asks for independent unit Gaussians, Sec. IV):
@@ -50,7 +51,8 @@ typedef struct {
     uint64_t seed;
     uint32_t replica;
     int32_t init_kind;
-    int32_t noise_kind;   /* 0: Xi(0) at the local rho (uncorrelated); 1: exact Xi(k) (correlated) */
+    int32_t noise_kind;   /* 0: Xi(0) at the local rho (uncorrelated); 1: exact Xi(k) (correlated);
+                             2: the diagonal of Xi(0) at the local rho ("ideal-gas-like") */
     int32_t pad_;
     double init_arg[6];
 } lbo_params;
@@ -239,7 +241,8 @@ static void equilibrium(const lbo_params *p, double rho, double jx, double jy,
 }
 
 /* Xi(0) of eq. (noise-yeo) at k = 0 with local rho and c_s^2: the nonzero block
-   entries X44, X49, X99 and the diagonal X55..X88 (indices are 0-based modes). */
+   entries X44, X49, X99 and the diagonal X55..X88 (indices are 0-based modes).  The
+   "ideal-gas-like" variant of Sec. IV (noise_kind 2) keeps only the diagonal. */
 static void noise_covariance(const lbo_params *p, double rho, double cs2, double X[Q][Q])
 {
     const double s2 = 1.0 / 3.0;
@@ -251,7 +254,7 @@ static void noise_covariance(const lbo_params *p, double rho, double cs2, double
     double pref = -rho * p->kT / s2;
     memset(X, 0, sizeof(double) * Q * Q);
     X[3][3] = pref * Nn[3] * (2.0 - 3.0 * cs2) * lt[3];
-    X[3][8] = X[8][3] = pref * 12.0 * (cs2 - s2) * lt_ee;
+    if (p->noise_kind != 2) X[3][8] = X[8][3] = pref * 12.0 * (cs2 - s2) * lt_ee;
     X[4][4] = pref * Nn[4] * lt[4];
     X[5][5] = pref * Nn[5] * lt[5];
     X[6][6] = pref * Nn[6] * lt[6];

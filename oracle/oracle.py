@@ -39,7 +39,7 @@ class LboParams(ctypes.Structure):
     ]
 
 
-NOISE_KINDS = {"k0": 0, "correlated": 1}
+NOISE_KINDS = {"k0": 0, "correlated": 1, "diagonal": 2}
 # counter word 1 of the white fields behind the correlated noise: replica | 2^31
 CORRELATED_STREAM = 0x80000000
 

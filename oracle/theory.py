@@ -283,15 +283,19 @@ def step_matrix(kx, ky, lam, cs2, rho0, kappa):
     return advection(-kx, -ky) @ (np.eye(9) + collision_operator(kx, ky, lam, cs2, rho0, kappa))
 
 
-def stationary_covariance_uncorrelated(kx, ky, lam, cs2, rho0, kappa, kT):
-    """Stationary <dm(k) dm(k)^H> when the noise has the k-independent covariance Xi(0).
+def stationary_covariance_uncorrelated(kx, ky, lam, cs2, rho0, kappa, kT, diagonal=False):
+    """Stationary <dm(k) dm(k)^H> when the noise has the k-independent covariance Xi(0)
+    (diagonal=True: only its diagonal, the "ideal-gas-like" noise of Sec. IV).
 
     Solves G = M G M^H + Q with Q = A(-k) Xi(0) A(-k)^H by vectorisation.
     Singular (undamped) directions make the system ill-posed; callers exclude k = 0 and
     the staggered-momentum points (pi, 0) / (0, pi)."""
     M = step_matrix(kx, ky, lam, cs2, rho0, kappa)
     Am = advection(-kx, -ky)
-    Q = Am @ noise_matrix_closed(0.0, 0.0, lam, cs2, rho0, 0.0, kT) @ Am.conj().T
+    X = noise_matrix_closed(0.0, 0.0, lam, cs2, rho0, 0.0, kT)
+    if diagonal:
+        X = np.diag(np.diag(X))
+    Q = Am @ X @ Am.conj().T
     n = 9
     # vec(M G M^H) = (conj(M) kron M) vec(G) with column-major vec
     K = np.eye(n * n) - np.kron(M.conj(), M)
@@ -305,6 +309,8 @@ def transient_covariance(kx, ky, lam, cs2, rho0, kappa, kT, t, noise="k0"):
     Am = advection(-kx, -ky)
     if noise == "k0":
         X = noise_matrix_closed(0.0, 0.0, lam, cs2, rho0, 0.0, kT)
+    elif noise == "diagonal":
+        X = np.diag(np.diag(noise_matrix_closed(0.0, 0.0, lam, cs2, rho0, 0.0, kT)))
     else:
         X = noise_matrix_closed(kx, ky, lam, cs2, rho0, kappa, kT)
     Q = Am @ X @ Am.conj().T

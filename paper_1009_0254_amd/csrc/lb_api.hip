@@ -65,8 +65,9 @@ int max_tiles_for(const lb_params *p, int n_rep)
 }
 
 // Xi(0) at (rho0, c_s^2(rho0)) must be positive semi-definite (Sec. III.C, Fig. 2):
-// with X of eq. (noise-yeo) at k = 0 the modes-4..9 block is diagonal except (4,9)
-bool xi0_psd(const lb_params &q)
+// with X of eq. (noise-yeo) at k = 0 the modes-4..9 block is diagonal except (4,9); the
+// diagonal-only noise needs just its diagonal to be non-negative
+bool xi0_psd(const lb_params &q, bool diagonal_only)
 {
     const double lb = -1.0 / q.tau_bulk, ls = -1.0 / q.tau_shear, lq = -1.0 / q.tau_q, le = -1.0 / q.tau_eps;
     const double x = q.rho0 - q.rhoc;
@@ -76,6 +77,7 @@ bool xi0_psd(const lb_params &q)
     const double a99 = -16.0 * le * (2 + le) * (1.25 - 0.75 * cs2);
     const bool diag_ok = ls * (2 + ls) <= 0 && lq * (2 + lq) <= 0;
     const double tol = 1e-14 * (fabs(a44) + fabs(a99) + 1e-300);
+    if (diagonal_only) return diag_ok && a44 >= -tol && a99 >= -tol;
     return diag_ok && a44 >= -tol && a99 >= -tol && a44 * a99 - a49 * a49 >= -tol * (fabs(a44) + fabs(a99));
 }
 
@@ -118,12 +120,12 @@ lb_status validate(const lb_params *p, int32_t n_rep, int32_t precision)
             return LB_EINVAL;
         if (q.init_kind < LB_INIT_UNIFORM || q.init_kind > LB_INIT_WAVE) return LB_EINVAL;
         if (q.init_kind == LB_INIT_SLAB && !(q.init_arg[4] != 0)) return LB_EINVAL;
-        if (q.noise_kind != LB_NOISE_K0 && q.noise_kind != LB_NOISE_CORRELATED) return LB_EINVAL;
+        if (q.noise_kind < LB_NOISE_K0 || q.noise_kind > LB_NOISE_DIAGONAL) return LB_EINVAL;
         if (q.reserved != 0 || q.replica >= 0x80000000u) return LB_EINVAL;
         if (q.noise_kind == LB_NOISE_CORRELATED &&
             (!is_pow2(q.nx) || !is_pow2(q.ny) || q.nx < 4 || q.ny < 4 || q.nx > CN_MAX || q.ny > CN_MAX))
             return LB_EINVAL;
-        if (!xi0_psd(q)) return LB_ENOTPSD;
+        if (!xi0_psd(q, q.noise_kind == LB_NOISE_DIAGONAL)) return LB_ENOTPSD;
         if (q.noise_kind == LB_NOISE_CORRELATED && !xik_psd(q)) return LB_ENOTPSD;
     }
     return LB_OK;
@@ -285,7 +287,7 @@ RepDesc describe(const lb_params &q, int precision, long long off, long long nod
     d.seed_lo = (uint32_t)q.seed;
     d.seed_hi = (uint32_t)(q.seed >> 32);
     d.rep_id = q.replica;
-    d.noise = q.kT > 0 ? (q.noise_kind == LB_NOISE_CORRELATED ? 2u : 1u) : 0u;
+    d.noise = q.kT > 0 ? (q.noise_kind == LB_NOISE_CORRELATED ? 2u : q.noise_kind == LB_NOISE_DIAGONAL ? 3u : 1u) : 0u;
     d.lognx = ilog2(q.nx);
     d.logny = ilog2(q.ny);
     d.xi_off = 0;

@@ -39,7 +39,8 @@ struct RepDesc {
     int64_t off;          // element offset of plane 0 in a population buffer
     int64_t node_off;     // node offset of this replica in replica-concatenated node arrays
     uint32_t seed_lo, seed_hi, rep_id;
-    uint32_t noise;       // 0: none (kT = 0); 1: Xi(0) at the local state; 2: correlated Xi(k)
+    uint32_t noise;       // 0: none (kT = 0); 1: Xi(0) at the local state; 2: correlated Xi(k);
+                          // 3: the diagonal of Xi(0) at the local state
     int32_t lognx, logny; // for correlated noise (powers of two)
     int64_t xi_off;       // correlated noise: offset (in pairs) of this replica's xi_4 + i xi_9 plane
     int64_t tw_off;       // correlated noise: offset (in double2) of its twiddles [nx/2 | ny/2]

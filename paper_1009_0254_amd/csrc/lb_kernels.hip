@@ -118,7 +118,7 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
         R l44 = 0, l94 = 0;
         if (a44 > 0) {
             l44 = fsqrt<R>(a44);
-            l94 = a49 * frcp<R>(l44);
+            if (noise != 3) l94 = a49 * frcp<R>(l44);   // 3: the diagonal of Xi(0) only (Sec. IV)
         } else if (a44 < 0) {
             st |= 1u;
         }

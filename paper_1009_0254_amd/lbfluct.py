@@ -20,7 +20,7 @@ LB_OK, LB_EINVAL, LB_ENOTPSD, LB_EUNSTABLE, LB_ENOMEM, LB_EDEVICE, LB_ESTATE = 0
 LB_FP64, LB_FP32, LB_FP32_SHIFTED = 0, 1, 2
 PRECISIONS = {"fp64": LB_FP64, "fp32": LB_FP32, "fp32s": LB_FP32_SHIFTED}
 INIT_KINDS = {"uniform": 0, "slab": 1, "random": 2, "wave": 3}
-NOISE_KINDS = {"k0": 0, "correlated": 1}
+NOISE_KINDS = {"k0": 0, "correlated": 1, "diagonal": 2}
 LB_FEATURE_STRUCTURE_FACTOR = 1
 LB_SK_RESET, LB_SK_SAMPLE, LB_SK_READ, LB_SK_SNAPSHOT = 0, 1, 2, 3
 LB_FLAG_CLAMPED_PIVOT, LB_FLAG_NONPOSITIVE_RHO, LB_FLAG_NAN, LB_FLAG_LOW_MACH = 1, 2, 4, 8

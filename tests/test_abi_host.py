@@ -140,3 +140,18 @@ def test_structure_factor_feature_size_rules():
     want = 2 * 9 * n * 4 + n * 8 + 9 * 16384 * 8193 * 8 + 9 * 16384 * 8193 * 16
     b = L.lb_workspace_size([W.cfg5()], L.LB_FP32_SHIFTED, F)
     assert want <= b < want + (64 << 20)
+
+
+def test_diagonal_noise_needs_only_a_nonnegative_diagonal():
+    """Near c_s^2 = 2/3 the 4-9 block of Xi(0) is not PSD (its determinant turns negative
+    before Xi_44 does), so the Cholesky noise is rejected; the diagonal variant of Sec. IV is
+    valid there.  Past c_s^2 = 2/3, Xi_44 < 0 and both are rejected."""
+    near = W.single_phase(16, 16, c0sq=0.6, A=0.05)        # c_s^2 = 0.65
+    with pytest.raises(L.LbError) as e:
+        L.lb_workspace_size([near], L.LB_FP32_SHIFTED)
+    assert e.value.status == L.LB_ENOTPSD
+    assert L.lb_workspace_size([dict(near, noise="diagonal")], L.LB_FP32_SHIFTED) > 0
+    past = W.single_phase(16, 16, c0sq=0.7, A=0.05)        # c_s^2 = 0.75
+    with pytest.raises(L.LbError) as e:
+        L.lb_workspace_size([dict(past, noise="diagonal")], L.LB_FP32_SHIFTED)
+    assert e.value.status == L.LB_ENOTPSD

@@ -184,6 +184,7 @@ NOISY = [
     ("tiny", lambda: W.single_phase(3, 5, kT=1e-5, seed=2), 300),
     ("slab", lambda: W.slab(64, 128, kT=1e-6, seed=5), 500),
     ("e4", lambda: W.e4(64, 64, kT=1e-7), 500),
+    ("diagonal", lambda: W.single_phase(64, 48, kT=1e-5, seed=9, c0sq=0.0, A=0.05, noise="diagonal"), 400),
 ]
 
 
@@ -495,7 +496,7 @@ def test_full_size_8192_sampled_parity():
 # ------------------------------------------------------------------ equipartition on the GPU
 
 
-def _unc_targets(cfg, kxv, kyv, mask):
+def _unc_targets(cfg, kxv, kyv, mask, diagonal=False):
     lam = th.relaxation_rates(cfg["tau_bulk"], cfg["tau_shear"], cfg["tau_q"], cfg["tau_eps"])
     cs2 = th.sound_speed2(cfg["rho0"], cfg["c0sq"], cfg["A"], cfg["B"], cfg["rhoc"])
     Gu = np.full((9, len(kyv), len(kxv)), np.nan)
@@ -505,20 +506,25 @@ def _unc_targets(cfg, kxv, kyv, mask):
             if not mask[iy, ix]:
                 continue
             Gu[:, iy, ix] = np.diag(th.stationary_covariance_uncorrelated(
-                kx, ky, lam, cs2, cfg["rho0"], cfg["kappa"], cfg["kT"])).real
+                kx, ky, lam, cs2, cfg["rho0"], cfg["kappa"], cfg["kT"], diagonal)).real
             Gp[:, iy, ix] = np.diag(th.equilibrium_correlations(kx, ky, cs2, cfg["rho0"], cfg["kappa"], cfg["kT"])).real
     return Gu, Gp
 
 
+@pytest.mark.parametrize("noise", ["k0", "diagonal"])
 @pytest.mark.parametrize("precision", [2, 0])
-def test_equipartition_all_modes_within_one_percent(precision):
+def test_equipartition_all_modes_within_one_percent(precision, noise):
     """S_a(k) of all nine modes from the GPU's FP64 S(k) accumulators equals the stationary
-    covariance of the linear model driven by Xi(0) (the noise the path uses) within 1% on
-    average over k, and within sampling error per |k| shell; the paper's G(k) (eq. g-mat-yeo)
-    is matched at small k."""
+    covariance of the linear model driven by the noise the path uses (Xi(0), or its diagonal
+    for the "ideal-gas-like" variant of Sec. IV at c_s^2 = 0.05, where Xi_49 is large) within 1%
+    on average over k, and within sampling error per |k| shell; the paper's G(k)
+    (eq. g-mat-yeo) is matched at small k."""
     L = _L()
     nx = ny = 64
-    cfg = W.single_phase(nx, ny, kT=1e-5, seed=101 + precision)
+    if noise == "k0":
+        cfg = W.single_phase(nx, ny, kT=1e-5, seed=101 + precision)
+    else:
+        cfg = W.single_phase(nx, ny, kT=1e-5, seed=201 + precision, c0sq=0.0, A=0.05, noise="diagonal")
     lat = L.Lattice(cfg, precision=precision, structure_factor=True)
     lat.step(3000)
     lat.lb_structure_factor(L.LB_SK_RESET, 0)
@@ -538,7 +544,7 @@ def test_equipartition_all_modes_within_one_percent(precision):
     mask[0, 0] = False
     undamped = ((np.abs(KX) == np.pi) & (KY == 0)) | ((KX == 0) & (np.abs(KY) == np.pi))
     mask &= ~undamped
-    Gu, Gp = _unc_targets(cfg, kxv, kyv, mask)
+    Gu, Gp = _unc_targets(cfg, kxv, kyv, mask, noise == "diagonal")
     ratio = S / Gu
     kmag = np.sqrt(KX ** 2 + KY ** 2)
     means = []
@@ -555,9 +561,14 @@ def test_equipartition_all_modes_within_one_percent(precision):
             assert abs(ratio[a][sel].mean() - 1) < 0.05, (a, lo, ratio[a][sel].mean())
     small = mask & (kmag < 0.35)
     pg = [(S[a][small] / Gp[a][small]).mean() for a in range(9)]
-    say("equipartition precision", precision, "mean S/G_unc", np.round(means, 4), "S/G (|k|<0.35)", np.round(pg, 3))
+    say("equipartition", noise, "precision", precision, "mean S/G_unc", np.round(means, 4), "S/G (|k|<0.35)", np.round(pg, 3))
+    # the paper's G(k) at small k: the exact target meets it within 1% (deterministic) ...
     for a in range(3):
-        assert abs(pg[a] - 1) < 0.03
+        assert np.abs(Gu[a][small] / Gp[a][small] - 1).max() < 0.01
+    # ... and so does the data, within sampling error: ~18 independent k with |k| < 0.35
+    # whose transverse momentum decorrelates over 250-1000 steps give ~2.5% (one sigma)
+    for a in range(3):
+        assert abs(pg[a] - 1) < 0.08
 
 
 # ------------------------------------------------------------------ spatially correlated noise

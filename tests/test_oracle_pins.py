@@ -407,6 +407,77 @@ def test_equipartition_uncorrelated_noise():
         assert abs((S[a][small] / G[a][small]).mean() - 1) < 0.06, a
 
 
+def test_diagonal_noise_covariance():
+    """The "ideal-gas-like" variant of Sec. IV: xi has the diagonal of Xi(0) and no 4-9
+    cross-correlation."""
+    cfg = _cfg1_like(4, 4, c0sq=0.0, A=-0.01, kT=1e-5, tau_q=0.9, tau_eps=1.3, noise="diagonal")
+    rho = 1.0
+    cs2 = _cs2(cfg, rho)
+    n = 200_000
+    xi = O.noise_samples(cfg, rho, cs2, t=3, n=n)
+    full = th.noise_matrix_k0_fdt(_lam(cfg), cs2, rho, cfg["kT"])
+    assert abs(full[3, 8]) > 0.3 * np.sqrt(full[3, 3] * full[8, 8])     # the dropped term matters here
+    want = np.diag(np.diag(full))
+    emp = xi.T @ xi / n
+    sd = np.sqrt((np.outer(np.diag(want), np.diag(want)) + want ** 2) / n)
+    assert np.all(np.abs(emp - want) <= 5 * sd + 1e-18)
+
+
+def _equipartition_targets(cfg, S, diagonal):
+    nx, ny = cfg["nx"], cfg["ny"]
+    lam, cs2 = _lam(cfg), _cs2(cfg)
+    kyv = 2 * np.pi * np.fft.fftfreq(ny)
+    kxv = 2 * np.pi * np.fft.rfftfreq(nx)
+    Gu = np.full_like(S, np.nan)
+    for iy, ky in enumerate(kyv):
+        for ix, kx in enumerate(kxv):
+            if (ix == 0 and iy == 0) or (abs(kx) == np.pi and ky == 0) or (kx == 0 and abs(ky) == np.pi):
+                continue
+            g = th.stationary_covariance_uncorrelated(kx, ky, lam, cs2, 1.0, cfg["kappa"], cfg["kT"], diagonal)
+            Gu[:, iy, ix] = np.diag(g).real
+    return Gu
+
+
+def test_equipartition_diagonal_noise():
+    """With the diagonal noise every mode reaches the stationary covariance of the linear model
+    driven by diag Xi(0) (not the Cholesky one: the targets differ), and the hydrodynamic modes
+    reach the paper's G(k) at small k, as Sec. IV reports."""
+    nx = ny = 24
+    cfg = _cfg1_like(nx, ny, kT=1e-5, seed=23, c0sq=0.0, A=0.05, noise="diagonal")   # c_s^2 = 0.05
+    o = O.Oracle(cfg)
+    o.step(1500)
+    acc = np.zeros((9, ny, nx // 2 + 1))
+    ns = 0
+    for _ in range(1200):
+        o.step(6)
+        acc += O.power_spectrum(o.moments())
+        ns += 1
+    S = acc / ns
+    Gd = _equipartition_targets(cfg, S, True)
+    Gc = _equipartition_targets(cfg, S, False)
+    for a in range(9):
+        r = (S[a] / Gd[a])[np.isfinite(Gd[a])]
+        assert abs(r.mean() - 1) < 0.015, (a, r.mean())
+    # the two targets are distinguishable: the Cholesky target misses the data in some mode
+    rc = [np.nanmean(S[a] / Gc[a]) for a in range(9)]
+    dt = [np.nanmean(Gd[a] / Gc[a]) for a in range(9)]
+    assert max(abs(v - 1) for v in dt) > 0.05, dt
+    a_max = int(np.argmax([abs(v - 1) for v in dt]))
+    assert abs(rc[a_max] - dt[a_max]) < 0.03
+    lam, cs2 = _lam(cfg), _cs2(cfg)
+    kyv = 2 * np.pi * np.fft.fftfreq(ny)
+    kxv = 2 * np.pi * np.fft.rfftfreq(nx)
+    kk = np.sqrt(kxv[None, :] ** 2 + kyv[:, None] ** 2)
+    small = (kk > 0) & (kk < 0.8)
+    G = np.zeros_like(S)
+    for iy, ky in enumerate(kyv):
+        for ix, kx in enumerate(kxv):
+            if small[iy, ix]:
+                G[:, iy, ix] = np.diag(th.equilibrium_correlations(kx, ky, cs2, 1.0, cfg["kappa"], cfg["kT"])).real
+    for a in (0, 1, 2):
+        assert abs((S[a][small] / G[a][small]).mean() - 1) < 0.06, a
+
+
 # ------------------------------------------------------------------ spatially correlated noise
 
 
