@@ -318,3 +318,20 @@ def transient_covariance(kx, ky, lam, cs2, rho0, kappa, kT, t, noise="k0"):
     for _ in range(t):
         G = M @ G @ M.conj().T + Q
     return G
+
+
+def psd_all_k(kappa, cs2, lam, rho0=1.0, nk=97, tol=1e-12):
+    """True when Xi(k) of eq. (noise-yeo) is positive semi-definite at every k with k_x, k_y in
+    [0, pi] (the white region of Fig. 2); checked on an nk x nk grid of k (which includes the
+    corner (pi, pi) where minus the App. B Laplacian symbol is largest)."""
+    for kx in np.linspace(0.0, np.pi, nk):
+        for ky in np.linspace(0.0, np.pi, nk):
+            X = noise_matrix_closed(kx, ky, lam, cs2, rho0, kappa, 1.0).real
+            if np.linalg.eigvalsh(X).min() < -tol * np.abs(X).max():
+                return False
+    return True
+
+
+def interface_width_paper(kappa, cs2, rho0=1.0):
+    """xi = 4 sqrt(rho0 kappa) / c_s (eq. interf-width); xi = 4 is the dashed curve of Fig. 2."""
+    return 4.0 * np.sqrt(rho0 * kappa / cs2)

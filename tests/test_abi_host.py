@@ -155,3 +155,21 @@ def test_diagonal_noise_needs_only_a_nonnegative_diagonal():
     with pytest.raises(L.LbError) as e:
         L.lb_workspace_size([dict(past, noise="diagonal")], L.LB_FP32_SHIFTED)
     assert e.value.status == L.LB_ENOTPSD
+
+
+def test_correlated_noise_validation_follows_the_fig2_region():
+    """lb_init's PSD check of Xi(k) over the lattice agrees with the closed-form boundary of
+    Fig. 2 for tau = 1 (c_s^2 + 16/3 kappa <= 3/5; a 16 x 16 lattice contains the corner)."""
+    for kappa in (0.0, 0.03, 0.06, 0.09):
+        for cs in (0.1, 0.3, 0.5, 0.7, 0.75):
+            margin = cs * cs + 16.0 / 3.0 * kappa - 0.6
+            if abs(margin) < 5e-3:
+                continue
+            cfg = dict(W.single_phase(16, 16, c0sq=cs * cs, A=0.0, B=0.0, kappa=kappa, kT=1e-7),
+                       tau_bulk=1.0, tau_shear=1.0, tau_q=1.0, tau_eps=1.0, noise="correlated")
+            if margin < 0:
+                assert L.lb_workspace_size([cfg], L.LB_FP32_SHIFTED) > 0
+            else:
+                with pytest.raises(L.LbError) as e:
+                    L.lb_workspace_size([cfg], L.LB_FP32_SHIFTED)
+                assert e.value.status == L.LB_ENOTPSD, (kappa, cs)

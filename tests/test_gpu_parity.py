@@ -571,6 +571,56 @@ def test_equipartition_all_modes_within_one_percent(precision, noise):
         assert abs(pg[a] - 1) < 0.08
 
 
+def _shell_means(R, kmag, mask, width=0.25):
+    out = []
+    for lo in np.arange(0.0, 4.5, width):
+        sel = mask & (kmag >= lo) & (kmag < lo + width)
+        if sel.sum():
+            out.append((lo, R[:, sel].mean(axis=1)))
+    return out
+
+
+@pytest.mark.parametrize("precision", [2, 0])
+def test_uncorrelated_noise_run_of_sec_VA_at_128(precision):
+    """The uncorrelated-noise equilibration run of Sec. V.A (128^2, kappa = 0.03, c_s = 0.156,
+    tau = 1, T = 1e-7, S(k) sampled inside lb_step).  S_a(k) follows the exact linear target
+    G_unc (the stationary covariance driven by Xi(0)) within 1% per mode.  Against the paper's
+    G(k): negligible errors for |k| < 0.8 (as the text says), momentum within its 10% at every
+    |k|; the density error, however, grows to ~18% near |k| = 3 and ~28% at the zone corner,
+    as G_unc / G predicts, where the text reports < 10%."""
+    L = _L()
+    nx = ny = 128
+    cfg = W.e4(nx, ny, kT=1e-7, seed=61 + precision)
+    lat = L.Lattice(cfg, precision=precision, structure_factor=True)
+    lat.lb_set_sampling(10, 15000)
+    lat.step(15000 + 30000)
+    S, ns = lat.lb_structure_factor(L.LB_SK_READ, 0)
+    S = S.cpu().numpy()
+    lat.close()
+    assert ns == 3001
+    kyv = 2 * np.pi * np.fft.fftfreq(ny)
+    kxv = 2 * np.pi * np.fft.rfftfreq(nx)
+    KX, KY = np.meshgrid(kxv, kyv)
+    mask = np.ones_like(KX, dtype=bool)
+    mask[0, 0] = False
+    mask &= ~(((np.abs(KX) == np.pi) & (KY == 0)) | ((KX == 0) & (np.abs(KY) == np.pi)))
+    Gu, Gp = _unc_targets(cfg, kxv, kyv, mask)
+    kmag = np.sqrt(KX ** 2 + KY ** 2)
+    for a in range(9):
+        r = (S[a] / Gu[a])[mask]
+        assert abs(r.mean() - 1) < 0.01, (a, r.mean())
+    shells = _shell_means(S / Gp, kmag, mask)
+    for lo, m in shells:
+        say("E4 |k| >= %.2f S/G" % lo, np.round(m, 3))
+    hydro = mask & (kmag < 0.8)
+    assert np.abs(Gu[:, hydro] / Gp[:, hydro] - 1).max() < 0.025
+    assert np.abs((S / Gp)[:, hydro].mean(axis=1) - 1).max() < 0.04
+    for lo, m in shells:
+        assert m[1] < 1.10 and m[2] < 1.10, (lo, m[1], m[2])
+    dens = {round(lo, 2): m[0] for lo, m in shells}
+    assert dens[3.0] > 1.12 and dens[4.25] > 1.2
+
+
 # ------------------------------------------------------------------ spatially correlated noise
 
 
@@ -606,19 +656,21 @@ def test_correlated_and_uncorrelated_replicas_in_one_handle():
     lat.close()
 
 
+@pytest.mark.parametrize("nx", [64, 128])
 @pytest.mark.parametrize("precision", [2, 0])
-def test_correlated_noise_equilibrates_to_paper_G_at_all_k(precision):
+def test_correlated_noise_equilibrates_to_paper_G_at_all_k(precision, nx):
     """The paper's headline (Sec. V.A, Fig. 3 parameters): with the exact Xi(k) all nine modes
     reach G(k) of eq. (g-mat-yeo) at every k -- here within 1% on average and 5% per shell."""
     L = _L()
-    nx = ny = 64
-    cfg = W.e3(nx, ny, kT=1e-6, seed=77 + precision)
+    ny = nx
+    cfg = W.e3(nx, ny, kT=1e-6, seed=77 + precision + nx)
     lat = L.Lattice(cfg, precision=precision, structure_factor=True)
-    lat.step(2000)
+    # burn-in and sampling interval grow with the slowest relaxation time, ~ (nx / 2 pi)^2 / nu
+    burn, every, nsamp = (2000, 8, 3000) if nx == 64 else (8000, 20, 3000)
+    lat.step(burn)
     lat.lb_structure_factor(L.LB_SK_RESET, 0)
-    nsamp = 3000
     for _ in range(nsamp):
-        lat.step(8)
+        lat.step(every)
         lat.lb_structure_factor(L.LB_SK_SAMPLE, 0)
     S, ns = lat.lb_structure_factor(L.LB_SK_READ, 0)
     S = S.cpu().numpy()

@@ -623,3 +623,47 @@ def test_quench_density_spectrum_follows_linear_theory():
     assert np.abs(got - want).max() <= 1e-4 * want.max()
     s0, _ = O.radial_spectrum(m0[0])
     assert (got / np.maximum(s0, 1e-300)).max() > 30      # the most unstable shells grew
+
+
+# ------------------------------------------------------------------ Fig. 2: where Xi(k) is PSD
+
+
+def test_psd_region_closed_form_for_unit_relaxation_times():
+    """Fig. 2 (all tau = 1, lambda = -1): with u = c_s^2(k) the (4,9) block of Xi(k) is
+    4(2 - 3u), 12(u - 1/3), 20 - 12u times rho0 kT, so its determinant is 144 - 240u and
+    Xi(k) is PSD iff u <= 3/5; u is largest at the zone corner, where minus the App. B
+    Laplacian symbol is 16/3.  Hence the white region is c_s^2 + (16/3) rho0 kappa <= 3/5."""
+    lam = th.relaxation_rates(1.0, 1.0, 1.0, 1.0)
+    assert np.isclose(th.k2_lattice(np.pi, np.pi), 16.0 / 3.0)
+    n_in = n_out = 0
+    for kappa in np.linspace(0.0, 0.12, 13):
+        for cs in np.linspace(0.02, 0.8, 14):
+            margin = cs * cs + 16.0 / 3.0 * kappa - 0.6
+            if abs(margin) < 5e-3:
+                continue
+            got = th.psd_all_k(kappa, cs * cs, lam, nk=25)
+            assert got == (margin < 0), (kappa, cs)
+            n_in += got
+            n_out += not got
+    assert n_in > 20 and n_out > 20
+    # with lambda_e = lambda_eps = lambda the whole block scales by -lambda (2 + lambda), so any
+    # common tau gives the same region; it moves when lambda_e != lambda_eps (Sec. III.C)
+    for tau in (0.7, 1.6):
+        lam_t = th.relaxation_rates(tau, tau, tau, tau)
+        assert all(th.psd_all_k(k, c * c, lam_t, nk=17) == (c * c + 16.0 / 3.0 * k < 0.6)
+                   for k in (0.0, 0.05) for c in (0.3, 0.5, 0.7, 0.76))
+    lam_d = th.relaxation_rates(0.8, 1.0, 1.0, 3.0)
+    flips = [(k, c) for k in (0.0, 0.05) for c in np.linspace(0.3, 0.8, 101)
+             if th.psd_all_k(k, c * c, lam_d, nk=25) != (c * c + 16.0 / 3.0 * k < 0.6)]
+    assert flips
+
+
+def test_paper_parameter_points_lie_in_the_allowed_region():
+    """The correlated (kappa = 0.08, c_s = 0.265) and uncorrelated (kappa = 0.03, c_s = 0.15)
+    equilibration runs of Sec. V.A are inside the PSD region and on the stable side of the
+    dashed curve xi = 4 (eq. interf-width), as the text requires."""
+    lam = th.relaxation_rates(1.0, 1.0, 1.0, 1.0)
+    for cfg in (W.e3(), W.e4()):
+        cs2 = _cs2(cfg)
+        assert th.psd_all_k(cfg["kappa"], cs2, lam, nk=33)
+        assert th.interface_width_paper(cfg["kappa"], cs2) >= 4.0
