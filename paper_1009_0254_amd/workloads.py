@@ -53,6 +53,24 @@ def slab(nx: int, ny: int, kT: float = 1e-6, seed: int = 1, **kw) -> dict:
     return d
 
 
+def capillary(nx: int = 2048, ny: int = 400, width: int = 180, kT: float = 1e-7, seed: int = 3, **kw) -> dict:
+    """The capillary-wave run of Sec. V.B: a liquid stripe of the given width parallel to x in a
+    periodic nx x ny box, rho_L = 1, rho_V = 0.5, beta = 0.04, kappa = 0.03, T = 1e-7; every
+    relaxation time 1 (the printed tau = 0.1 violates tau > 1/2 and is read as 1.0).  The
+    free energy is the paper's f0 (eq. f0-bulk): c0sq = 0, B = 4 beta, A = -beta (rho_L - rho_V)^2,
+    rhoc = (rho_L + rho_V) / 2; the walls start as tanh profiles of half-width
+    sqrt(2 kappa / beta) / (rho_L - rho_V)."""
+    beta, rl, rv, kappa = 0.04, 1.0, 0.5, 0.03
+    d = dict(rho0=1.0, rhoc=0.5 * (rl + rv), A=-beta * (rl - rv) ** 2, B=4.0 * beta, kappa=kappa, c0sq=0.0,
+             tau_bulk=1.0, tau_shear=1.0, tau_q=1.0, tau_eps=1.0, nx=nx, ny=ny, kT=kT, seed=seed)
+    w = math.sqrt(2.0 * kappa / beta) / (rl - rv)
+    y1 = (ny - width) / 2 - 0.5
+    d["init"] = "slab"
+    d["init_arg"] = [rl, rv, y1, y1 + width, w]
+    d.update(kw)
+    return d
+
+
 def spinodal(nx: int, ny: int, kT: float = 1e-6, seed: int = 1, amp: float = 0.01, **kw) -> dict:
     d = dict(_TWO, nx=nx, ny=ny, kT=kT, seed=seed, init="random", init_arg=[amp])
     d.update(kw)
