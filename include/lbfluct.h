@@ -112,7 +112,7 @@ enum {
  * beta (rho - rho_V)^2 (rho - rho_L)^2 (eq. f0-bulk) is c0sq = 0, B = 4 beta,
  * A = -beta (rho_L - rho_V)^2, rhoc = (rho_L + rho_V)/2, up to a constant. */
 typedef struct lb_params {
-    int32_t nx, ny;            /* lattice size, each >= 3; nx*ny < 2^32 */
+    int32_t nx, ny;            /* lattice size, each >= 3; nx <= 2^24; nx*ny < 2^32 */
     double rho0;               /* reference density (> 0): noise-free rest state and storage shift */
     double rhoc, A, B, kappa, c0sq;
     double tau_bulk, tau_shear, tau_q, tau_eps;  /* each > 1/2 */

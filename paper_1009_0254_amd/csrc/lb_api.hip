@@ -111,6 +111,7 @@ lb_status validate(const lb_params *p, int32_t n_rep, int32_t precision)
         const lb_params &q = p[r];
         if (q.nx < 3 || q.ny < 3) return LB_EINVAL;
         if ((long long)q.nx * q.ny >= (1ll << 32)) return LB_EINVAL;
+        if (q.nx > (1 << 24)) return LB_EINVAL;   // a row's bytes must fit a buffer descriptor's 31-bit range
         if (!(q.rho0 > 0) || !isfinite(q.rho0)) return LB_EINVAL;
         const double taus[4] = {q.tau_bulk, q.tau_shear, q.tau_q, q.tau_eps};
         for (double tau : taus)

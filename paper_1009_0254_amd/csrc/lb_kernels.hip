@@ -29,6 +29,36 @@ template <typename S> __device__ __forceinline__ void st_at(S *base, unsigned by
     __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(base) + byte_off));
 }
 
+// The fused step addresses populations through buffer resources: one per lattice row (base =
+// the row, range = its 9 nx elements), the lane's column as a 32-bit offset and the plane of
+// population i as a scalar offset, so that no per-lane 64-bit address arithmetic is spent on
+// the 18 accesses per node.  Stores carry the nontemporal cache policy.
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *row, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(row), 0, (int)bytes, 0x00020000);
+}
+template <typename S> __device__ __forceinline__ S bld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <> __device__ __forceinline__ float bld<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+constexpr int CPOL_NT = 2;
+template <typename S> __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, S v);
+template <> __device__ __forceinline__ void bst<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, CPOL_NT);
+}
+template <> __device__ __forceinline__ void bst<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)voff, (int)soff, CPOL_NT);
+}
+
 template <typename R> __device__ __forceinline__ R frcp(R v);
 template <> __device__ __forceinline__ float frcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ __forceinline__ double frcp<double>(double v) { return 1.0 / v; }
@@ -177,6 +207,8 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
     const Consts<R> &c = consts<R>(d);
     const unsigned nx = (unsigned)d.nx, ny = (unsigned)d.ny;
     const unsigned long long pitch = 9ull * nx;   // elements per lattice row
+    constexpr unsigned ESZ = sizeof(S);
+    const unsigned rowb = 9u * nx * ESZ, nxb = nx * ESZ;   // bytes per row and per population plane
     const unsigned long long t = tdev[0] + (unsigned long long)toff;
     const S *__restrict__ P = fin + d.off;
     S *__restrict__ Qo = fout + d.off;
@@ -203,19 +235,27 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
 
     // pulled populations f_i(x, yy) = f*_i(x - c_i, yy - c_iy): uniform row pointers, lane
     // byte offsets
-    auto pull = [&](int yy, unsigned o0, unsigned ol, unsigned orr, R f[Q]) {
-        const S *rm = P + (unsigned long long)wrapy(yy - 1) * pitch;
-        const S *r0 = P + (unsigned long long)wrapy(yy) * pitch;
-        const S *rp = P + (unsigned long long)wrapy(yy + 1) * pitch;
-        f[0] = (R)ld_at(r0, o0);
-        f[1] = (R)ld_at(r0 + nx, ol);
-        f[2] = (R)ld_at(rm + 2 * nx, o0);
-        f[3] = (R)ld_at(r0 + 3 * nx, orr);
-        f[4] = (R)ld_at(rp + 4 * nx, o0);
-        f[5] = (R)ld_at(rm + 5 * nx, ol);
-        f[6] = (R)ld_at(rm + 6 * nx, orr);
-        f[7] = (R)ld_at(rp + 7 * nx, orr);
-        f[8] = (R)ld_at(rp + 8 * nx, ol);
+    // the three stored rows that the pull of row yy reads (descriptors built outside any
+    // divergent branch, so that they stay in scalar registers)
+    struct Rows {
+        __amdgpu_buffer_rsrc_t m, z, p;
+    };
+    auto rows_of = [&](int yy) -> Rows {
+        return Rows{row_rsrc(P + (unsigned long long)wrapy(yy - 1) * pitch, rowb),
+                    row_rsrc(P + (unsigned long long)wrapy(yy) * pitch, rowb),
+                    row_rsrc(P + (unsigned long long)wrapy(yy + 1) * pitch, rowb)};
+    };
+    auto pull = [&](const Rows &rr, unsigned o0, unsigned ol, unsigned orr, R f[Q]) {
+        const auto Rm = rr.m, R0 = rr.z, Rp = rr.p;
+        f[0] = (R)bld<S>(R0, o0, 0);
+        f[1] = (R)bld<S>(R0, ol, nxb);
+        f[2] = (R)bld<S>(Rm, o0, 2 * nxb);
+        f[3] = (R)bld<S>(R0, orr, 3 * nxb);
+        f[4] = (R)bld<S>(Rp, o0, 4 * nxb);
+        f[5] = (R)bld<S>(Rm, ol, 5 * nxb);
+        f[6] = (R)bld<S>(Rm, orr, 6 * nxb);
+        f[7] = (R)bld<S>(Rp, orr, 7 * nxb);
+        f[8] = (R)bld<S>(Rp, ol, 8 * nxb);
     };
     // density deviation of pulled (stored) values
     auto dens = [&](const R f[Q]) {
@@ -250,38 +290,41 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
         }
         st |= collide<R, CN>(cur, lap, gx, gy, c, d.noise, (unsigned)y * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi,
                          xi4, xi9);
+        const auto W = row_rsrc(Qo + (unsigned long long)(unsigned)y * pitch, rowb);
         if (store) {
-            S *__restrict__ o = Qo + (unsigned long long)(unsigned)y * pitch;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) st_at(o + (unsigned long long)i * nx, c0, (S)(PLAIN ? cur[i] + c.sub[i] : cur[i]));
+            for (int i = 0; i < Q; ++i) bst<S>(W, c0, i * nxb, (S)(PLAIN ? cur[i] + c.sub[i] : cur[i]));
         }
     };
 
     R fa[Q], fb[Q], hv[Q];
     // prologue: densities of rows y0-1 and y0 (own and halo columns), populations of row y0
-    pull(y0 - 1, c0, cm, cp, fb);
+    const Rows ra = rows_of(y0 - 1), rb = rows_of(y0);
+    pull(ra, c0, cm, cp, fb);
     ring[((unsigned)(y0 - 1) & 3u) * WL + tid + 1] = dens(fb);
     if (halo) {
-        pull(y0 - 1, hc0, hcm, hcp, hv);
+        pull(ra, hc0, hcm, hcp, hv);
         ring[((unsigned)(y0 - 1) & 3u) * WL + hslot] = dens(hv);
-        pull(y0, hc0, hcm, hcp, hv);
+        pull(rb, hc0, hcm, hcp, hv);
         ring[((unsigned)y0 & 3u) * WL + hslot] = dens(hv);
     }
-    pull(y0, c0, cm, cp, fa);
+    pull(rb, c0, cm, cp, fa);
     ring[((unsigned)y0 & 3u) * WL + tid + 1] = dens(fa);
 
     // row y+1 is already in flight when row y starts; row y+2 is issued before the barrier
     // and lands while row y collides
     R fcq[Q];
-    pull(y0 + 1, c0, cm, cp, fb);
-    if (halo) pull(y0 + 1, hc0, hcm, hcp, hv);
+    const Rows rc = rows_of(y0 + 1);
+    pull(rc, c0, cm, cp, fb);
+    if (halo) pull(rc, hc0, hcm, hcp, hv);
     auto row = [&](int y, R cur[Q], R nxt[Q], R nn[Q]) {
         const unsigned sp = ((unsigned)(y + 1) & 3u) * WL;
         ring[sp + tid + 1] = dens(nxt);
         if (halo) ring[sp + hslot] = dens(hv);
         if (y + 1 < y1) {
-            pull(y + 2, c0, cm, cp, nn);
-            if (halo) pull(y + 2, hc0, hcm, hcp, hv);
+            const Rows rn = rows_of(y + 2);
+            pull(rn, c0, cm, cp, nn);
+            if (halo) pull(rn, hc0, hcm, hcp, hv);
         }
         __syncthreads();
         finish_row(y, cur, sp);
