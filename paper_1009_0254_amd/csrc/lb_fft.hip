@@ -45,15 +45,18 @@ int cn_threads(int points) { return points >= 4096 ? 1024 : 256; }
 // columns per column block: adjacent x, up to CN_COL_POINTS points (one column if longer)
 int cn_cols_per_block(int nx, int ny) { return ny >= CN_COL_POINTS ? 1 : (CN_COL_POINTS / ny < nx ? CN_COL_POINTS / ny : nx); }
 
-// rows: generate xi(k) of row ky, transform along kx, store the row [ky][x] to A
+// rows: generate xi(k) of row ky, transform along kx, store the row [ky][x] to A.  The
+// transforms run in the precision R of the storage: double for FP64 storage (parity with
+// FP64 references), float otherwise (the step consumes the fields in float).
 template <typename R>
-__global__ void __launch_bounds__(CN_THREADS) k_cn_rows(double2 *__restrict__ A, const RepDesc *__restrict__ reps,
+__global__ void __launch_bounds__(CN_THREADS) k_cn_rows(void *__restrict__ Av, const RepDesc *__restrict__ reps,
                                                         int rep_index, const double2 *__restrict__ twx,
                                                         const unsigned long long *__restrict__ tdev, int toff)
 {
+    typedef typename V2<R>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ TwCache T;
-    double2 *X = reinterpret_cast<double2 *>(smem_raw);
+    __shared__ TwCacheT<R> T;
+    C *X = reinterpret_cast<C *>(smem_raw);
     const RepDesc &d = reps[rep_index];
     const Consts<double> &c = d.cd;
     const int nx = d.nx, ny = d.ny, ky = blockIdx.x;
@@ -93,44 +96,46 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_rows(double2 *__restrict__ A,
         // Z = xi_4(k) + i xi_9(k), xi_4 = l44 nu_4, xi_9 = l94 nu_4 + l99 nu_9
         const double x4r = l44 * n4r, x4i = l44 * n4i;
         const double x9r = l94 * n4r + l99 * n9r, x9i = l94 * n4i + l99 * n9i;
-        X[bitrev((unsigned)kx, d.lognx)] = make_double2(x4r - x9i, x4i + x9r);
+        X[bitrev((unsigned)kx, d.lognx)] = mk2((R)(x4r - x9i), (R)(x4i + x9r));
     }
     __syncthreads();
-    fft_lds<false>(X, nx, d.lognx, 1, T, nx);
-    double2 *row = A + (long long)ky * nx;
+    fft_lds<false, R>(X, nx, d.lognx, 1, T, nx);
+    C *row = reinterpret_cast<C *>(Av) + (long long)ky * nx;
     for (int x = threadIdx.x; x < nx; x += blockDim.x) row[x] = X[x];
 }
 
 // columns: transform C adjacent columns of A along ky, scale by n^-1/2, store xi_4, xi_9
 template <typename S>
-__global__ void __launch_bounds__(CN_THREADS) k_cn_cols(const double2 *__restrict__ A, S *__restrict__ xi,
+__global__ void __launch_bounds__(CN_THREADS) k_cn_cols(const void *__restrict__ Av, S *__restrict__ xi,
                                                         const RepDesc *__restrict__ reps, int rep_index, int cpb,
                                                         const double2 *__restrict__ twy)
 {
+    typedef typename V2<S>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ TwCache T;
-    double2 *X = reinterpret_cast<double2 *>(smem_raw);
+    __shared__ TwCacheT<S> T;
+    C *X = reinterpret_cast<C *>(smem_raw);
+    const C *A = reinterpret_cast<const C *>(Av);
     const RepDesc &d = reps[rep_index];
     const int nx = d.nx, ny = d.ny;
     const long long lb = xcd_logical((nx + cpb - 1) / cpb);
     if (lb < 0) return;
-    const int x0 = (int)lb * cpb, C = min(cpb, nx - x0);
+    const int x0 = (int)lb * cpb, Cn = min(cpb, nx - x0);
     tw_cache_load(T, twy, ny);
-    const int tot = C * ny;
+    const int tot = Cn * ny;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int y = e / C, cc = e - y * C;
+        const int y = e / Cn, cc = e - y * Cn;
         X[cc * ny + bitrev((unsigned)y, d.logny)] = A[(long long)y * nx + x0 + cc];
     }
     __syncthreads();
-    fft_lds<false>(X, ny, d.logny, C, T, ny);
-    const double s = rsqrt((double)nx * (double)ny);
+    fft_lds<false, S>(X, ny, d.logny, Cn, T, ny);
+    const S s = (S)rsqrt((double)nx * (double)ny);
     S *out = xi + 2 * d.xi_off;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int y = e / C, cc = e - y * C;
-        const double2 v = X[cc * ny + y];
+        const int y = e / Cn, cc = e - y * Cn;
+        const C v = X[cc * ny + y];
         const long long o = 2 * ((long long)y * nx + x0 + cc);
-        out[o] = (S)(v.x * s);
-        out[o + 1] = (S)(v.y * s);
+        out[o] = v.x * s;
+        out[o + 1] = v.y * s;
     }
 }
 
@@ -156,19 +161,18 @@ hipError_t launch_correlated_noise(int precision, const RepDesc *d_reps, const R
     const int nx = h_rep.nx, ny = h_rep.ny;
     const double2 *twx = (const double2 *)tw_base + h_rep.tw_off;
     const double2 *twy = twx + nx / 2;
-    double2 *A = (double2 *)work;
     const int cpb = cn_cols_per_block(nx, ny);
-    const unsigned ncb = (unsigned)((nx + cpb - 1) / cpb);
+    const unsigned ncb = xcd_grid((nx + cpb - 1) / cpb);
     if (precision == 0) {
-        hipLaunchKernelGGL(k_cn_rows<double>, dim3(ny), dim3(cn_threads(nx)), sizeof(double2) * nx, s, A, d_reps,
-                           rep_index, twx, tdev, toff);
-        hipLaunchKernelGGL(k_cn_cols<double>, dim3(xcd_grid(ncb)), dim3(cn_threads(cpb * ny)), sizeof(double2) * cpb * ny, s,
-                           (const double2 *)A, (double *)xi_base, d_reps, rep_index, cpb, twy);
+        hipLaunchKernelGGL(k_cn_rows<double>, dim3(ny), dim3(cn_threads(nx)), sizeof(double2) * nx, s, (void *)work,
+                           d_reps, rep_index, twx, tdev, toff);
+        hipLaunchKernelGGL(k_cn_cols<double>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(double2) * cpb * ny, s,
+                           (const void *)work, (double *)xi_base, d_reps, rep_index, cpb, twy);
     } else {
-        hipLaunchKernelGGL(k_cn_rows<float>, dim3(ny), dim3(cn_threads(nx)), sizeof(double2) * nx, s, A, d_reps,
-                           rep_index, twx, tdev, toff);
-        hipLaunchKernelGGL(k_cn_cols<float>, dim3(xcd_grid(ncb)), dim3(cn_threads(cpb * ny)), sizeof(double2) * cpb * ny, s,
-                           (const double2 *)A, (float *)xi_base, d_reps, rep_index, cpb, twy);
+        hipLaunchKernelGGL(k_cn_rows<float>, dim3(ny), dim3(cn_threads(nx)), sizeof(float2) * nx, s, (void *)work,
+                           d_reps, rep_index, twx, tdev, toff);
+        hipLaunchKernelGGL(k_cn_cols<float>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(float2) * cpb * ny, s,
+                           (const void *)work, (float *)xi_base, d_reps, rep_index, cpb, twy);
     }
     return hipGetLastError();
 }

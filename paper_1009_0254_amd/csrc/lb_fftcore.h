@@ -10,12 +10,19 @@ namespace lbf {
 
 __device__ __forceinline__ unsigned bitrev(unsigned v, int bits) { return bits > 0 ? __brev(v) >> (32 - bits) : 0u; }
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+// complex pairs of float or double
+template <typename T> struct V2;
+template <> struct V2<float> { typedef float2 type; };
+template <> struct V2<double> { typedef double2 type; };
+
+__device__ __forceinline__ double2 mk2(double x, double y) { return make_double2(x, y); }
+__device__ __forceinline__ float2 mk2(float x, float y) { return make_float2(x, y); }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b)
 {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return mk2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return mk2(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return mk2(a.x - b.x, a.y - b.y); }
 
 // Workgroups are dealt to the 8 XCDs round robin; give each XCD a contiguous range of
 // logical indices so that neighbouring rows / columns share its L2.  Returns -1 for the
@@ -30,20 +37,34 @@ inline unsigned xcd_grid(long long total) { return (unsigned)(((total + 7) >> 3)
 
 constexpr int TW_LO = 64, TW_HI = 128;   // N <= 2 * 64 * 128 = 16384
 
-struct TwCache {
-    double2 lo[TW_LO];
-    double2 hi[TW_HI];
+template <typename T> struct TwCacheT {
+    typedef typename V2<T>::type C;
+    C lo[TW_LO];
+    C hi[TW_HI];
 };
+typedef TwCacheT<double> TwCache;
 
-// fill T from tw (N/2 entries); the caller's next barrier publishes it
-__device__ __forceinline__ void tw_cache_load(TwCache &T, const double2 *__restrict__ tw, int N)
+// fill T from tw (N/2 FP64 entries, rounded to T's precision); the caller's next barrier
+// publishes it
+template <typename T>
+__device__ __forceinline__ void tw_cache_load(TwCacheT<T> &Tc, const double2 *__restrict__ tw, int N)
 {
     const int half = N >> 1, nhi = N >= 2 * TW_LO ? N / (2 * TW_LO) : 1;
-    for (int i = threadIdx.x; i < TW_LO; i += blockDim.x) T.lo[i] = i < half ? tw[i] : make_double2(1.0, 0.0);
-    for (int h = threadIdx.x; h < nhi; h += blockDim.x) T.hi[h] = tw[h * TW_LO];
+    for (int i = threadIdx.x; i < TW_LO; i += blockDim.x) {
+        const double2 w = i < half ? tw[i] : make_double2(1.0, 0.0);
+        Tc.lo[i] = mk2((T)w.x, (T)w.y);
+    }
+    for (int h = threadIdx.x; h < nhi; h += blockDim.x) {
+        const double2 w = tw[h * TW_LO];
+        Tc.hi[h] = mk2((T)w.x, (T)w.y);
+    }
 }
 
-__device__ __forceinline__ double2 twiddle(const TwCache &T, int t) { return cmul(T.hi[t >> 6], T.lo[t & (TW_LO - 1)]); }
+template <typename T>
+__device__ __forceinline__ typename V2<T>::type twiddle(const TwCacheT<T> &Tc, int t)
+{
+    return cmul(Tc.hi[t >> 6], Tc.lo[t & (TW_LO - 1)]);
+}
 
 // `count` independent in-place decimation-in-time transforms of length n = 2^logn (n >= 2)
 // stored back to back in X, each already in bit-reversed order, with the twiddles of an
@@ -51,9 +72,10 @@ __device__ __forceinline__ double2 twiddle(const TwCache &T, int t) { return cmu
 // stage's odd twiddle is the first's times w_4 = -i), with one radix-2 pass when logn is
 // odd.  INV uses the conjugate twiddles exp(+2 pi i k / n) and does not scale.  Ends with
 // a barrier.
-template <bool INV>
-__device__ void fft_lds(double2 *X, int n, int logn, int count, const TwCache &T, int N)
+template <bool INV, typename T>
+__device__ void fft_lds(typename V2<T>::type *X, int n, int logn, int count, const TwCacheT<T> &Tc, int N)
 {
+    typedef typename V2<T>::type C;
     int s = 1;
     for (; s + 1 <= logn; s += 2) {
         const int lq = s - 1, q = 1 << lq;
@@ -63,17 +85,17 @@ __device__ void fft_lds(double2 *X, int n, int logn, int count, const TwCache &T
             const int g = b >> (logn - 2), bb = b & (n4 - 1);
             const int pos = bb & (q - 1);
             const int base = g * n + ((bb >> lq) << (lq + 2)) + pos;
-            double2 w1 = twiddle(T, pos * st1), w2 = twiddle(T, pos * st2);
+            C w1 = twiddle(Tc, pos * st1), w2 = twiddle(Tc, pos * st2);
             if (INV) {
                 w1.y = -w1.y;
                 w2.y = -w2.y;
             }
-            const double2 a = X[base], bv = X[base + q], c = X[base + 2 * q], d = X[base + 3 * q];
-            const double2 b1 = cmul(w1, bv), d1 = cmul(w1, d);
-            const double2 a1 = cadd(a, b1), bq = csub(a, b1), c1 = cadd(c, d1), dq = csub(c, d1);
-            const double2 c2 = cmul(w2, c1);
-            double2 d2 = cmul(w2, dq);
-            d2 = INV ? make_double2(-d2.y, d2.x) : make_double2(d2.y, -d2.x);   // times +i / -i
+            const C a = X[base], bv = X[base + q], c = X[base + 2 * q], d = X[base + 3 * q];
+            const C b1 = cmul(w1, bv), d1 = cmul(w1, d);
+            const C a1 = cadd(a, b1), bq = csub(a, b1), c1 = cadd(c, d1), dq = csub(c, d1);
+            const C c2 = cmul(w2, c1);
+            C d2 = cmul(w2, dq);
+            d2 = INV ? mk2(-d2.y, d2.x) : mk2(d2.y, -d2.x);   // times +i / -i
             X[base] = cadd(a1, c2);
             X[base + 2 * q] = csub(a1, c2);
             X[base + q] = cadd(bq, d2);
@@ -87,9 +109,9 @@ __device__ void fft_lds(double2 *X, int n, int logn, int count, const TwCache &T
             const int g = b >> (logn - 1), bb = b & (nb - 1);
             const int pos = bb & (half - 1);
             const int i0 = g * n + ((bb >> (s - 1)) << s) + pos, i1 = i0 + half;
-            double2 w = twiddle(T, pos * st);
+            C w = twiddle(Tc, pos * st);
             if (INV) w.y = -w.y;
-            const double2 u = X[i0], t = cmul(X[i1], w);
+            const C u = X[i0], t = cmul(X[i1], w);
             X[i0] = cadd(u, t);
             X[i1] = csub(u, t);
         }

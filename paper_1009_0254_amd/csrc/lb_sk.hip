@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(SK_THREADS)
             }
         }
         __syncthreads();
-        fft_lds<false>(X, M, logM, gcount * R, T, nmax);
+        fft_lds<false, double>(X, M, logM, gcount * R, T, nmax);
         // X_k = E_k + W^k O_k with E = (Z_k + conj Z_{M-k}) / 2, O = (Z_k - conj Z_{M-k}) / 2i,
         // W = exp(-2 pi i / nx), for k = 0..M (Z has period M)
         for (int idx = threadIdx.x; idx < gcount * R * nh; idx += blockDim.x) {
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(SK_THREADS)
         }
     }
     __syncthreads();
-    fft_lds<false>(X, L, logL, split == 1 ? C : 1, T, nmax);
+    fft_lds<false, double>(X, L, logL, split == 1 ? C : 1, T, nmax);
     const int tot = (split == 1 ? C : 1) * L;
     if (SNAP) {
         double *D = plane + (long long)kx0 * ny;
