@@ -673,7 +673,7 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
             q.ny = p[r].ny;
             q.lognx = ilog2(q.nx);
             q.logny = ilog2(q.ny);
-            q.split = q.ny > SK_LINE_MAX ? 2 : 1;
+            q.split = q.ny > SK_LINE_MAX / 2 ? 2 : 1;   // halves of 8192-long columns: two workgroups per CU
             q.cpb = sk_cols_per_block(q.nx, q.ny);
             q.rpb = sk_rows_per_block(q.nx, q.ny);
             const int nh = q.nx / 2 + 1;

@@ -133,7 +133,7 @@ constexpr int SK_LINE_MAX = 8192;   // longest complex line held in LDS (128 KiB
 
 struct SkRep {
     int32_t nx, ny, lognx, logny;
-    int32_t split;      // column blocks per kx: 1 if ny <= SK_LINE_MAX, else 2 (one per output parity)
+    int32_t split;      // column blocks per kx: 1 if ny <= SK_LINE_MAX / 2, else 2 (one per output parity)
     int32_t cpb;        // adjacent kx columns per column block (1 when split)
     int32_t rpb;        // rows per row block
     int32_t pad_;

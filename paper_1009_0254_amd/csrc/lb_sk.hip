@@ -12,9 +12,9 @@
 //      row hit the caches), writing mode a to slot a of the spectra, [ny][nx/2+1] each;
 //   2. columns: one workgroup per kx and mode reads its column of the row spectra in place
 //      (consecutive kx share cache lines and are kept on one XCD), transforms along y
-//      (lines longer than 8192 are split by one decimation-in-frequency stage into two
-//      half-length transforms, one per output parity) and adds |X|^2 / n to the FP64
-//      accumulators [9][nx/2+1][ny].
+//      (lines longer than 4096 are split by one decimation-in-frequency stage into two
+//      half-length transforms, one per output parity, so that two workgroups fit a CU's
+//      LDS) and adds |X|^2 / n to the FP64 accumulators [9][nx/2+1][ny].
 // The radially binned density spectrum (the isotropic average of S_rho(k), used to follow
 // density modes after a quench to c_s^2 < 0, where M(k) of eq. (lb-lang-ft) has growing
 // eigenvalues) reuses 1-3 for mode 0 of one replica and bins |rho(k)|^2 / n with integer

@@ -309,15 +309,15 @@ def fp64_spectrum_tol(n, smax):
     return 1e-10 + 8 * 2 * eps * np.log2(n) * n / np.sqrt(n * smax)
 
 
-SK_SHAPES = [(64, 32), (16384, 16), (16, 16384), (2048, 8), (4, 4)]
+SK_SHAPES = [(64, 32), (16384, 16), (16, 16384), (16, 8192), (2048, 8), (4, 4)]
 
 
 @pytest.mark.parametrize("shape", SK_SHAPES, ids=[f"{a}x{b}" for a, b in SK_SHAPES])
 @pytest.mark.parametrize("precision", [0, 2])
 def test_structure_factor_matches_oracle_fft(precision, shape):
     """All nine |m_a(k)|^2 against numpy's FFT of the oracle's moments: rows of length 16384
-    (real-to-complex split), columns of 16384 (one decimation-in-frequency stage), several
-    modes per pass (2048 wide: 8 + 1) and the smallest lattice."""
+    (real-to-complex split), columns of 8192 and 16384 (one decimation-in-frequency stage),
+    several modes per pass (2048 wide: 8 + 1) and the smallest lattice."""
     L = _L()
     nx, ny = shape
     cfg = W.single_phase(nx, ny, kT=1e-5, seed=31)
