@@ -85,7 +85,30 @@ __device__ __forceinline__ void moments9(const double g[9], double m[9])
     m[8] = 2 * g[0] - 4 * sa + 8 * sd;
 }
 
+// mode a of m = T f from the nine pulled values of one node (stored + shift, in FP64), with
+// the expression trees of moments9 for that mode only
 template <typename S>
+__device__ __forceinline__ double moment_of(int a, const S v[9], const double *sh)
+{
+    auto g = [&](int i) { return (double)v[i] + sh[i]; };
+    switch (a) {
+    case 0: return g(0) + ((g(1) + g(2)) + (g(3) + g(4))) + ((g(5) + g(6)) + (g(7) + g(8)));
+    case 1: return (g(1) - g(3)) + (g(5) - g(7)) + (g(8) - g(6));
+    case 2: return (g(2) - g(4)) + (g(5) - g(7)) - (g(8) - g(6));
+    case 3: return -2 * g(0) + ((g(1) + g(2)) + (g(3) + g(4))) + 4 * ((g(5) + g(6)) + (g(7) + g(8)));
+    case 4: return (g(1) + g(3)) - (g(2) + g(4));
+    case 5: return (g(5) + g(7)) - (g(6) + g(8));
+    case 6: return -(g(1) - g(3)) + 2 * ((g(5) - g(7)) + (g(8) - g(6)));
+    case 7: return -(g(2) - g(4)) + 2 * ((g(5) - g(7)) - (g(8) - g(6)));
+    default: return 2 * g(0) - 4 * ((g(1) + g(2)) + (g(3) + g(4))) + 8 * ((g(5) + g(6)) + (g(7) + g(8)));
+    }
+}
+
+constexpr int SK_CACHE_PAIRS = 4;   // node pairs per lane kept in registers across mode groups
+
+// CACHE: every lane's pulls (at most SK_CACHE_PAIRS pairs) are loaded once and kept in
+// registers for all mode groups; otherwise each group pulls again (the repeats hit L2/MALL)
+template <typename S, bool CACHE>
 __global__ void __launch_bounds__(SK_THREADS)
     k_sk_rows(const S *__restrict__ f, const RepDesc *__restrict__ reps, const SkRep *__restrict__ sk, int r0, int r1,
               long long row_base, long long nrows, int a_first, int a_count, int G, long long Ptot,
@@ -107,8 +130,33 @@ __global__ void __launch_bounds__(SK_THREADS)
     const int pairs = R * M;
     const S *P = f + d.off;
     const int wstride = nmax / nx;
+    S cv[CACHE ? SK_CACHE_PAIRS : 1][2][9];
+    if (CACHE) {
+#pragma unroll
+        for (int j = 0; j < SK_CACHE_PAIRS; ++j) {
+            const int e = threadIdx.x + j * (int)blockDim.x;
+            if (e < pairs) {
+                const int rr = e / M, n = e - rr * M;
+                load_pull(P, nx, ny, 2 * n, y0 + rr, cv[j][0]);
+                load_pull(P, nx, ny, 2 * n + 1, y0 + rr, cv[j][1]);
+            }
+        }
+    }
     for (int a0 = a_first; a0 < a_first + a_count; a0 += G) {
         const int gcount = min(G, a_first + a_count - a0);
+        if (CACHE) {
+#pragma unroll
+            for (int j = 0; j < SK_CACHE_PAIRS; ++j) {
+                const int e = threadIdx.x + j * (int)blockDim.x;
+                if (e < pairs) {
+                    const int rr = e / M, n = e - rr * M;
+                    const unsigned jb = bitrev((unsigned)n, logM);
+                    for (int c = 0; c < gcount; ++c)
+                        X[(c * R + rr) * M + jb] = make_double2(moment_of(a0 + c, cv[j][0], d.shift),
+                                                                moment_of(a0 + c, cv[j][1], d.shift));
+                }
+            }
+        } else
         // two pairs of nodes per lane and iteration, all 36 loads issued before use
         for (int e0 = threadIdx.x; e0 < pairs; e0 += 2 * blockDim.x) {
             const int e1 = e0 + blockDim.x < pairs ? e0 + blockDim.x : e0;
@@ -313,13 +361,22 @@ hipError_t launch_rows(int precision, const SkLaunch &a, int a_first, int a_coun
 {
     const int G = a_count < a.G ? a_count : a.G;
     const size_t lds = sizeof(double) * (size_t)G * a.lds_rows;
+    const int threads = sk_threads(a.lds_rows);
+    // FP32 pulls of every block in the range fit the lanes' registers when a block has at
+    // most SK_CACHE_PAIRS node pairs per lane (a.lds_rows nodes at most per block)
+    const bool cache = precision != 0 && a.lds_rows / 2 <= SK_CACHE_PAIRS * threads && a_count > G;
     if (precision == 0)
-        hipLaunchKernelGGL(k_sk_rows<double>, dim3(xcd_grid(a.rows)), dim3(sk_threads(a.lds_rows)), lds, s,
+        hipLaunchKernelGGL((k_sk_rows<double, false>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s,
                            (const double *)a.f,
                            a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
                            (long long)a.Ptot, (double2 *)a.spec, (const double2 *)a.tw, a.nmax);
+    else if (cache)
+        hipLaunchKernelGGL((k_sk_rows<float, true>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s,
+                           (const float *)a.f,
+                           a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
+                           (long long)a.Ptot, (double2 *)a.spec, (const double2 *)a.tw, a.nmax);
     else
-        hipLaunchKernelGGL(k_sk_rows<float>, dim3(xcd_grid(a.rows)), dim3(sk_threads(a.lds_rows)), lds, s,
+        hipLaunchKernelGGL((k_sk_rows<float, false>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s,
                            (const float *)a.f,
                            a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
                            (long long)a.Ptot, (double2 *)a.spec, (const double2 *)a.tw, a.nmax);
@@ -331,9 +388,12 @@ hipError_t launch_rows(int precision, const SkLaunch &a, int a_first, int a_coun
 hipError_t set_sk_lds_limits(int G, int max_nx, int max_col)
 {
     const int rows = (int)sizeof(double) * G * max_nx, cols = (int)sizeof(double2) * max_col;
-    hipError_t e = hipFuncSetAttribute((const void *)k_sk_rows<double>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
+    hipError_t e =
+        hipFuncSetAttribute((const void *)k_sk_rows<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_sk_rows<float>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
+        e = hipFuncSetAttribute((const void *)k_sk_rows<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_sk_rows<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_sk_cols<false>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
     if (e == hipSuccess)
