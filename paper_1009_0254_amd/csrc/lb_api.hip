@@ -306,17 +306,6 @@ RepDesc describe(const lb_params &q, int precision, long long off, long long nod
     return d;
 }
 
-// Tiles of every replica for strip width bx and rows per tile h.  Workgroup i runs on
-// XCD i mod 8, each XCD with its own L2.  Tiles that share data -- horizontal neighbours
-// share the cache lines that straddle a strip boundary (pulls from x +- 1, halo columns),
-// vertical neighbours share their boundary rows -- should run on the same XCD, while the
-// workgroups in flight should cover whole lattice rows (HBM page locality).  So each
-// replica's strips are split into 8 contiguous groups, one per XCD (replicas with fewer
-// than 8 strips go whole to the least-loaded XCD), every XCD walks its tiles in bands
-// (segment-major, then strip), and the eight per-XCD queues are interleaved so that list
-// position j * 8 + k holds the j-th tile of XCD k.
-// LBF_TILE_ORDER=rows (plain full-width bands) and =xcd (strip-major runs per XCD) select
-// the alternatives.
 lb_status hip_ok(hipError_t e) { return e == hipSuccess ? LB_OK : LB_EDEVICE; }
 
 lb_status set_tiles(lb_handle *h, int bx, double rows)

@@ -10,8 +10,9 @@
 // Loads run two rows ahead: while row y collides, the populations of row y+2 are in
 // flight (on gfx950 a workgroup barrier only waits for LDS, not for global loads).
 // Populations are row-interleaved ([y][i][x], see pop_at): a row of the lattice is one
-// contiguous block, and tiles are walked in full-width bands, so that the workgroups in
-// flight stream whole rows (HBM page locality).  Stores bypass the caches (nontemporal).
+// contiguous block.  The tile list (lb_tiles.hip) keeps neighbouring tiles on one XCD.
+// Every access goes through a buffer descriptor of its row (no per-lane 64-bit address
+// arithmetic); stores carry the nontemporal policy.
 
 #include "lb_internal.h"
 #include "lb_rng.h"

@@ -25,9 +25,17 @@ struct Bands {
 
 }  // namespace
 
-// Tile order: each replica's strips are split into 8 contiguous groups, one per XCD
-// (workgroup i runs on XCD i mod 8); each XCD walks its tiles in bands down the strips;
-// the 8 queues are interleaved.  LBF_TILE_ORDER=rows|xcd selects simpler orders.
+// Tiles of every replica for strip width bx and about h rows per tile.  Workgroup i runs on
+// XCD i mod 8, each XCD with its own L2.  Tiles that share data -- horizontal neighbours
+// share the cache lines that straddle a strip boundary (pulls from x +- 1, halo columns),
+// vertical neighbours share their boundary rows -- should run on the same XCD, while the
+// workgroups in flight should cover whole lattice rows (HBM page locality).  So each
+// replica's strips are split into 8 contiguous groups, one per XCD (replicas with fewer
+// than 8 strips go whole to the least-loaded XCD), every XCD walks its tiles in bands
+// (segment-major, then strip), and the eight per-XCD queues are interleaved so that list
+// position j * 8 + k holds the j-th tile of XCD k.
+// LBF_TILE_ORDER=rows (plain full-width bands) and =xcd (strip-major runs per XCD) select
+// the alternatives.
 std::vector<Tile> make_tiles(const std::vector<RepDesc> &reps, int bx, double h)
 {
     constexpr int X = 8;
