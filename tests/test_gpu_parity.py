@@ -760,3 +760,46 @@ def test_capillary_spectrum_sec_VB():
     for lo in (8, 16, 32, 64):
         assert abs(bands[lo] - 1) < 0.15, (lo, bands[lo])
     assert bands[512] > 1.3 and bands[1] < 0.85
+
+
+# ------------------------------------------------------------------ ensemble equipartition
+
+
+def test_ensemble_size_class_equipartition():
+    """The ensemble workload's 128^2 size class (256 replicas, kT log-uniform in [1e-6, 1e-4],
+    each with its own Philox stream): S(k) of all replicas sampled together inside lb_step;
+    the per-class mean of S_a(k) / G_unc,aa(k; kT_r) (the exact target scales with kT in the
+    linear model) is 1 within 0.5% for every mode, and the replicas agree with each other
+    (the spread of the per-replica means is the sampling error's, not a kT trend)."""
+    L = _L()
+    reps = [r for r in W.cfg4() if r["nx"] == 128]
+    assert len(reps) == 256
+    lat = L.Lattice(reps, precision="fp32s", structure_factor=True)
+    burn, every, nsamp = 16000, 20, 500
+    lat.lb_set_sampling(every, burn)
+    lat.step(burn + every * (nsamp - 1))
+    nx = ny = 128
+    kyv = 2 * np.pi * np.fft.fftfreq(ny)
+    kxv = 2 * np.pi * np.fft.rfftfreq(nx)
+    KX, KY = np.meshgrid(kxv, kyv)
+    mask = np.ones_like(KX, dtype=bool)
+    mask[0, 0] = False
+    mask &= ~(((np.abs(KX) == np.pi) & (KY == 0)) | ((KX == 0) & (np.abs(KY) == np.pi)))
+    unit = dict(reps[0], kT=1.0)
+    Gu, _ = _unc_targets(unit, kxv, kyv, mask)
+    per = np.zeros((len(reps), 9))
+    for r, c in enumerate(reps):
+        S, ns = lat.lb_structure_factor(L.LB_SK_READ, r)
+        assert ns == nsamp
+        ratio = S.cpu().numpy() / (Gu * c["kT"])
+        per[r] = [ratio[a][mask].mean() for a in range(9)]
+    f, _ = lat.lb_status_flags()
+    lat.close()
+    assert f == 0
+    mean = per.mean(axis=0)
+    say("ensemble 128^2 class: mean S/G_unc", np.round(mean, 4), "replica spread", np.round(per.std(axis=0), 4))
+    assert np.abs(mean - 1).max() < 0.005
+    # no dependence on kT across two decades: compare the low- and high-kT halves
+    order = np.argsort([c["kT"] for c in reps])
+    lo, hi = per[order[:128]].mean(axis=0), per[order[128:]].mean(axis=0)
+    assert np.abs(lo - hi).max() < 0.01
