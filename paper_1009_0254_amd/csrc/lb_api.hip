@@ -424,8 +424,16 @@ lb_status autotune(lb_handle *h)
     int bx0 = 256;
     while (bx0 > MIN_BX && bx0 / 2 >= min_nx) bx0 /= 2;
     if (h->L.nodes < (1ll << 22)) return set_tiles(h, bx0, h->L.nodes < (1ll << 16) ? MIN_H : 16);
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LB_EDEVICE;
+    struct Events {   // destroyed on every return path
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) return LB_EDEVICE;
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     // candidates in order of how often they win; every candidate is timed once after a
     // warm-up, the three fastest are timed again, and among those re-timings a later one
     // replaces an earlier one only when at least 2% faster, so that near-ties resolve the
@@ -483,8 +491,6 @@ lb_status autotune(lb_handle *h)
             bbx = c.bx;
             brows = c.rows;
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (hipMemcpyAsync(h->flags, &h->init_flags, sizeof(unsigned), hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return LB_EDEVICE;
     return set_tiles(h, bbx, brows);
