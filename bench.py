@@ -109,9 +109,33 @@ def cpu_baseline(torch, L, cfg, steps):
         scale = np.abs(mo[a] - mo[a].mean()).max()
         err.append(float(np.abs(mg[a] - mo[a]).max() / scale))
     del mo, mg, ora
-    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{cfg['nx']}x{cfg['ny']} lattice of the same workload, {steps} steps, FP64 "
-                      f"({dt:.1f} s)"}, err
+    out = {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{cfg['nx']}x{cfg['ny']} lattice of the same workload, {steps} steps, FP64 "
+                     f"({dt:.1f} s)"}
+    one = cpu_baseline_one_core(cfg)
+    if one:
+        out["one_core"] = one
+    return out, err
+
+
+def cpu_baseline_one_core(cfg, side=2048, steps=2):
+    """The oracle on one host core (a child process with OMP_NUM_THREADS=1) on a side x side
+    crop of the same workload."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "from oracle import oracle as O\n"
+            "cfg = dict(%r, nx=%d, ny=%d)\n"
+            "o = O.Oracle(cfg); t0 = time.perf_counter(); o.step(%d); print(time.perf_counter() - t0)\n"
+            % (ROOT, {k: v for k, v in cfg.items()}, side, side, steps))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        dt = float(r.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        return None
+    log(f"cpu baseline, one core: {side}^2 x {steps} steps in {dt:.1f} s")
+    return {"value": side * side * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{side}x{side} crop of the same workload, {steps} steps, FP64 ({dt:.1f} s)"}
 
 
 def main():
