@@ -133,13 +133,13 @@ constexpr int SK_LINE_MAX = 8192;   // longest complex line held in LDS (128 KiB
 
 struct SkRep {
     int32_t nx, ny, lognx, logny;
-    int32_t split;      // column blocks per kx: 1 if ny <= SK_LINE_MAX / 2, else 2 (one per output parity)
+    int32_t split;      // column blocks per kx: 1, or 2 (one per output parity) when a column does not fit
     int32_t cpb;        // adjacent kx columns per column block (1 when split)
     int32_t rpb;        // rows per row block
     int32_t pad_;
     int64_t row0;       // first row block of this replica (prefix of ceil(ny / rpb))
     int64_t col0;       // first column block (prefix of split * ceil(nh / cpb)), nh = nx/2 + 1
-    int64_t soff;       // offset (double2) of its [ny][nh] spectrum inside one mode slot
+    int64_t soff;       // offset (complex elements) of its [ny][nh] spectrum inside one mode slot
     int64_t acc_off;    // offset (double) of its [9][nh][ny] accumulators
 };
 
@@ -153,9 +153,10 @@ struct SkLaunch {
     int32_t lds_rows;         // most row points per block in the range (rpb * nx)
     int32_t lds_cols;         // most column points per block in the range (cpb * ny, or ny/2 if split)
     int32_t G;                // modes per transform group of the row kernel
-    int64_t Ptot;             // double2 per mode slot (sum of ny * nh over all replicas)
-    double *spec;             // nine mode slots of row spectra
+    int64_t Ptot;             // complex elements per mode slot (sum of ny * nh over all replicas)
+    void *spec;               // nine mode slots of row spectra (float2 for FP32 storage, else double2)
     double *acc;
+    double *base;             // [replica][9]: the moments of node (0, 0) of the last sample
     const double *tw;         // exp(-2 pi i j / nmax), j < nmax/2
     int32_t nmax;
 };
