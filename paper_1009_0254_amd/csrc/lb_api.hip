@@ -44,7 +44,7 @@ size_t elem_size(int precision) { return precision == LB_FP64 ? sizeof(double) :
 
 struct Layout {
     size_t fbuf[2], reps, tiles, tdev, flags, partials, tot, rho_tmp;
-    size_t sk_tw, sk_reps, spec, acc;   // structure factor
+    size_t sk_tw, sk_reps, spec, acc, sk_base;   // structure factor
     int sk_G, sk_nmax;
     long long sk_ptot;
     size_t xi, cn_a, cn_tw;     // correlated noise
@@ -132,15 +132,8 @@ lb_status validate(const lb_params *p, int32_t n_rep, int32_t precision)
     return LB_OK;
 }
 
-// modes per sampling pass: the row kernel holds G half-length transforms of the widest
-// row in LDS, at most 128 KiB
-int sk_modes_per_pass(int max_nx) { return std::max(1, std::min(9, SK_LINE_MAX * 2 / std::max(max_nx, 4))); }
-
 // rows per row workgroup: narrow rows are grouped to 512 complex points
 int sk_rows_per_block(int nx, int ny) { return std::max(1, std::min(ny, 1024 / nx)); }
-
-// adjacent kx columns per column workgroup: up to 4096 points (64 KiB) of short columns
-int sk_cols_per_block(int nx, int ny) { return ny >= 4096 ? 1 : std::min(4096 / ny, nx / 2 + 1); }
 
 // the S(k) feature needs power-of-two sides in [4, SK_MAX] on every replica
 lb_status validate_features(const lb_params *p, int32_t n_rep, uint32_t features)
@@ -191,13 +184,14 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
     L.rho_tmp = o; o += align_up(sizeof(double) * L.max_n);
     if (features & LB_FEATURE_STRUCTURE_FACTOR) {
         L.sk_nmax = std::max(L.max_nx, L.max_ny);
-        L.sk_G = sk_modes_per_pass(L.max_nx);
+        L.sk_G = sk_modes_per_pass(precision, L.max_nx);
         L.sk_ptot = 0;
         for (int r = 0; r < n_rep; ++r) L.sk_ptot += (long long)p[r].ny * (p[r].nx / 2 + 1);
         L.sk_tw = o; o += align_up(sizeof(double) * 2 * (size_t)(L.sk_nmax / 2));
         L.sk_reps = o; o += align_up(sizeof(SkRep) * n_rep);
-        L.spec = o; o += align_up(sizeof(double) * 2 * 9 * (size_t)L.sk_ptot);
+        L.spec = o; o += align_up((size_t)sk_elem(precision) * 9 * (size_t)L.sk_ptot);
         L.acc = o; o += align_up(sizeof(double) * L.acc_elems);
+        L.sk_base = o; o += align_up(sizeof(double) * 9 * (size_t)n_rep);
     }
     if (L.cn_nodes > 0) {
         L.xi = o; o += align_up((size_t)2 * L.cn_nodes * elem_size(precision));
@@ -235,7 +229,8 @@ struct lb_handle {
     std::vector<SkRep> sk;
     SkRep *sk_d = nullptr;
     long long sk_rows = 0, sk_cols = 0;   // totals over all replicas
-    double *sk_tw = nullptr, *spec = nullptr, *acc = nullptr;
+    double *sk_tw = nullptr, *acc = nullptr, *sk_base = nullptr;
+    void *spec = nullptr;
     long long sample_every = 0, sample_first = 0;
     hipGraphExec_t sgraph[2] = {nullptr, nullptr};      // sample_every steps + one sample
     // correlated noise
@@ -387,6 +382,7 @@ SkLaunch sk_launch(const lb_handle *h, int r0, int r1, int par)
     a.Ptot = h->L.sk_ptot;
     a.spec = h->spec;
     a.acc = h->acc;
+    a.base = h->sk_base;
     a.tw = h->sk_tw;
     a.nmax = h->L.sk_nmax;
     return a;
@@ -689,8 +685,9 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
     if (features & LB_FEATURE_STRUCTURE_FACTOR) {
         h->sk_tw = (double *)(h->ws + L.sk_tw);
         h->sk_d = (SkRep *)(h->ws + L.sk_reps);
-        h->spec = (double *)(h->ws + L.spec);
+        h->spec = h->ws + L.spec;
         h->acc = (double *)(h->ws + L.acc);
+        h->sk_base = (double *)(h->ws + L.sk_base);
         long long rows = 0, cols = 0, soff = 0;
         int max_col = 0, max_row = 0;
         for (int r = 0; r < n_rep; ++r) {
@@ -699,8 +696,8 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
             q.ny = p[r].ny;
             q.lognx = ilog2(q.nx);
             q.logny = ilog2(q.ny);
-            q.split = q.ny > SK_LINE_MAX / 2 ? 2 : 1;   // halves of 8192-long columns: two workgroups per CU
-            q.cpb = sk_cols_per_block(q.nx, q.ny);
+            q.split = sk_split(precision, q.ny);
+            q.cpb = sk_cols_per_block(precision, q.nx, q.ny);
             q.rpb = sk_rows_per_block(q.nx, q.ny);
             const int nh = q.nx / 2 + 1;
             q.row0 = rows;
@@ -718,7 +715,7 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
         h->sk_cols = cols;
         e = hipMemcpyAsync(h->sk_d, h->sk.data(), sizeof(SkRep) * n_rep, hipMemcpyHostToDevice, h->stream);
         if (e == hipSuccess) e = launch_twiddles(h->sk_tw, L.sk_nmax, h->stream);
-        if (e == hipSuccess) e = set_sk_lds_limits(L.sk_G, max_row, max_col);
+        if (e == hipSuccess) e = set_sk_lds_limits(precision, L.sk_G, max_row, max_col);
         if (e == hipSuccess) e = launch_fill(h->acc, (int64_t)L.acc_elems, 0.0, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) {

@@ -66,6 +66,7 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_rows(void *__restrict__ Av, c
     const double cy = cospi(2.0 * ky / ny);
     const double pre = c.kT3 * c.rho0;
     const double rs = 0.70710678118654752440;   // 1/sqrt(2)
+    const int sh = lds_pad_shift(d.lognx);
     for (int kx = threadIdx.x; kx < nx; kx += blockDim.x) {
         const int mx = (nx - kx) & (nx - 1);
         const unsigned idx = (unsigned)ky * nx + kx, midx = (unsigned)my * nx + mx;
@@ -96,12 +97,12 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_rows(void *__restrict__ Av, c
         // Z = xi_4(k) + i xi_9(k), xi_4 = l44 nu_4, xi_9 = l94 nu_4 + l99 nu_9
         const double x4r = l44 * n4r, x4i = l44 * n4i;
         const double x9r = l94 * n4r + l99 * n9r, x9i = l94 * n4i + l99 * n9i;
-        X[bitrev((unsigned)kx, d.lognx)] = mk2((R)(x4r - x9i), (R)(x4i + x9r));
+        X[lds_at(bitrev((unsigned)kx, d.lognx), sh)] = mk2((R)(x4r - x9i), (R)(x4i + x9r));
     }
     __syncthreads();
     fft_lds<false, R>(X, nx, d.lognx, 1, T, nx);
     C *row = reinterpret_cast<C *>(Av) + (long long)ky * nx;
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) row[x] = X[x];
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) row[x] = X[lds_at(x, sh)];
 }
 
 // columns: transform C adjacent columns of A along ky, scale by n^-1/2, store xi_4, xi_9
@@ -121,10 +122,10 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_cols(const void *__restrict__
     if (lb < 0) return;
     const int x0 = (int)lb * cpb, Cn = min(cpb, nx - x0);
     tw_cache_load(T, twy, ny);
-    const int tot = Cn * ny;
+    const int tot = Cn * ny, sh = lds_pad_shift(d.logny);
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         const int y = e / Cn, cc = e - y * Cn;
-        X[cc * ny + bitrev((unsigned)y, d.logny)] = A[(long long)y * nx + x0 + cc];
+        X[lds_at(cc * ny + bitrev((unsigned)y, d.logny), sh)] = A[(long long)y * nx + x0 + cc];
     }
     __syncthreads();
     fft_lds<false, S>(X, ny, d.logny, Cn, T, ny);
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_cols(const void *__restrict__
     S *out = xi + 2 * d.xi_off;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         const int y = e / Cn, cc = e - y * Cn;
-        const C v = X[cc * ny + y];
+        const C v = X[lds_at(cc * ny + y, sh)];
         const long long o = 2 * ((long long)y * nx + x0 + cc);
         out[o] = v.x * s;
         out[o + 1] = v.y * s;
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_cols(const void *__restrict__
 
 hipError_t set_fft_lds_limit(int max_nx, int max_col_points)
 {
-    const int rows = (int)sizeof(double2) * max_nx, cols = (int)sizeof(double2) * max_col_points;
+    const int rows = (int)(sizeof(double2) * lds_padded(max_nx)), cols = (int)(sizeof(double2) * lds_padded(max_col_points));
     hipError_t e = hipFuncSetAttribute((const void *)k_cn_rows<double>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_cn_rows<float>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
@@ -164,14 +165,14 @@ hipError_t launch_correlated_noise(int precision, const RepDesc *d_reps, const R
     const int cpb = cn_cols_per_block(nx, ny);
     const unsigned ncb = xcd_grid((nx + cpb - 1) / cpb);
     if (precision == 0) {
-        hipLaunchKernelGGL(k_cn_rows<double>, dim3(ny), dim3(cn_threads(nx)), sizeof(double2) * nx, s, (void *)work,
+        hipLaunchKernelGGL(k_cn_rows<double>, dim3(ny), dim3(cn_threads(nx)), sizeof(double2) * lds_padded(nx), s, (void *)work,
                            d_reps, rep_index, twx, tdev, toff);
-        hipLaunchKernelGGL(k_cn_cols<double>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(double2) * cpb * ny, s,
+        hipLaunchKernelGGL(k_cn_cols<double>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(double2) * lds_padded(cpb * ny), s,
                            (const void *)work, (double *)xi_base, d_reps, rep_index, cpb, twy);
     } else {
-        hipLaunchKernelGGL(k_cn_rows<float>, dim3(ny), dim3(cn_threads(nx)), sizeof(float2) * nx, s, (void *)work,
+        hipLaunchKernelGGL(k_cn_rows<float>, dim3(ny), dim3(cn_threads(nx)), sizeof(float2) * lds_padded(nx), s, (void *)work,
                            d_reps, rep_index, twx, tdev, toff);
-        hipLaunchKernelGGL(k_cn_cols<float>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(float2) * cpb * ny, s,
+        hipLaunchKernelGGL(k_cn_cols<float>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(float2) * lds_padded(cpb * ny), s,
                            (const void *)work, (float *)xi_base, d_reps, rep_index, cpb, twy);
     }
     return hipGetLastError();

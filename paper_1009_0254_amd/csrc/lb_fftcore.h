@@ -37,6 +37,15 @@ inline unsigned xcd_grid(long long total) { return (unsigned)(((total + 7) >> 3)
 
 constexpr int TW_LO = 64, TW_HI = 128;   // N <= 2 * 64 * 128 = 16384
 
+// LDS layout of a batch of length-n transforms: element i sits at lds_at(i, sh) = i + (i >> sh)
+// with sh = lds_pad_shift(log2 n), one pad slot after every 2^sh elements.  The bit-reversed
+// fill sends the 64 lanes of a wave to elements n / 64 apart, which without the pad share one
+// LDS bank; with it they fall into distinct banks.
+__host__ __device__ constexpr int lds_pad_shift(int logn) { return logn - 6 > 5 ? logn - 6 : 5; }
+__device__ __forceinline__ int lds_at(int i, int sh) { return i + (i >> sh); }
+// LDS elements that hold `total` elements of transforms of any length (pad at most 1/32)
+constexpr long long lds_padded(long long total) { return total + (total >> 5) + 1; }
+
 template <typename T> struct TwCacheT {
     typedef typename V2<T>::type C;
     C lo[TW_LO];
@@ -67,15 +76,16 @@ __device__ __forceinline__ typename V2<T>::type twiddle(const TwCacheT<T> &Tc, i
 }
 
 // `count` independent in-place decimation-in-time transforms of length n = 2^logn (n >= 2)
-// stored back to back in X, each already in bit-reversed order, with the twiddles of an
-// N-point table in T.  Pairs of radix-2 stages are fused into radix-4 passes (the second
-// stage's odd twiddle is the first's times w_4 = -i), with one radix-2 pass when logn is
-// odd.  INV uses the conjugate twiddles exp(+2 pi i k / n) and does not scale.  Ends with
-// a barrier.
+// stored back to back in X (through lds_at), each already in bit-reversed order, with the
+// twiddles of an N-point table in T.  Pairs of radix-2 stages are fused into radix-4 passes
+// (the second stage's odd twiddle is the first's times w_4 = -i), with one radix-2 pass when
+// logn is odd.  INV uses the conjugate twiddles exp(+2 pi i k / n) and does not scale.  Ends
+// with a barrier.
 template <bool INV, typename T>
 __device__ void fft_lds(typename V2<T>::type *X, int n, int logn, int count, const TwCacheT<T> &Tc, int N)
 {
     typedef typename V2<T>::type C;
+    const int sh = lds_pad_shift(logn);
     int s = 1;
     for (; s + 1 <= logn; s += 2) {
         const int lq = s - 1, q = 1 << lq;
@@ -85,21 +95,23 @@ __device__ void fft_lds(typename V2<T>::type *X, int n, int logn, int count, con
             const int g = b >> (logn - 2), bb = b & (n4 - 1);
             const int pos = bb & (q - 1);
             const int base = g * n + ((bb >> lq) << (lq + 2)) + pos;
+            const int i0 = lds_at(base, sh), i1 = lds_at(base + q, sh), i2 = lds_at(base + 2 * q, sh),
+                      i3 = lds_at(base + 3 * q, sh);
             C w1 = twiddle(Tc, pos * st1), w2 = twiddle(Tc, pos * st2);
             if (INV) {
                 w1.y = -w1.y;
                 w2.y = -w2.y;
             }
-            const C a = X[base], bv = X[base + q], c = X[base + 2 * q], d = X[base + 3 * q];
+            const C a = X[i0], bv = X[i1], c = X[i2], d = X[i3];
             const C b1 = cmul(w1, bv), d1 = cmul(w1, d);
             const C a1 = cadd(a, b1), bq = csub(a, b1), c1 = cadd(c, d1), dq = csub(c, d1);
             const C c2 = cmul(w2, c1);
             C d2 = cmul(w2, dq);
             d2 = INV ? mk2(-d2.y, d2.x) : mk2(d2.y, -d2.x);   // times +i / -i
-            X[base] = cadd(a1, c2);
-            X[base + 2 * q] = csub(a1, c2);
-            X[base + q] = cadd(bq, d2);
-            X[base + 3 * q] = csub(bq, d2);
+            X[i0] = cadd(a1, c2);
+            X[i2] = csub(a1, c2);
+            X[i1] = cadd(bq, d2);
+            X[i3] = csub(bq, d2);
         }
         __syncthreads();
     }
@@ -108,7 +120,8 @@ __device__ void fft_lds(typename V2<T>::type *X, int n, int logn, int count, con
         for (int b = threadIdx.x; b < total; b += blockDim.x) {
             const int g = b >> (logn - 1), bb = b & (nb - 1);
             const int pos = bb & (half - 1);
-            const int i0 = g * n + ((bb >> (s - 1)) << s) + pos, i1 = i0 + half;
+            const int e0 = g * n + ((bb >> (s - 1)) << s) + pos;
+            const int i0 = lds_at(e0, sh), i1 = lds_at(e0 + half, sh);
             C w = twiddle(Tc, pos * st);
             if (INV) w.y = -w.y;
             const C u = X[i0], t = cmul(X[i1], w);

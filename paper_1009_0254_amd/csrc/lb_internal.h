@@ -129,7 +129,6 @@ int cn_col_points(int nx, int ny);
 // structure factor (lb_sk.hip).  Replicas are sampled together: every pass covers a range
 // [r0, r1) of replicas with one launch per kernel, whatever their sizes.
 constexpr int SK_MAX = 16384;       // largest side the sampler transforms
-constexpr int SK_LINE_MAX = 8192;   // longest complex line held in LDS (128 KiB of double2)
 
 struct SkRep {
     int32_t nx, ny, lognx, logny;
@@ -160,7 +159,13 @@ struct SkLaunch {
     const double *tw;         // exp(-2 pi i j / nmax), j < nmax/2
     int32_t nmax;
 };
-hipError_t set_sk_lds_limits(int G, int max_nx, int max_col);
+// sampler layout policy: bytes per complex transform element (16 for FP64 storage, else 8),
+// modes per row pass, column blocks per kx, adjacent kx per column block
+int sk_elem(int precision);
+int sk_modes_per_pass(int precision, int max_nx);
+int sk_split(int precision, int ny);
+int sk_cols_per_block(int precision, int nx, int ny);
+hipError_t set_sk_lds_limits(int precision, int G, int max_row, int max_col);
 // add |m_a(k)|^2 / n, a = 0..8, of every replica in the range to its accumulators
 hipError_t launch_sk_sample(int precision, const SkLaunch &a, hipStream_t s);
 // |rho(k)|^2 / n of replica a.r0 (a one-replica range), radially binned into out[0..nbins)

@@ -5,20 +5,27 @@
 //
 // A sample covers a range of replicas of any sizes with two launches, whatever their sizes:
 //   1. rows: one workgroup per lattice row of any replica in the range.  It pulls the
-//      pre-collision populations, forms G of the nine moments in FP64 and turns each real
-//      row of length nx into its half spectrum with one complex transform of length nx/2
-//      (even samples as real part, odd as imaginary, then the standard split); it repeats
-//      this for the next G modes until all nine are done (the repeated pulls of the same
-//      row hit the caches), writing mode a to slot a of the spectra, [ny][nx/2+1] each;
+//      pre-collision populations, forms G of the nine moments in FP64 relative to those of
+//      node (0, 0), rounds them once to the transform precision (FP32 for FP32 storage, FP64
+//      for FP64 storage) and turns each real row of length nx into its half spectrum with
+//      one complex transform of length nx/2 (even samples as real part, odd as imaginary,
+//      then the standard split); it repeats this for the next G modes until all nine are
+//      done (the repeated pulls of the same row hit the caches), writing mode a to slot a
+//      of the spectra, [ny][nx/2+1] each;
 //   2. columns: one workgroup per kx and mode reads its column of the row spectra in place
 //      (consecutive kx share cache lines and are kept on one XCD), transforms along y
-//      (lines longer than 4096 are split by one decimation-in-frequency stage into two
-//      half-length transforms, one per output parity, so that two workgroups fit a CU's
-//      LDS) and adds |X|^2 / n to the FP64 accumulators [9][nx/2+1][ny].
+//      (a column longer than 64 KiB of LDS is split by one decimation-in-frequency stage
+//      into two half-length transforms, one per output parity, so that it fits), restores
+//      the k = 0 coefficient in FP64 and adds |X|^2 / n to the FP64 accumulators
+//      [9][nx/2+1][ny].
+// Subtracting a constant per mode moves only k = 0, so the transforms see fluctuation-sized
+// values whatever the mean state: in FP32 their rounding is ~1e-7 of the spectrum's scale.
 // The radially binned density spectrum (the isotropic average of S_rho(k), used to follow
 // density modes after a quench to c_s^2 < 0, where M(k) of eq. (lb-lang-ft) has growing
 // eigenvalues) reuses 1-3 for mode 0 of one replica and bins |rho(k)|^2 / n with integer
 // shell arithmetic.
+
+#include <algorithm>
 
 #include "lb_fftcore.h"
 #include "lb_internal.h"
@@ -85,12 +92,11 @@ __device__ __forceinline__ void moments9(const double g[9], double m[9])
     m[8] = 2 * g[0] - 4 * sa + 8 * sd;
 }
 
-// mode a of m = T f from the nine pulled values of one node (stored + shift, in FP64), with
-// the expression trees of moments9 for that mode only
-template <typename S>
-__device__ __forceinline__ double moment_of(int a, const S v[9], const double *sh)
+// mode a of m = T f from the nine pulled values of one node (in FP64), with the expression
+// trees of moments9 for that mode only
+template <typename S> __device__ __forceinline__ double moment_of(int a, const S v[9])
 {
-    auto g = [&](int i) { return (double)v[i] + sh[i]; };
+    auto g = [&](int i) { return (double)v[i]; };
     switch (a) {
     case 0: return g(0) + ((g(1) + g(2)) + (g(3) + g(4))) + ((g(5) + g(6)) + (g(7) + g(8)));
     case 1: return (g(1) - g(3)) + (g(5) - g(7)) + (g(8) - g(6));
@@ -104,19 +110,24 @@ __device__ __forceinline__ double moment_of(int a, const S v[9], const double *s
     }
 }
 
-constexpr int SK_CACHE_PAIRS = 4;   // node pairs per lane kept in registers across mode groups
-
-// CACHE: every lane's pulls (at most SK_CACHE_PAIRS pairs) are loaded once and kept in
-// registers for all mode groups; otherwise each group pulls again (the repeats hit L2/MALL)
-template <typename S, bool CACHE>
+// Transforms run in Tt (float for FP32 storage, double for FP64) on m_a(r) - m_a(0, 0): the
+// moments relative to those of node (0, 0), formed in FP64 and rounded once, so that the
+// transforms see fluctuation-sized values whatever the mean state; a constant only moves the
+// k = 0 coefficient, which the column pass restores in FP64 as X(0) + n m_a(0, 0).  The
+// block of row 0 stores m_a(0, 0) (with the storage shift) in base[9 r + a].  Each group of
+// G modes pulls the row again (the repeats hit L2 or the MALL).
+template <typename S, typename Tt>
 __global__ void __launch_bounds__(SK_THREADS)
     k_sk_rows(const S *__restrict__ f, const RepDesc *__restrict__ reps, const SkRep *__restrict__ sk, int r0, int r1,
               long long row_base, long long nrows, int a_first, int a_count, int G, long long Ptot,
-              double2 *__restrict__ spec, const double2 *__restrict__ tw, int nmax)
+              typename V2<Tt>::type *__restrict__ spec, double *__restrict__ base, const double2 *__restrict__ tw,
+              int nmax)
 {
+    typedef typename V2<Tt>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ TwCache T;
-    double2 *X = reinterpret_cast<double2 *>(smem_raw);
+    __shared__ TwCacheT<Tt> T;
+    __shared__ double m00[9];
+    C *X = reinterpret_cast<C *>(smem_raw);
     const long long lr = xcd_logical(nrows);
     if (lr < 0) return;
     tw_cache_load(T, tw, nmax);
@@ -129,34 +140,23 @@ __global__ void __launch_bounds__(SK_THREADS)
     const int R = min(q.rpb, ny - y0);          // rows of this block; transform (c, rr) at X[(c R + rr) M]
     const int pairs = R * M;
     const S *P = f + d.off;
-    const int wstride = nmax / nx;
-    S cv[CACHE ? SK_CACHE_PAIRS : 1][2][9];
-    if (CACHE) {
-#pragma unroll
-        for (int j = 0; j < SK_CACHE_PAIRS; ++j) {
-            const int e = threadIdx.x + j * (int)blockDim.x;
-            if (e < pairs) {
-                const int rr = e / M, n = e - rr * M;
-                load_pull(P, nx, ny, 2 * n, y0 + rr, cv[j][0]);
-                load_pull(P, nx, ny, 2 * n + 1, y0 + rr, cv[j][1]);
-            }
+    const int wstride = nmax / nx, sh = lds_pad_shift(logM);
+    if (threadIdx.x == 0) {
+        S v[9];
+        double g[9], m[9];
+        load_pull(P, nx, ny, 0, 0, v);
+        for (int i = 0; i < 9; ++i) g[i] = (double)v[i];
+        moments9(g, m);
+        for (int i = 0; i < 9; ++i) m00[i] = m[i];
+        if (y0 == 0) {
+            for (int i = 0; i < 9; ++i) g[i] += d.shift[i];
+            moments9(g, m);
+            for (int i = 0; i < 9; ++i) base[9 * r + i] = m[i];
         }
     }
+    __syncthreads();   // m00
     for (int a0 = a_first; a0 < a_first + a_count; a0 += G) {
         const int gcount = min(G, a_first + a_count - a0);
-        if (CACHE) {
-#pragma unroll
-            for (int j = 0; j < SK_CACHE_PAIRS; ++j) {
-                const int e = threadIdx.x + j * (int)blockDim.x;
-                if (e < pairs) {
-                    const int rr = e / M, n = e - rr * M;
-                    const unsigned jb = bitrev((unsigned)n, logM);
-                    for (int c = 0; c < gcount; ++c)
-                        X[(c * R + rr) * M + jb] = make_double2(moment_of(a0 + c, cv[j][0], d.shift),
-                                                                moment_of(a0 + c, cv[j][1], d.shift));
-                }
-            }
-        } else
         // two pairs of nodes per lane and iteration, all 36 loads issued before use
         for (int e0 = threadIdx.x; e0 < pairs; e0 += 2 * blockDim.x) {
             const int e1 = e0 + blockDim.x < pairs ? e0 + blockDim.x : e0;
@@ -167,32 +167,29 @@ __global__ void __launch_bounds__(SK_THREADS)
             load_pull(P, nx, ny, 2 * n1, y0 + rr1, v[2]);
             load_pull(P, nx, ny, 2 * n1 + 1, y0 + rr1, v[3]);
             for (int p = 0; p < 2; ++p) {
-                double ge[9], go[9], me[9], mo[9];
-                for (int i = 0; i < 9; ++i) {
-                    ge[i] = (double)v[2 * p][i] + d.shift[i];
-                    go[i] = (double)v[2 * p + 1][i] + d.shift[i];
-                }
-                moments9(ge, me);
-                moments9(go, mo);
                 const int rr = p ? rr1 : rr0;
                 const unsigned j = bitrev((unsigned)(p ? n1 : n0), logM);
-                for (int c = 0; c < gcount; ++c) X[(c * R + rr) * M + j] = make_double2(me[a0 + c], mo[a0 + c]);
+                for (int c = 0; c < gcount; ++c) {
+                    const double mc = m00[a0 + c];
+                    X[lds_at((c * R + rr) * M + j, sh)] =
+                        mk2((Tt)(moment_of(a0 + c, v[2 * p]) - mc), (Tt)(moment_of(a0 + c, v[2 * p + 1]) - mc));
+                }
             }
         }
         __syncthreads();
-        fft_lds<false, double>(X, M, logM, gcount * R, T, nmax);
+        fft_lds<false, Tt>(X, M, logM, gcount * R, T, nmax);
         // X_k = E_k + W^k O_k with E = (Z_k + conj Z_{M-k}) / 2, O = (Z_k - conj Z_{M-k}) / 2i,
         // W = exp(-2 pi i / nx), for k = 0..M (Z has period M)
+        const Tt h = (Tt)0.5;
         for (int idx = threadIdx.x; idx < gcount * R * nh; idx += blockDim.x) {
             const int t = idx / nh, k = idx - t * nh;     // t = c R + rr
             const int c = t / R, rr = t - c * R;
-            const double2 Zk = X[t * M + (k & (M - 1))];
-            const double2 Zm = X[t * M + ((M - k) & (M - 1))];
-            const double2 E = make_double2(0.5 * (Zk.x + Zm.x), 0.5 * (Zk.y - Zm.y));
-            const double2 O = make_double2(0.5 * (Zk.y + Zm.y), -0.5 * (Zk.x - Zm.x));
-            const double2 W = k < M ? twiddle(T, k * wstride) : make_double2(-1.0, 0.0);
-            const double2 WO = cmul(W, O);
-            spec[(a0 + c) * Ptot + q.soff + (long long)(y0 + rr) * nh + k] = make_double2(E.x + WO.x, E.y + WO.y);
+            const C Zk = X[lds_at(t * M + (k & (M - 1)), sh)];
+            const C Zm = X[lds_at(t * M + ((M - k) & (M - 1)), sh)];
+            const C E = mk2(h * (Zk.x + Zm.x), h * (Zk.y - Zm.y));
+            const C O = mk2(h * (Zk.y + Zm.y), -h * (Zk.x - Zm.x));
+            const C W = k < M ? twiddle(T, k * wstride) : mk2((Tt)-1, (Tt)0);
+            spec[(a0 + c) * Ptot + q.soff + (long long)(y0 + rr) * nh + k] = cadd(E, cmul(W, O));
         }
         __syncthreads();   // X is reused by the next group
     }
@@ -200,17 +197,20 @@ __global__ void __launch_bounds__(SK_THREADS)
 
 // column transforms of every replica in the range, reading the row spectra in place;
 // mode a = a_first + blockIdx.y.  A block takes cpb adjacent kx (reads coalesced along kx)
-// or, for split lines, one kx and one output parity.  SNAP writes |X|^2 / n to plane
-// ([nh][ny], one replica), otherwise adds it to the accumulators.
-template <bool SNAP>
+// or, for split lines, one kx and one output parity.  |X|^2 is formed in FP64, with the
+// k = 0 coefficient restored to X(0) + n m_a(0, 0) (the row pass transformed moments
+// relative to node (0, 0)).  SNAP writes |X|^2 / n to plane ([nh][ny], one replica),
+// otherwise adds it to the accumulators.
+template <typename Tt, bool SNAP>
 __global__ void __launch_bounds__(SK_THREADS)
-    k_sk_cols(const double2 *__restrict__ spec, const SkRep *__restrict__ sk, int r0, int r1, long long col_base,
-              long long ncols, long long Ptot, int a_first, double *__restrict__ acc, double *__restrict__ plane,
-              const double2 *__restrict__ tw, int nmax)
+    k_sk_cols(const typename V2<Tt>::type *__restrict__ spec, const SkRep *__restrict__ sk, int r0, int r1,
+              long long col_base, long long ncols, long long Ptot, int a_first, double *__restrict__ acc,
+              double *__restrict__ plane, const double *__restrict__ base, const double2 *__restrict__ tw, int nmax)
 {
+    typedef typename V2<Tt>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ TwCache T;
-    double2 *X = reinterpret_cast<double2 *>(smem_raw);
+    __shared__ TwCacheT<Tt> T;
+    C *X = reinterpret_cast<C *>(smem_raw);
     const long long lc = xcd_logical(ncols);
     if (lc < 0) return;
     tw_cache_load(T, tw, nmax);
@@ -222,50 +222,50 @@ __global__ void __launch_bounds__(SK_THREADS)
     const int local = (int)(gc - q.col0);
     const int grp = local / split, par = local - grp * split;
     const int kx0 = grp * q.cpb;
-    const int C = min(q.cpb, nh - kx0);          // columns of this block
+    const int C_ = min(q.cpb, nh - kx0);         // columns of this block
     const int a = a_first + blockIdx.y;
-    const double2 *S0 = spec + a * Ptot + q.soff + kx0;    // (y, c) at S0[y * nh + c]
+    const C *S0 = spec + a * Ptot + q.soff + kx0;    // (y, c) at S0[y * nh + c]
     const double inv_n = 1.0 / ((double)q.nx * (double)ny);
-    int L, logL;
+    // added to the real part of output 0 of this block when that output is k = 0
+    const double k0 = kx0 == 0 && par == 0 ? (double)q.nx * (double)ny * base[9 * r + a] : 0.0;
+    const int L = ny / split, logL = q.logny - (split - 1), sh = lds_pad_shift(logL);
     if (split == 1) {
-        L = ny;
-        logL = q.logny;
-        const int tot = C * ny;
+        const int tot = C_ * ny;
         for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * blockDim.x) {
-            double2 v[4];
+            C v[4];
             for (int u = 0; u < 4; ++u) {
-                const int e = min(e0 + u * (int)blockDim.x, tot - 1), y = e / C, c = e - y * C;
+                const int e = min(e0 + u * (int)blockDim.x, tot - 1), y = e / C_, c = e - y * C_;
                 v[u] = S0[(long long)y * nh + c];
             }
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u * (int)blockDim.x;
                 if (e < tot) {
-                    const int y = e / C, c = e - y * C;
-                    X[c * ny + bitrev((unsigned)y, logL)] = v[u];
+                    const int y = e / C_, c = e - y * C_;
+                    X[lds_at(c * ny + bitrev((unsigned)y, logL), sh)] = v[u];
                 }
             }
         }
     } else {
         // X_{2k+p} = sum_n [x_n + (-1)^p x_{n+L}] W^{pn} exp(-2 pi i n k / L), W = exp(-2 pi i / ny)
-        L = ny >> 1;
-        logL = q.logny - 1;
         const int wstride = nmax / ny;
         for (int n = threadIdx.x; n < L; n += blockDim.x) {
-            const double2 u = S0[(long long)n * nh], v = S0[(long long)(n + L) * nh];
-            const double2 w = par == 0 ? make_double2(u.x + v.x, u.y + v.y)
-                                       : cmul(make_double2(u.x - v.x, u.y - v.y), twiddle(T, n * wstride));
-            X[bitrev((unsigned)n, logL)] = w;
+            const C u = S0[(long long)n * nh], v = S0[(long long)(n + L) * nh];
+            X[lds_at(bitrev((unsigned)n, logL), sh)] = par == 0 ? cadd(u, v) : cmul(csub(u, v), twiddle(T, n * wstride));
         }
     }
     __syncthreads();
-    fft_lds<false, double>(X, L, logL, split == 1 ? C : 1, T, nmax);
-    const int tot = (split == 1 ? C : 1) * L;
+    fft_lds<false, Tt>(X, L, logL, split == 1 ? C_ : 1, T, nmax);
+    const int tot = (split == 1 ? C_ : 1) * L;
+    auto power = [&](int e) {
+        const C v = X[lds_at(e, sh)];
+        const double re = (double)v.x + (e == 0 ? k0 : 0.0), im = (double)v.y;
+        return (re * re + im * im) * inv_n;
+    };
     if (SNAP) {
         double *D = plane + (long long)kx0 * ny;
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
             const int c = e / L, k = e - c * L;
-            const double2 v = X[e];
-            D[(long long)c * ny + k * split + par] = (v.x * v.x + v.y * v.y) * inv_n;
+            D[(long long)c * ny + k * split + par] = power(e);
         }
     } else {
         double *A = acc + q.acc_off + (long long)a * nh * ny + (long long)kx0 * ny;
@@ -279,8 +279,7 @@ __global__ void __launch_bounds__(SK_THREADS)
                 const int e = e0 + u * (int)blockDim.x;
                 if (e < tot) {
                     const int c = e / L, k = e - c * L;
-                    const double2 v = X[e];
-                    A[(long long)c * ny + k * split + par] = old[u] + (v.x * v.x + v.y * v.y) * inv_n;
+                    A[(long long)c * ny + k * split + par] = old[u] + power(e);
                 }
             }
         }
@@ -357,47 +356,76 @@ __global__ void k_sk_read(const double *__restrict__ acc, double *__restrict__ o
     }
 }
 
+template <typename S, typename Tt>
+void rows_kernel(const SkLaunch &a, int a_first, int a_count, int G, int threads, hipStream_t s)
+{
+    const size_t lds = (size_t)sk_elem(sizeof(Tt) == 8 ? 0 : 1) * lds_padded((long long)G * (a.lds_rows / 2));
+    hipLaunchKernelGGL((k_sk_rows<S, Tt>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s, (const S *)a.f,
+                       a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
+                       (long long)a.Ptot, (typename V2<Tt>::type *)a.spec, a.base, (const double2 *)a.tw, a.nmax);
+}
+
 hipError_t launch_rows(int precision, const SkLaunch &a, int a_first, int a_count, hipStream_t s)
 {
     const int G = a_count < a.G ? a_count : a.G;
-    const size_t lds = sizeof(double) * (size_t)G * a.lds_rows;
     const int threads = sk_threads(a.lds_rows);
-    // FP32 pulls of every block in the range fit the lanes' registers when a block has at
-    // most SK_CACHE_PAIRS node pairs per lane (a.lds_rows nodes at most per block)
-    const bool cache = precision != 0 && a.lds_rows / 2 <= SK_CACHE_PAIRS * threads && a_count > G;
     if (precision == 0)
-        hipLaunchKernelGGL((k_sk_rows<double, false>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s,
-                           (const double *)a.f,
-                           a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
-                           (long long)a.Ptot, (double2 *)a.spec, (const double2 *)a.tw, a.nmax);
-    else if (cache)
-        hipLaunchKernelGGL((k_sk_rows<float, true>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s,
-                           (const float *)a.f,
-                           a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
-                           (long long)a.Ptot, (double2 *)a.spec, (const double2 *)a.tw, a.nmax);
+        rows_kernel<double, double>(a, a_first, a_count, G, threads, s);
     else
-        hipLaunchKernelGGL((k_sk_rows<float, false>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s,
-                           (const float *)a.f,
-                           a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
-                           (long long)a.Ptot, (double2 *)a.spec, (const double2 *)a.tw, a.nmax);
+        rows_kernel<float, float>(a, a_first, a_count, G, threads, s);
     return hipGetLastError();
+}
+
+template <typename Tt, bool SNAP>
+void cols_kernel(int precision, const SkLaunch &a, unsigned modes, double *plane, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sk_cols<Tt, SNAP>), dim3(xcd_grid(a.cols), modes), dim3(sk_threads(a.lds_cols)),
+                       (size_t)sk_elem(precision) * lds_padded(a.lds_cols), s, (const typename V2<Tt>::type *)a.spec, a.sk, a.r0,
+                       a.r1, (long long)a.col_base, (long long)a.cols, (long long)a.Ptot, 0, SNAP ? nullptr : a.acc,
+                       plane, (const double *)a.base, (const double2 *)a.tw, a.nmax);
+}
+
+template <typename K> hipError_t lds_limit(K kernel, size_t bytes)
+{
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 }  // namespace
 
-hipError_t set_sk_lds_limits(int G, int max_nx, int max_col)
+int sk_elem(int precision) { return precision == 0 ? (int)sizeof(double2) : (int)sizeof(float2); }
+
+// LDS budgets: the row kernel holds G half-length transforms of its widest rows in at most
+// 128 KiB; a column block holds at most 64 KiB (two blocks per CU)
+constexpr int ROW_BUDGET = 131072, COL_BUDGET = 65536;
+
+int sk_modes_per_pass(int precision, int max_nx)
 {
-    const int rows = (int)sizeof(double) * G * max_nx, cols = (int)sizeof(double2) * max_col;
-    hipError_t e =
-        hipFuncSetAttribute((const void *)k_sk_rows<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_sk_rows<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_sk_rows<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_sk_cols<false>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_sk_cols<true>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
+    const int per_mode = sk_elem(precision) * (std::max(max_nx, 1024) / 2);
+    return std::max(1, std::min(9, ROW_BUDGET / per_mode));
+}
+
+int sk_split(int precision, int ny) { return (long long)ny * sk_elem(precision) > COL_BUDGET ? 2 : 1; }
+
+int sk_cols_per_block(int precision, int nx, int ny)
+{
+    const int pts = COL_BUDGET / sk_elem(precision);
+    return ny >= pts ? 1 : std::min(pts / ny, nx / 2 + 1);
+}
+
+hipError_t set_sk_lds_limits(int precision, int G, int max_row, int max_col)
+{
+    const size_t rows = (size_t)sk_elem(precision) * lds_padded((long long)G * (max_row / 2)),
+                 cols = (size_t)sk_elem(precision) * lds_padded(max_col);
+    hipError_t e;
+    if (precision == 0) {
+        e = lds_limit(k_sk_rows<double, double>, rows);
+        if (e == hipSuccess) e = lds_limit(k_sk_cols<double, false>, cols);
+        if (e == hipSuccess) e = lds_limit(k_sk_cols<double, true>, cols);
+    } else {
+        e = lds_limit(k_sk_rows<float, float>, rows);
+        if (e == hipSuccess) e = lds_limit(k_sk_cols<float, false>, cols);
+        if (e == hipSuccess) e = lds_limit(k_sk_cols<float, true>, cols);
+    }
     return e;
 }
 
@@ -405,9 +433,10 @@ hipError_t launch_sk_sample(int precision, const SkLaunch &a, hipStream_t s)
 {
     hipError_t e = launch_rows(precision, a, 0, 9, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sk_cols<false>, dim3(xcd_grid(a.cols), 9), dim3(sk_threads(a.lds_cols)), sizeof(double2) * a.lds_cols, s,
-                       (const double2 *)a.spec, a.sk, a.r0, a.r1, (long long)a.col_base, (long long)a.cols,
-                       (long long)a.Ptot, 0, a.acc, (double *)nullptr, (const double2 *)a.tw, a.nmax);
+    if (precision == 0)
+        cols_kernel<double, false>(precision, a, 9, nullptr, s);
+    else
+        cols_kernel<float, false>(precision, a, 9, nullptr, s);
     return hipGetLastError();
 }
 
@@ -417,10 +446,11 @@ hipError_t launch_sk_snapshot(int precision, const SkLaunch &a, int nx, int ny, 
     hipError_t e = launch_rows(precision, a, 0, 1, s);
     if (e != hipSuccess) return e;
     // the density's |X|^2 / n goes to spectrum slot 1 (unused here) as [nh][ny] doubles
-    double *plane = a.spec + 2 * a.Ptot;
-    hipLaunchKernelGGL(k_sk_cols<true>, dim3(xcd_grid(a.cols), 1), dim3(sk_threads(a.lds_cols)), sizeof(double2) * a.lds_cols, s,
-                       (const double2 *)a.spec, a.sk, a.r0, a.r1, (long long)a.col_base, (long long)a.cols,
-                       (long long)a.Ptot, 0, (double *)nullptr, plane, (const double2 *)a.tw, a.nmax);
+    double *plane = (double *)((char *)a.spec + (size_t)sk_elem(precision) * a.Ptot);
+    if (precision == 0)
+        cols_kernel<double, true>(precision, a, 1, plane, s);
+    else
+        cols_kernel<float, true>(precision, a, 1, plane, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sk_bins, dim3((unsigned)nbins), dim3(256), 0, s, (const double *)plane, nx, ny, P, xwide,
                        nbins, out);

@@ -71,8 +71,11 @@ def test_workspace_size_counts_both_population_buffers():
     b32 = L.lb_workspace_size([c], L.LB_FP32_SHIFTED)
     assert b64 >= 2 * 9 * n * 8 and b32 >= 2 * 9 * n * 4 and b64 > b32
     bsk = L.lb_workspace_size([c], L.LB_FP32_SHIFTED, L.LB_FEATURE_STRUCTURE_FACTOR)
-    # accumulators [9][33][32] plus the row spectra of all nine modes
-    assert bsk >= b32 + 9 * 32 * 33 * 8 + 9 * 32 * 33 * 16
+    # accumulators [9][33][32] plus the row spectra of all nine modes (FP32 complex for FP32
+    # storage, FP64 complex for FP64 storage)
+    assert bsk >= b32 + 9 * 32 * 33 * 8 + 9 * 32 * 33 * 8
+    bsk64 = L.lb_workspace_size([c], L.LB_FP64, L.LB_FEATURE_STRUCTURE_FACTOR)
+    assert bsk64 >= b64 + 9 * 32 * 33 * 8 + 9 * 32 * 33 * 16
     two = L.lb_workspace_size([c, W.single_phase(128, 128)], L.LB_FP32_SHIFTED)
     assert two >= b32 + 2 * 9 * 128 * 128 * 4
 
@@ -135,9 +138,9 @@ def test_structure_factor_feature_size_rules():
         L.lb_workspace_size([W.single_phase(16, 16)], L.LB_FP32_SHIFTED, 2)
     assert e.value.status == L.LB_EINVAL
     # the 16384^2 workspace: two FP32 population buffers, the FP64 initial density, the
-    # accumulators and the row spectra of the nine modes
+    # accumulators and the FP32 complex row spectra of the nine modes
     n = 16384 * 16384
-    want = 2 * 9 * n * 4 + n * 8 + 9 * 16384 * 8193 * 8 + 9 * 16384 * 8193 * 16
+    want = 2 * 9 * n * 4 + n * 8 + 9 * 16384 * 8193 * 8 + 9 * 16384 * 8193 * 8
     b = L.lb_workspace_size([W.cfg5()], L.LB_FP32_SHIFTED, F)
     assert want <= b < want + (64 << 20)
 
