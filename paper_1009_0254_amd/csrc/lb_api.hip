@@ -699,6 +699,7 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
             q.split = sk_split(precision, q.ny);
             q.cpb = sk_cols_per_block(precision, q.nx, q.ny);
             q.rpb = sk_rows_per_block(q.nx, q.ny);
+            q.logrpb = ilog2(q.rpb);
             const int nh = q.nx / 2 + 1;
             q.row0 = rows;
             q.col0 = cols;

@@ -2,6 +2,8 @@
 // filter.  Twiddles w^t = exp(-2 pi i t / N), t < N/2, come from a table in global memory
 // (tw[t]) through a 3 KiB two-level copy in LDS: w^t = hi[t / 64] lo[t % 64] with
 // lo[l] = w^l and hi[h] = w^(64 h).  A transform of length n <= N uses every (N/n)-th.
+// Transforms are in place, decimation in time on bit-reversed input, in passes of up to
+// four radix-2 stages held in a lane's registers (radix 4, 8 or 16).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -75,61 +77,115 @@ __device__ __forceinline__ typename V2<T>::type twiddle(const TwCacheT<T> &Tc, i
     return cmul(Tc.hi[t >> 6], Tc.lo[t & (TW_LO - 1)]);
 }
 
-// `count` independent in-place decimation-in-time transforms of length n = 2^logn (n >= 2)
-// stored back to back in X (through lds_at), each already in bit-reversed order, with the
-// twiddles of an N-point table in T.  Pairs of radix-2 stages are fused into radix-4 passes
-// (the second stage's odd twiddle is the first's times w_4 = -i), with one radix-2 pass when
-// logn is odd.  INV uses the conjugate twiddles exp(+2 pi i k / n) and does not scale.  Ends
-// with a barrier.
-template <bool INV, typename T>
-__device__ void fft_lds(typename V2<T>::type *X, int n, int logn, int count, const TwCacheT<T> &Tc, int N)
+// w exp(-+2 pi i k / 16) (forward: minus; INV: plus), k a compile-time constant < 8
+template <bool INV, int K, typename C> __device__ __forceinline__ C rot16(C w)
+{
+    constexpr double c16[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                               0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
+    constexpr double s16[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                               1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+    typedef decltype(w.x) T;
+    if (K == 0) return w;
+    if (K == 4) return INV ? mk2(-w.y, w.x) : mk2(w.y, -w.x);   // times +i / -i
+    return cmul(w, mk2((T)c16[K], INV ? (T)s16[K] : (T)-s16[K]));
+}
+
+// butterflies of stage t of a radix-2^RL pass for the pairs (j, j + 2^t) with j mod 2^t = M,
+// twiddle w W_{2^(t+1)}^M, then the next M.  UNIT: w = 1 exactly (the first pass), so only
+// the constant roots are applied.
+template <bool INV, int RL, int t, int M, bool UNIT, typename C> __device__ __forceinline__ void stage_pairs(C *x, C w)
+{
+    if constexpr (M < (1 << t)) {
+        typedef decltype(w.x) T;
+        const C tw = rot16<INV, (M << (3 - t))>(UNIT ? mk2((T)1, (T)0) : w);
+#pragma unroll
+        for (int j0 = M; j0 < (1 << RL); j0 += 2 << t) {
+            const C u = x[j0];
+            const C v = UNIT && M == 0 ? x[j0 + (1 << t)] : cmul(tw, x[j0 + (1 << t)]);
+            x[j0] = cadd(u, v);
+            x[j0 + (1 << t)] = csub(u, v);
+        }
+        stage_pairs<INV, RL, t, M + 1, UNIT>(x, w);
+    }
+}
+
+// stages t .. RL-1 of a radix-2^RL pass on x[0 .. 2^RL), stage s + t of the transform
+template <bool INV, int RL, int t, bool UNIT, typename T>
+__device__ __forceinline__ void pass_stages(typename V2<T>::type *x, int pos, int s, const TwCacheT<T> &Tc, int N)
+{
+    if constexpr (t < RL) {
+        typename V2<T>::type w = mk2((T)1, (T)0);
+        if (!UNIT) {
+            w = twiddle(Tc, pos * (N >> (s + t)));
+            if (INV) w.y = -w.y;
+        }
+        stage_pairs<INV, RL, t, 0, UNIT>(x, w);
+        pass_stages<INV, RL, t + 1, UNIT>(x, pos, s, Tc, N);
+    }
+}
+
+// Stages s .. s + RL - 1 (a radix-2^RL pass) of `count` in-place decimation-in-time
+// transforms of length 2^logn held back to back in X (through lds_at).  Stage s + t pairs
+// elements i and i + 2^t q (q = 2^(s-1)) with twiddle W_{2^(s+t)}^(i mod 2^t q); a lane takes
+// the 2^RL elements base + j q, j < 2^RL, whose twiddles at stage t are W_{2^(s+t)}^pos (one
+// table lookup) times the constant W_{2^(t+1)}^(j mod 2^t).  FIRST: s = 1, where pos = 0 and
+// every looked-up twiddle is 1.  When q is a multiple of the pad period the lane's elements
+// sit a uniform stride apart.  Ends with a barrier.
+template <bool INV, int RL, bool FIRST, typename T>
+__device__ __forceinline__ void fft_pass(typename V2<T>::type *X, int logn, int count, int s, int sh,
+                                         const TwCacheT<T> &Tc, int N)
 {
     typedef typename V2<T>::type C;
-    const int sh = lds_pad_shift(logn);
-    int s = 1;
-    for (; s + 1 <= logn; s += 2) {
-        const int lq = s - 1, q = 1 << lq;
-        const int st1 = N >> s, st2 = N >> (s + 1);   // N / 2q and N / 4q
-        const int n4 = n >> 2, total = n4 * count;
-        for (int b = threadIdx.x; b < total; b += blockDim.x) {
-            const int g = b >> (logn - 2), bb = b & (n4 - 1);
-            const int pos = bb & (q - 1);
-            const int base = g * n + ((bb >> lq) << (lq + 2)) + pos;
-            const int i0 = lds_at(base, sh), i1 = lds_at(base + q, sh), i2 = lds_at(base + 2 * q, sh),
-                      i3 = lds_at(base + 3 * q, sh);
-            C w1 = twiddle(Tc, pos * st1), w2 = twiddle(Tc, pos * st2);
-            if (INV) {
-                w1.y = -w1.y;
-                w2.y = -w2.y;
-            }
-            const C a = X[i0], bv = X[i1], c = X[i2], d = X[i3];
-            const C b1 = cmul(w1, bv), d1 = cmul(w1, d);
-            const C a1 = cadd(a, b1), bq = csub(a, b1), c1 = cadd(c, d1), dq = csub(c, d1);
-            const C c2 = cmul(w2, c1);
-            C d2 = cmul(w2, dq);
-            d2 = INV ? mk2(-d2.y, d2.x) : mk2(d2.y, -d2.x);   // times +i / -i
-            X[i0] = cadd(a1, c2);
-            X[i2] = csub(a1, c2);
-            X[i1] = cadd(bq, d2);
-            X[i3] = csub(bq, d2);
+    constexpr int R = 1 << RL;
+    const int lq = s - 1, q = 1 << lq;
+    const int groups = (count << logn) >> RL, gmask = (1 << (logn - RL)) - 1;
+    const bool uniform = lq >= sh;
+    const int stride = q + (q >> sh);
+    for (int b = threadIdx.x; b < groups; b += blockDim.x) {
+        const int g = b >> (logn - RL), bb = b & gmask;
+        const int pos = bb & (q - 1);
+        const int base = (g << logn) + ((bb >> lq) << (lq + RL)) + pos;
+        C x[R];
+        if (uniform) {
+            const int a0 = lds_at(base, sh);
+#pragma unroll
+            for (int j = 0; j < R; ++j) x[j] = X[a0 + j * stride];
+            pass_stages<INV, RL, 0, FIRST, T>(x, pos, s, Tc, N);
+#pragma unroll
+            for (int j = 0; j < R; ++j) X[a0 + j * stride] = x[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) x[j] = X[lds_at(base + j * q, sh)];
+            pass_stages<INV, RL, 0, FIRST, T>(x, pos, s, Tc, N);
+#pragma unroll
+            for (int j = 0; j < R; ++j) X[lds_at(base + j * q, sh)] = x[j];
         }
-        __syncthreads();
     }
-    if (s == logn) {
-        const int half = 1 << (s - 1), st = N >> s, nb = n >> 1, total = nb * count;
-        for (int b = threadIdx.x; b < total; b += blockDim.x) {
-            const int g = b >> (logn - 1), bb = b & (nb - 1);
-            const int pos = bb & (half - 1);
-            const int e0 = g * n + ((bb >> (s - 1)) << s) + pos;
-            const int i0 = lds_at(e0, sh), i1 = lds_at(e0 + half, sh);
-            C w = twiddle(Tc, pos * st);
-            if (INV) w.y = -w.y;
-            const C u = X[i0], t = cmul(X[i1], w);
-            X[i0] = cadd(u, t);
-            X[i1] = csub(u, t);
-        }
-        __syncthreads();
+    __syncthreads();
+}
+
+// `count` independent in-place decimation-in-time transforms of length n = 2^logn (n >= 2)
+// stored back to back in X (through lds_at), each already in bit-reversed order, with the
+// twiddles of an N-point table in T: one pass of radix 2^(logn mod RMAX) for the first
+// stages, then radix-2^RMAX passes (each lane keeps 2^RMAX points in registers for RMAX
+// stages).  INV uses the conjugate twiddles exp(+2 pi i k / n) and does not scale.  Ends
+// with a barrier.
+template <bool INV, typename T, int RMAX = 4>
+__device__ __forceinline__ void fft_lds(typename V2<T>::type *X, int n, int logn, int count, const TwCacheT<T> &Tc,
+                                        int N)
+{
+    static_assert(RMAX >= 2 && RMAX <= 4, "radix 4, 8 or 16");
+    const int sh = lds_pad_shift(logn), rem = logn % RMAX;
+    (void)n;
+    if (rem == 1) fft_pass<INV, 1, true, T>(X, logn, count, 1, sh, Tc, N);
+    if (RMAX > 2 && rem == 2) fft_pass<INV, 2, true, T>(X, logn, count, 1, sh, Tc, N);
+    if (RMAX > 3 && rem == 3) fft_pass<INV, 3, true, T>(X, logn, count, 1, sh, Tc, N);
+    int s = 1 + rem;
+    if (rem == 0) {
+        fft_pass<INV, RMAX, true, T>(X, logn, count, 1, sh, Tc, N);
+        s += RMAX;
     }
+    for (; s <= logn; s += RMAX) fft_pass<INV, RMAX, false, T>(X, logn, count, s, sh, Tc, N);
 }
 
 }  // namespace lbf

@@ -134,8 +134,8 @@ struct SkRep {
     int32_t nx, ny, lognx, logny;
     int32_t split;      // column blocks per kx: 1, or 2 (one per output parity) when a column does not fit
     int32_t cpb;        // adjacent kx columns per column block (1 when split)
-    int32_t rpb;        // rows per row block
-    int32_t pad_;
+    int32_t rpb;        // rows per row block (a power of two)
+    int32_t logrpb;     // log2(rpb)
     int64_t row0;       // first row block of this replica (prefix of ceil(ny / rpb))
     int64_t col0;       // first column block (prefix of split * ceil(nh / cpb)), nh = nx/2 + 1
     int64_t soff;       // offset (complex elements) of its [ny][nh] spectrum inside one mode slot

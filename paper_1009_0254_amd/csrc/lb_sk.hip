@@ -5,13 +5,13 @@
 //
 // A sample covers a range of replicas of any sizes with two launches, whatever their sizes:
 //   1. rows: one workgroup per lattice row of any replica in the range.  It pulls the
-//      pre-collision populations, forms G of the nine moments in FP64 relative to those of
-//      node (0, 0), rounds them once to the transform precision (FP32 for FP32 storage, FP64
-//      for FP64 storage) and turns each real row of length nx into its half spectrum with
-//      one complex transform of length nx/2 (even samples as real part, odd as imaginary,
-//      then the standard split); it repeats this for the next G modes until all nine are
-//      done (the repeated pulls of the same row hit the caches), writing mode a to slot a
-//      of the spectra, [ny][nx/2+1] each;
+//      pre-collision populations, forms the nine moments relative to those of node (0, 0)
+//      in the transform precision (FP32 for FP32 storage, FP64 for FP64 storage) and turns
+//      each real row of length nx into its half spectrum with one complex transform of
+//      length nx/2 (even samples as real part, odd as imaginary, then the standard split),
+//      G modes at a time in LDS until all nine are done (for FP32 rows up to 8192 the
+//      moments stay in registers between groups; otherwise each group pulls again and the
+//      repeats hit the caches), writing mode a to slot a of the spectra, [ny][nx/2+1] each;
 //   2. columns: one workgroup per kx and mode reads its column of the row spectra in place
 //      (consecutive kx share cache lines and are kept on one XCD), transforms along y
 //      (a column longer than 64 KiB of LDS is split by one decimation-in-frequency stage
@@ -20,6 +20,7 @@
 //      [9][nx/2+1][ny].
 // Subtracting a constant per mode moves only k = 0, so the transforms see fluctuation-sized
 // values whatever the mean state: in FP32 their rounding is ~1e-7 of the spectrum's scale.
+// The transforms are lb_fftcore.h's radix-8 passes (radix 4 for the FP64 columns).
 // The radially binned density spectrum (the isotropic average of S_rho(k), used to follow
 // density modes after a quench to c_s^2 < 0, where M(k) of eq. (lb-lang-ft) has growing
 // eigenvalues) reuses 1-3 for mode 0 of one replica and bins |rho(k)|^2 / n with integer
@@ -76,7 +77,7 @@ __device__ __forceinline__ void load_pull(const S *__restrict__ P, int nx, int n
 }
 
 // m = T f with the integer rows of the moment basis of Table I
-__device__ __forceinline__ void moments9(const double g[9], double m[9])
+template <typename U> __device__ __forceinline__ void moments9(const U g[9], U m[9])
 {
     const double sa = (g[1] + g[2]) + (g[3] + g[4]);
     const double sd = (g[5] + g[6]) + (g[7] + g[8]);
@@ -92,31 +93,38 @@ __device__ __forceinline__ void moments9(const double g[9], double m[9])
     m[8] = 2 * g[0] - 4 * sa + 8 * sd;
 }
 
-// mode a of m = T f from the nine pulled values of one node (in FP64), with the expression
-// trees of moments9 for that mode only
-template <typename S> __device__ __forceinline__ double moment_of(int a, const S v[9])
+constexpr int SK_CACHE_PAIRS = 4;   // node pairs per lane whose moments stay in registers
+
+// The nine moments of nodes (x, y) and (x + 1, y) relative to those of node (0, 0), in Tt,
+// packed as (even, odd) complex pairs: the differences of the pulled values come first (for
+// values of one population they are exact or rounded at the fluctuation's own scale), then
+// the integer combinations of Table I.
+template <typename S, typename Tt>
+__device__ __forceinline__ void pair_moments(const S *__restrict__ P, int nx, int ny, int x, int y,
+                                             const Tt *v00, typename V2<Tt>::type m[9])
 {
-    auto g = [&](int i) { return (double)v[i]; };
-    switch (a) {
-    case 0: return g(0) + ((g(1) + g(2)) + (g(3) + g(4))) + ((g(5) + g(6)) + (g(7) + g(8)));
-    case 1: return (g(1) - g(3)) + (g(5) - g(7)) + (g(8) - g(6));
-    case 2: return (g(2) - g(4)) + (g(5) - g(7)) - (g(8) - g(6));
-    case 3: return -2 * g(0) + ((g(1) + g(2)) + (g(3) + g(4))) + 4 * ((g(5) + g(6)) + (g(7) + g(8)));
-    case 4: return (g(1) + g(3)) - (g(2) + g(4));
-    case 5: return (g(5) + g(7)) - (g(6) + g(8));
-    case 6: return -(g(1) - g(3)) + 2 * ((g(5) - g(7)) + (g(8) - g(6)));
-    case 7: return -(g(2) - g(4)) + 2 * ((g(5) - g(7)) - (g(8) - g(6)));
-    default: return 2 * g(0) - 4 * ((g(1) + g(2)) + (g(3) + g(4))) + 8 * ((g(5) + g(6)) + (g(7) + g(8)));
+    S v[2][9];
+    load_pull(P, nx, ny, x, y, v[0]);
+    load_pull(P, nx, ny, x + 1, y, v[1]);
+    Tt de[9], dd[9], me[9], mo[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        de[i] = (Tt)v[0][i] - v00[i];
+        dd[i] = (Tt)v[1][i] - v00[i];
     }
+    moments9(de, me);
+    moments9(dd, mo);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) m[a] = mk2(me[a], mo[a]);
 }
 
-// Transforms run in Tt (float for FP32 storage, double for FP64) on m_a(r) - m_a(0, 0): the
-// moments relative to those of node (0, 0), formed in FP64 and rounded once, so that the
-// transforms see fluctuation-sized values whatever the mean state; a constant only moves the
-// k = 0 coefficient, which the column pass restores in FP64 as X(0) + n m_a(0, 0).  The
-// block of row 0 stores m_a(0, 0) (with the storage shift) in base[9 r + a].  Each group of
-// G modes pulls the row again (the repeats hit L2 or the MALL).
-template <typename S, typename Tt>
+// Transforms run in Tt (float for FP32 storage, double for FP64) on m_a(r) - m_a(0, 0); a
+// constant only moves the k = 0 coefficient, which the column pass restores in FP64 as
+// X(0) + n m_a(0, 0).  The block of row 0 stores m_a(0, 0) (with the storage shift, in FP64)
+// in base[9 r + a].  CACHE: a lane's node pairs (at most SK_CACHE_PAIRS) are pulled once and
+// their nine moments kept in registers for all mode groups; otherwise each group of G modes
+// pulls the row again (the repeats hit L2 or the MALL).
+template <typename S, typename Tt, int RMAX, bool CACHE>
 __global__ void __launch_bounds__(SK_THREADS)
     k_sk_rows(const S *__restrict__ f, const RepDesc *__restrict__ reps, const SkRep *__restrict__ sk, int r0, int r1,
               long long row_base, long long nrows, int a_first, int a_count, int G, long long Ptot,
@@ -126,7 +134,7 @@ __global__ void __launch_bounds__(SK_THREADS)
     typedef typename V2<Tt>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ TwCacheT<Tt> T;
-    __shared__ double m00[9];
+    __shared__ Tt v00[9];
     C *X = reinterpret_cast<C *>(smem_raw);
     const long long lr = xcd_logical(nrows);
     if (lr < 0) return;
@@ -137,60 +145,78 @@ __global__ void __launch_bounds__(SK_THREADS)
     const RepDesc &d = reps[r];
     const int nx = q.nx, ny = q.ny, M = nx >> 1, logM = q.lognx - 1, nh = M + 1;
     const int y0 = (int)(gr - q.row0) * q.rpb;
-    const int R = min(q.rpb, ny - y0);          // rows of this block; transform (c, rr) at X[(c R + rr) M]
+    const int R = min(q.rpb, ny - y0);          // rows of this block
+    const int Rp = q.rpb, lRp = q.logrpb;       // transform (c, rr) at X[(c Rp + rr) M]
     const int pairs = R * M;
     const S *P = f + d.off;
     const int wstride = nmax / nx, sh = lds_pad_shift(logM);
     if (threadIdx.x == 0) {
         S v[9];
-        double g[9], m[9];
         load_pull(P, nx, ny, 0, 0, v);
-        for (int i = 0; i < 9; ++i) g[i] = (double)v[i];
-        moments9(g, m);
-        for (int i = 0; i < 9; ++i) m00[i] = m[i];
+        for (int i = 0; i < 9; ++i) v00[i] = (Tt)v[i];
         if (y0 == 0) {
-            for (int i = 0; i < 9; ++i) g[i] += d.shift[i];
+            double g[9], m[9];
+            for (int i = 0; i < 9; ++i) g[i] = (double)v[i] + d.shift[i];
             moments9(g, m);
             for (int i = 0; i < 9; ++i) base[9 * r + i] = m[i];
         }
     }
-    __syncthreads();   // m00
+    __syncthreads();   // v00
+    C cm[CACHE ? SK_CACHE_PAIRS : 1][9];
+    if (CACHE) {
+#pragma unroll
+        for (int j = 0; j < SK_CACHE_PAIRS; ++j) {
+            const int e = threadIdx.x + j * (int)blockDim.x;
+            if (e < pairs) {
+                const int rr = e >> logM, n = e & (M - 1);
+                pair_moments(P, nx, ny, 2 * n, y0 + rr, v00, cm[j]);
+            }
+        }
+    }
     for (int a0 = a_first; a0 < a_first + a_count; a0 += G) {
         const int gcount = min(G, a_first + a_count - a0);
-        // two pairs of nodes per lane and iteration, all 36 loads issued before use
-        for (int e0 = threadIdx.x; e0 < pairs; e0 += 2 * blockDim.x) {
-            const int e1 = e0 + blockDim.x < pairs ? e0 + blockDim.x : e0;
-            const int rr0 = e0 / M, n0 = e0 - rr0 * M, rr1 = e1 / M, n1 = e1 - rr1 * M;
-            S v[4][9];
-            load_pull(P, nx, ny, 2 * n0, y0 + rr0, v[0]);
-            load_pull(P, nx, ny, 2 * n0 + 1, y0 + rr0, v[1]);
-            load_pull(P, nx, ny, 2 * n1, y0 + rr1, v[2]);
-            load_pull(P, nx, ny, 2 * n1 + 1, y0 + rr1, v[3]);
-            for (int p = 0; p < 2; ++p) {
-                const int rr = p ? rr1 : rr0;
-                const unsigned j = bitrev((unsigned)(p ? n1 : n0), logM);
-                for (int c = 0; c < gcount; ++c) {
-                    const double mc = m00[a0 + c];
-                    X[lds_at((c * R + rr) * M + j, sh)] =
-                        mk2((Tt)(moment_of(a0 + c, v[2 * p]) - mc), (Tt)(moment_of(a0 + c, v[2 * p + 1]) - mc));
+        if (CACHE) {
+#pragma unroll
+            for (int j = 0; j < SK_CACHE_PAIRS; ++j) {
+                const int e = threadIdx.x + j * (int)blockDim.x;
+                if (e < pairs) {
+                    const int rr = e >> logM, n = e & (M - 1);
+                    const unsigned jb = bitrev((unsigned)n, logM);
+#pragma unroll
+                    for (int c = 0; c < 9; ++c)
+                        if (c >= a0 && c < a0 + gcount) X[lds_at((((c - a0) << lRp) + rr) * M + jb, sh)] = cm[j][c];
                 }
+            }
+        } else {
+            for (int e = threadIdx.x; e < pairs; e += blockDim.x) {
+                const int rr = e >> logM, n = e & (M - 1);
+                C m[9];
+                pair_moments(P, nx, ny, 2 * n, y0 + rr, v00, m);
+                const unsigned jb = bitrev((unsigned)n, logM);
+#pragma unroll
+                for (int c = 0; c < 9; ++c)
+                    if (c >= a0 && c < a0 + gcount) X[lds_at((((c - a0) << lRp) + rr) * M + jb, sh)] = m[c];
             }
         }
         __syncthreads();
-        fft_lds<false, Tt>(X, M, logM, gcount * R, T, nmax);
+        // slots rr >= R (the last rows of a replica) hold no data; their results are dropped
+        const int nt = gcount << lRp;
+        fft_lds<false, Tt, RMAX>(X, M, logM, nt, T, nmax);
         // X_k = E_k + W^k O_k with E = (Z_k + conj Z_{M-k}) / 2, O = (Z_k - conj Z_{M-k}) / 2i,
-        // W = exp(-2 pi i / nx), for k = 0..M (Z has period M)
+        // W = exp(-2 pi i / nx), for k = 0..M (Z has period M); k = M in the second loop
         const Tt h = (Tt)0.5;
-        for (int idx = threadIdx.x; idx < gcount * R * nh; idx += blockDim.x) {
-            const int t = idx / nh, k = idx - t * nh;     // t = c R + rr
-            const int c = t / R, rr = t - c * R;
+        auto untangle = [&](int t, int k) {
+            const int c = t >> lRp, rr = t & (Rp - 1);
+            if (rr >= R) return;
             const C Zk = X[lds_at(t * M + (k & (M - 1)), sh)];
             const C Zm = X[lds_at(t * M + ((M - k) & (M - 1)), sh)];
             const C E = mk2(h * (Zk.x + Zm.x), h * (Zk.y - Zm.y));
             const C O = mk2(h * (Zk.y + Zm.y), -h * (Zk.x - Zm.x));
             const C W = k < M ? twiddle(T, k * wstride) : mk2((Tt)-1, (Tt)0);
             spec[(a0 + c) * Ptot + q.soff + (long long)(y0 + rr) * nh + k] = cadd(E, cmul(W, O));
-        }
+        };
+        for (int idx = threadIdx.x; idx < nt << logM; idx += blockDim.x) untangle(idx >> logM, idx & (M - 1));
+        for (int t = threadIdx.x; t < nt; t += blockDim.x) untangle(t, M);
         __syncthreads();   // X is reused by the next group
     }
 }
@@ -201,7 +227,7 @@ __global__ void __launch_bounds__(SK_THREADS)
 // k = 0 coefficient restored to X(0) + n m_a(0, 0) (the row pass transformed moments
 // relative to node (0, 0)).  SNAP writes |X|^2 / n to plane ([nh][ny], one replica),
 // otherwise adds it to the accumulators.
-template <typename Tt, bool SNAP>
+template <typename Tt, bool SNAP, int RMAX>
 __global__ void __launch_bounds__(SK_THREADS)
     k_sk_cols(const typename V2<Tt>::type *__restrict__ spec, const SkRep *__restrict__ sk, int r0, int r1,
               long long col_base, long long ncols, long long Ptot, int a_first, double *__restrict__ acc,
@@ -230,19 +256,18 @@ __global__ void __launch_bounds__(SK_THREADS)
     const double k0 = kx0 == 0 && par == 0 ? (double)q.nx * (double)ny * base[9 * r + a] : 0.0;
     const int L = ny / split, logL = q.logny - (split - 1), sh = lds_pad_shift(logL);
     if (split == 1) {
-        const int tot = C_ * ny;
+        // lanes over (y, c) with c < Cp = 2^ceil(log2 C_); c >= C_ idle
+        const int lCp = C_ > 1 ? 32 - __clz(C_ - 1) : 0, tot = ny << lCp;
         for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * blockDim.x) {
             C v[4];
             for (int u = 0; u < 4; ++u) {
-                const int e = min(e0 + u * (int)blockDim.x, tot - 1), y = e / C_, c = e - y * C_;
+                const int e = min(e0 + u * (int)blockDim.x, tot - 1), y = e >> lCp;
+                const int c = min(e & ((1 << lCp) - 1), C_ - 1);
                 v[u] = S0[(long long)y * nh + c];
             }
             for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * (int)blockDim.x;
-                if (e < tot) {
-                    const int y = e / C_, c = e - y * C_;
-                    X[lds_at(c * ny + bitrev((unsigned)y, logL), sh)] = v[u];
-                }
+                const int e = e0 + u * (int)blockDim.x, y = e >> lCp, c = e & ((1 << lCp) - 1);
+                if (e < tot && c < C_) X[lds_at(c * ny + bitrev((unsigned)y, logL), sh)] = v[u];
             }
         }
     } else {
@@ -254,7 +279,7 @@ __global__ void __launch_bounds__(SK_THREADS)
         }
     }
     __syncthreads();
-    fft_lds<false, Tt>(X, L, logL, split == 1 ? C_ : 1, T, nmax);
+    fft_lds<false, Tt, RMAX>(X, L, logL, split == 1 ? C_ : 1, T, nmax);
     const int tot = (split == 1 ? C_ : 1) * L;
     auto power = [&](int e) {
         const C v = X[lds_at(e, sh)];
@@ -264,7 +289,7 @@ __global__ void __launch_bounds__(SK_THREADS)
     if (SNAP) {
         double *D = plane + (long long)kx0 * ny;
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            const int c = e / L, k = e - c * L;
+            const int c = e >> logL, k = e & (L - 1);
             D[(long long)c * ny + k * split + par] = power(e);
         }
     } else {
@@ -272,13 +297,13 @@ __global__ void __launch_bounds__(SK_THREADS)
         for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * blockDim.x) {
             double old[4];
             for (int u = 0; u < 4; ++u) {
-                const int e = min(e0 + u * (int)blockDim.x, tot - 1), c = e / L, k = e - c * L;
+                const int e = min(e0 + u * (int)blockDim.x, tot - 1), c = e >> logL, k = e & (L - 1);
                 old[u] = A[(long long)c * ny + k * split + par];
             }
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u * (int)blockDim.x;
                 if (e < tot) {
-                    const int c = e / L, k = e - c * L;
+                    const int c = e >> logL, k = e & (L - 1);
                     A[(long long)c * ny + k * split + par] = old[u] + power(e);
                 }
             }
@@ -356,11 +381,16 @@ __global__ void k_sk_read(const double *__restrict__ acc, double *__restrict__ o
     }
 }
 
-template <typename S, typename Tt>
+// radix of the in-LDS passes: 8, except 4 for the FP64 column transforms (at 8 their
+// registers allow only one 1024-lane workgroup per CU)
+template <typename Tt> constexpr int SK_ROW_RADIX = 3;
+template <typename Tt> constexpr int SK_COL_RADIX = sizeof(Tt) == 4 ? 3 : 2;
+
+template <typename S, typename Tt, int RMAX, bool CACHE>
 void rows_kernel(const SkLaunch &a, int a_first, int a_count, int G, int threads, hipStream_t s)
 {
     const size_t lds = (size_t)sk_elem(sizeof(Tt) == 8 ? 0 : 1) * lds_padded((long long)G * (a.lds_rows / 2));
-    hipLaunchKernelGGL((k_sk_rows<S, Tt>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s, (const S *)a.f,
+    hipLaunchKernelGGL((k_sk_rows<S, Tt, RMAX, CACHE>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s, (const S *)a.f,
                        a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
                        (long long)a.Ptot, (typename V2<Tt>::type *)a.spec, a.base, (const double2 *)a.tw, a.nmax);
 }
@@ -369,25 +399,40 @@ hipError_t launch_rows(int precision, const SkLaunch &a, int a_first, int a_coun
 {
     const int G = a_count < a.G ? a_count : a.G;
     const int threads = sk_threads(a.lds_rows);
+    // FP32: with at most SK_CACHE_PAIRS node pairs per lane the nine moments stay in
+    // registers across the mode groups (FP64 would spill)
+    const bool cache = precision != 0 && a_count > G && a.lds_rows / 2 <= SK_CACHE_PAIRS * threads;
     if (precision == 0)
-        rows_kernel<double, double>(a, a_first, a_count, G, threads, s);
+        rows_kernel<double, double, SK_ROW_RADIX<double>, false>(a, a_first, a_count, G, threads, s);
+    else if (cache)
+        rows_kernel<float, float, SK_ROW_RADIX<float>, true>(a, a_first, a_count, G, threads, s);
     else
-        rows_kernel<float, float>(a, a_first, a_count, G, threads, s);
+        rows_kernel<float, float, SK_ROW_RADIX<float>, false>(a, a_first, a_count, G, threads, s);
     return hipGetLastError();
 }
 
 template <typename Tt, bool SNAP>
 void cols_kernel(int precision, const SkLaunch &a, unsigned modes, double *plane, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sk_cols<Tt, SNAP>), dim3(xcd_grid(a.cols), modes), dim3(sk_threads(a.lds_cols)),
-                       (size_t)sk_elem(precision) * lds_padded(a.lds_cols), s, (const typename V2<Tt>::type *)a.spec, a.sk, a.r0,
-                       a.r1, (long long)a.col_base, (long long)a.cols, (long long)a.Ptot, 0, SNAP ? nullptr : a.acc,
-                       plane, (const double *)a.base, (const double2 *)a.tw, a.nmax);
+    hipLaunchKernelGGL((k_sk_cols<Tt, SNAP, SK_COL_RADIX<Tt>>), dim3(xcd_grid(a.cols), modes),
+                       dim3(sk_threads(a.lds_cols)), (size_t)sk_elem(precision) * lds_padded(a.lds_cols), s,
+                       (const typename V2<Tt>::type *)a.spec, a.sk, a.r0, a.r1, (long long)a.col_base,
+                       (long long)a.cols, (long long)a.Ptot, 0, SNAP ? nullptr : a.acc, plane, (const double *)a.base,
+                       (const double2 *)a.tw, a.nmax);
 }
 
 template <typename K> hipError_t lds_limit(K kernel, size_t bytes)
 {
     return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename S, typename Tt> hipError_t lds_limits_of(size_t rows, size_t cols)
+{
+    hipError_t e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, false>, rows);
+    if (e == hipSuccess && sizeof(Tt) == 4) e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, true>, rows);
+    if (e == hipSuccess) e = lds_limit(k_sk_cols<Tt, false, SK_COL_RADIX<Tt>>, cols);
+    if (e == hipSuccess) e = lds_limit(k_sk_cols<Tt, true, SK_COL_RADIX<Tt>>, cols);
+    return e;
 }
 
 }  // namespace
@@ -416,17 +461,7 @@ hipError_t set_sk_lds_limits(int precision, int G, int max_row, int max_col)
 {
     const size_t rows = (size_t)sk_elem(precision) * lds_padded((long long)G * (max_row / 2)),
                  cols = (size_t)sk_elem(precision) * lds_padded(max_col);
-    hipError_t e;
-    if (precision == 0) {
-        e = lds_limit(k_sk_rows<double, double>, rows);
-        if (e == hipSuccess) e = lds_limit(k_sk_cols<double, false>, cols);
-        if (e == hipSuccess) e = lds_limit(k_sk_cols<double, true>, cols);
-    } else {
-        e = lds_limit(k_sk_rows<float, float>, rows);
-        if (e == hipSuccess) e = lds_limit(k_sk_cols<float, false>, cols);
-        if (e == hipSuccess) e = lds_limit(k_sk_cols<float, true>, cols);
-    }
-    return e;
+    return precision == 0 ? lds_limits_of<double, double>(rows, cols) : lds_limits_of<float, float>(rows, cols);
 }
 
 hipError_t launch_sk_sample(int precision, const SkLaunch &a, hipStream_t s)
