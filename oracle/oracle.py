@@ -254,6 +254,25 @@ def power_spectrum(m: np.ndarray) -> np.ndarray:
     return (F.real ** 2 + F.imag ** 2) / n
 
 
+def power_at(a: np.ndarray, kx, ky) -> np.ndarray:
+    """|a(k)|^2 with a(k) = n^-1/2 sum_r e^{ik.r} a(r) (Sec. III notation) of one real field
+    a[ny][nx], at the lattice wave vectors k = (2 pi kx / nx, 2 pi ky / ny) listed in kx, ky:
+    the double sum itself, taken over x for each listed kx (two real matrix-vector products)
+    and then over y."""
+    ny, nx = a.shape
+    x, y = np.arange(nx), np.arange(ny)
+    rows = {}
+    out = np.empty(len(kx))
+    for i, (p, q) in enumerate(zip(kx, ky)):
+        if p not in rows:
+            ph = 2 * np.pi * ((p * x) % nx) / nx
+            rows[p] = a @ np.cos(ph) + 1j * (a @ np.sin(ph))   # sum_x a(x, y) e^{i kx x}
+        ph = 2 * np.pi * ((q * y) % ny) / ny
+        c = np.dot(np.cos(ph) + 1j * np.sin(ph), rows[p])
+        out[i] = (c.real ** 2 + c.imag ** 2) / (nx * ny)
+    return out
+
+
 def radial_shell(kx, ky, nx: int, ny: int):
     """Shell index of the lattice wave vector k = (2 pi kx / nx, 2 pi ky / ny) (integer kx, ky,
     any sign): b = floor(|k| L / 2 pi + 1/2) with L = min(nx, ny), i.e. shells of width

@@ -191,7 +191,7 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
         L.sk_reps = o; o += align_up(sizeof(SkRep) * n_rep);
         L.spec = o; o += align_up((size_t)sk_elem(precision) * 9 * (size_t)L.sk_ptot);
         L.acc = o; o += align_up(sizeof(double) * L.acc_elems);
-        L.sk_base = o; o += align_up(sizeof(double) * 9 * (size_t)n_rep);
+        L.sk_base = o; o += align_up(sizeof(double) * 18 * (size_t)n_rep);
     }
     if (L.cn_nodes > 0) {
         L.xi = o; o += align_up((size_t)2 * L.cn_nodes * elem_size(precision));

@@ -155,7 +155,7 @@ struct SkLaunch {
     int64_t Ptot;             // complex elements per mode slot (sum of ny * nh over all replicas)
     void *spec;               // nine mode slots of row spectra (float2 for FP32 storage, else double2)
     double *acc;
-    double *base;             // [replica][9]: the moments of node (0, 0) of the last sample
+    double *base;             // [replica][18]: reference moments (FP64) and populations of the last sample
     const double *tw;         // exp(-2 pi i j / nmax), j < nmax/2
     int32_t nmax;
 };

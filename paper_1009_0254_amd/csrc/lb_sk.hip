@@ -5,8 +5,9 @@
 //
 // A sample covers a range of replicas of any sizes with two launches, whatever their sizes:
 //   1. rows: one workgroup per lattice row of any replica in the range.  It pulls the
-//      pre-collision populations, forms the nine moments relative to those of node (0, 0)
-//      in the transform precision (FP32 for FP32 storage, FP64 for FP64 storage) and turns
+//      pre-collision populations, forms the nine moments relative to those of a reference
+//      (the mean pulled populations of row 0, from a one-block-per-replica pre-pass) in the
+//      transform precision (FP32 for FP32 storage, FP64 for FP64 storage) and turns
 //      each real row of length nx into its half spectrum with one complex transform of
 //      length nx/2 (even samples as real part, odd as imaginary, then the standard split),
 //      G modes at a time in LDS until all nine are done (for FP32 rows up to 8192 the
@@ -18,8 +19,10 @@
 //      into two half-length transforms, one per output parity, so that it fits), restores
 //      the k = 0 coefficient in FP64 and adds |X|^2 / n to the FP64 accumulators
 //      [9][nx/2+1][ny].
-// Subtracting a constant per mode moves only k = 0, so the transforms see fluctuation-sized
-// values whatever the mean state: in FP32 their rounding is ~1e-7 of the spectrum's scale.
+// Subtracting a constant per mode moves only k = 0; with the row-0 mean as that constant the
+// transforms see fluctuation-sized values whatever the mean state, and so do the row sums
+// (kx = 0) and totals, whose remaining offset is of the order of their own fluctuation: in
+// FP32 the rounding is ~1e-7 of the spectrum's scale.
 // The transforms are lb_fftcore.h's radix-8 passes (radix 4 for the FP64 columns).
 // The radially binned density spectrum (the isotropic average of S_rho(k), used to follow
 // density modes after a quench to c_s^2 < 0, where M(k) of eq. (lb-lang-ft) has growing
@@ -95,13 +98,13 @@ template <typename U> __device__ __forceinline__ void moments9(const U g[9], U m
 
 constexpr int SK_CACHE_PAIRS = 4;   // node pairs per lane whose moments stay in registers
 
-// The nine moments of nodes (x, y) and (x + 1, y) relative to those of node (0, 0), in Tt,
+// The nine moments of nodes (x, y) and (x + 1, y) relative to those of the reference, in Tt,
 // packed as (even, odd) complex pairs: the differences of the pulled values come first (for
 // values of one population they are exact or rounded at the fluctuation's own scale), then
 // the integer combinations of Table I.
 template <typename S, typename Tt>
 __device__ __forceinline__ void pair_moments(const S *__restrict__ P, int nx, int ny, int x, int y,
-                                             const Tt *v00, typename V2<Tt>::type m[9])
+                                             const Tt *vref, typename V2<Tt>::type m[9])
 {
     S v[2][9];
     load_pull(P, nx, ny, x, y, v[0]);
@@ -109,8 +112,8 @@ __device__ __forceinline__ void pair_moments(const S *__restrict__ P, int nx, in
     Tt de[9], dd[9], me[9], mo[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        de[i] = (Tt)v[0][i] - v00[i];
-        dd[i] = (Tt)v[1][i] - v00[i];
+        de[i] = (Tt)v[0][i] - vref[i];
+        dd[i] = (Tt)v[1][i] - vref[i];
     }
     moments9(de, me);
     moments9(dd, mo);
@@ -118,23 +121,67 @@ __device__ __forceinline__ void pair_moments(const S *__restrict__ P, int nx, in
     for (int a = 0; a < 9; ++a) m[a] = mk2(me[a], mo[a]);
 }
 
-// Transforms run in Tt (float for FP32 storage, double for FP64) on m_a(r) - m_a(0, 0); a
-// constant only moves the k = 0 coefficient, which the column pass restores in FP64 as
-// X(0) + n m_a(0, 0).  The block of row 0 stores m_a(0, 0) (with the storage shift, in FP64)
-// in base[9 r + a].  CACHE: a lane's node pairs (at most SK_CACHE_PAIRS) are pulled once and
+constexpr int SK_REF_THREADS = 256;
+
+// The reference of replica r: the mean over row 0 of each pulled population, in FP64 with a
+// fixed-order reduction, rounded to the transform type: vref_i = base[18 r + 9 + i].  Every
+// node's moments are transformed relative to m(vref), whose distance from the replica's mean
+// is ~ sigma / sqrt(nx), so that neither the row sums (kx = 0) nor the totals carry an offset
+// that FP32 would have to resolve against the fluctuations.  base[18 r + a] = m_a(vref + shift)
+// in FP64, the constant the column pass restores at k = 0.
+template <typename S, typename Tt>
+__global__ void __launch_bounds__(SK_REF_THREADS)
+    k_sk_ref(const S *__restrict__ f, const RepDesc *__restrict__ reps, const SkRep *__restrict__ sk, int r0,
+             double *__restrict__ base)
+{
+    __shared__ double part[SK_REF_THREADS / 64][9];
+    const int r = r0 + (int)blockIdx.x;
+    const SkRep &q = sk[r];
+    const RepDesc &d = reps[r];
+    const S *P = f + d.off;
+    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int x = threadIdx.x; x < q.nx; x += blockDim.x) {
+        S v[9];
+        load_pull(P, q.nx, q.ny, x, 0, v);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) s[i] += (double)v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        for (int o = 32; o > 0; o >>= 1) s[i] += __shfl_xor(s[i], o);
+    if ((threadIdx.x & 63) == 0)
+        for (int i = 0; i < 9; ++i) part[threadIdx.x >> 6][i] = s[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double g[9], m[9];
+        for (int i = 0; i < 9; ++i) {
+            double t = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w][i];
+            const double vr = (double)(Tt)(t / q.nx);
+            base[18 * r + 9 + i] = vr;
+            g[i] = vr + d.shift[i];
+        }
+        moments9(g, m);
+        for (int a = 0; a < 9; ++a) base[18 * r + a] = m[a];
+    }
+}
+
+// Transforms run in Tt (float for FP32 storage, double for FP64) on m_a(r) - m_a(vref) (the
+// reference of k_sk_ref); a constant only moves the k = 0 coefficient, which the column pass
+// restores in FP64 as X(0) + n m_a(vref + shift).  CACHE: a lane's node pairs (at most SK_CACHE_PAIRS) are pulled once and
 // their nine moments kept in registers for all mode groups; otherwise each group of G modes
 // pulls the row again (the repeats hit L2 or the MALL).
 template <typename S, typename Tt, int RMAX, bool CACHE>
 __global__ void __launch_bounds__(SK_THREADS)
     k_sk_rows(const S *__restrict__ f, const RepDesc *__restrict__ reps, const SkRep *__restrict__ sk, int r0, int r1,
               long long row_base, long long nrows, int a_first, int a_count, int G, long long Ptot,
-              typename V2<Tt>::type *__restrict__ spec, double *__restrict__ base, const double2 *__restrict__ tw,
-              int nmax)
+              typename V2<Tt>::type *__restrict__ spec, const double *__restrict__ base,
+              const double2 *__restrict__ tw, int nmax)
 {
     typedef typename V2<Tt>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ TwCacheT<Tt> T;
-    __shared__ Tt v00[9];
+    __shared__ Tt vref[9];
     C *X = reinterpret_cast<C *>(smem_raw);
     const long long lr = xcd_logical(nrows);
     if (lr < 0) return;
@@ -150,18 +197,8 @@ __global__ void __launch_bounds__(SK_THREADS)
     const int pairs = R * M;
     const S *P = f + d.off;
     const int wstride = nmax / nx, sh = lds_pad_shift(logM);
-    if (threadIdx.x == 0) {
-        S v[9];
-        load_pull(P, nx, ny, 0, 0, v);
-        for (int i = 0; i < 9; ++i) v00[i] = (Tt)v[i];
-        if (y0 == 0) {
-            double g[9], m[9];
-            for (int i = 0; i < 9; ++i) g[i] = (double)v[i] + d.shift[i];
-            moments9(g, m);
-            for (int i = 0; i < 9; ++i) base[9 * r + i] = m[i];
-        }
-    }
-    __syncthreads();   // v00
+    if (threadIdx.x < 9) vref[threadIdx.x] = (Tt)base[18 * r + 9 + threadIdx.x];
+    __syncthreads();   // vref (the reference)
     C cm[CACHE ? SK_CACHE_PAIRS : 1][9];
     if (CACHE) {
 #pragma unroll
@@ -169,7 +206,7 @@ __global__ void __launch_bounds__(SK_THREADS)
             const int e = threadIdx.x + j * (int)blockDim.x;
             if (e < pairs) {
                 const int rr = e >> logM, n = e & (M - 1);
-                pair_moments(P, nx, ny, 2 * n, y0 + rr, v00, cm[j]);
+                pair_moments(P, nx, ny, 2 * n, y0 + rr, vref, cm[j]);
             }
         }
     }
@@ -191,7 +228,7 @@ __global__ void __launch_bounds__(SK_THREADS)
             for (int e = threadIdx.x; e < pairs; e += blockDim.x) {
                 const int rr = e >> logM, n = e & (M - 1);
                 C m[9];
-                pair_moments(P, nx, ny, 2 * n, y0 + rr, v00, m);
+                pair_moments(P, nx, ny, 2 * n, y0 + rr, vref, m);
                 const unsigned jb = bitrev((unsigned)n, logM);
 #pragma unroll
                 for (int c = 0; c < 9; ++c)
@@ -224,8 +261,8 @@ __global__ void __launch_bounds__(SK_THREADS)
 // column transforms of every replica in the range, reading the row spectra in place;
 // mode a = a_first + blockIdx.y.  A block takes cpb adjacent kx (reads coalesced along kx)
 // or, for split lines, one kx and one output parity.  |X|^2 is formed in FP64, with the
-// k = 0 coefficient restored to X(0) + n m_a(0, 0) (the row pass transformed moments
-// relative to node (0, 0)).  SNAP writes |X|^2 / n to plane ([nh][ny], one replica),
+// k = 0 coefficient restored to X(0) + n m_a(vref + shift) (the row pass transformed moments
+// relative to the reference of k_sk_ref).  SNAP writes |X|^2 / n to plane ([nh][ny], one replica),
 // otherwise adds it to the accumulators.
 template <typename Tt, bool SNAP, int RMAX>
 __global__ void __launch_bounds__(SK_THREADS)
@@ -253,7 +290,7 @@ __global__ void __launch_bounds__(SK_THREADS)
     const C *S0 = spec + a * Ptot + q.soff + kx0;    // (y, c) at S0[y * nh + c]
     const double inv_n = 1.0 / ((double)q.nx * (double)ny);
     // added to the real part of output 0 of this block when that output is k = 0
-    const double k0 = kx0 == 0 && par == 0 ? (double)q.nx * (double)ny * base[9 * r + a] : 0.0;
+    const double k0 = kx0 == 0 && par == 0 ? (double)q.nx * (double)ny * base[18 * r + a] : 0.0;
     const int L = ny / split, logL = q.logny - (split - 1), sh = lds_pad_shift(logL);
     if (split == 1) {
         // lanes over (y, c) with c < Cp = 2^ceil(log2 C_); c >= C_ idle
@@ -397,6 +434,12 @@ void rows_kernel(const SkLaunch &a, int a_first, int a_count, int G, int threads
 
 hipError_t launch_rows(int precision, const SkLaunch &a, int a_first, int a_count, hipStream_t s)
 {
+    if (precision == 0)
+        hipLaunchKernelGGL((k_sk_ref<double, double>), dim3((unsigned)(a.r1 - a.r0)), dim3(SK_REF_THREADS), 0, s,
+                           (const double *)a.f, a.reps, a.sk, a.r0, a.base);
+    else
+        hipLaunchKernelGGL((k_sk_ref<float, float>), dim3((unsigned)(a.r1 - a.r0)), dim3(SK_REF_THREADS), 0, s,
+                           (const float *)a.f, a.reps, a.sk, a.r0, a.base);
     const int G = a_count < a.G ? a_count : a.G;
     const int threads = sk_threads(a.lds_rows);
     // FP32: with at most SK_CACHE_PAIRS node pairs per lane the nine moments stay in

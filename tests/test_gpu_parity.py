@@ -309,7 +309,7 @@ def fp64_spectrum_tol(n, smax):
     return 1e-10 + 8 * 2 * eps * np.log2(n) * n / np.sqrt(n * smax)
 
 
-SK_SHAPES = [(64, 32), (16384, 16), (16, 16384), (16, 8192), (2048, 8), (4, 4)]
+SK_SHAPES = [(64, 32), (16384, 16), (16, 16384), (16, 8192), (2048, 8), (4096, 64), (8192, 16), (4, 4)]
 
 
 @pytest.mark.parametrize("shape", SK_SHAPES, ids=[f"{a}x{b}" for a, b in SK_SHAPES])
@@ -317,7 +317,8 @@ SK_SHAPES = [(64, 32), (16384, 16), (16, 16384), (16, 8192), (2048, 8), (4, 4)]
 def test_structure_factor_matches_oracle_fft(precision, shape):
     """All nine |m_a(k)|^2 against numpy's FFT of the oracle's moments: rows of length 16384
     (real-to-complex split), columns of 8192 and 16384 (one decimation-in-frequency stage),
-    several modes per pass (2048 wide: 8 + 1) and the smallest lattice."""
+    all nine modes per pass (up to 2048 wide), rows of 4096 and 8192 whose FP32 moments stay
+    in registers across mode groups (8 + 1 and 4 + 4 + 1), and the smallest lattice."""
     L = _L()
     nx, ny = shape
     cfg = W.single_phase(nx, ny, kT=1e-5, seed=31)
@@ -491,6 +492,49 @@ def test_full_size_8192_sampled_parity():
     t = lat.totals()
     assert abs(t[0] - 8192.0 * 8192.0) / (8192.0 * 8192.0) < 1e-9
     lat.close()
+
+
+def test_full_size_8192_structure_factor_sampled():
+    """One S(k) sample of the bench workload (8192^2 single phase, FP32-shifted storage, the
+    batched launch bench.py times) after two steps against the oracle's |m_a(k)|^2 / n of its
+    own moments at 36 k per mode: k = 0 (restored in FP64 by the column pass), kx = 1, the
+    Nyquist column and row, and random k.  Gates: off k = 0, 1e-4 of the mode's variance (the
+    mean of S_a over k != 0).  At k = 0, relative to max(S_a(0), variance): 1e-5 for the
+    conserved rho, jx, jy (their totals are exact on both sides; the FP32 transform rounds X(0)
+    by ~ eps32 sqrt(log2 n) |m'|_2, ~6e-7 of the variance in S_a(0)); 1e-3 for the other modes,
+    whose X(0) = sum_r m_a(r) adds the FP32 trajectory's per-node differences (1.6e-7 of the
+    range after two steps) coherently, up to ~ sqrt(n) 1.6e-7 ~ 1e-2 in the worst case."""
+    L = _L()
+    cfg = W.cfg3()
+    nx, ny = cfg["nx"], cfg["ny"]
+    lat = L.Lattice(cfg, precision=2, structure_factor=True)
+    ora = O.Oracle(cfg)
+    lat.step(2)
+    ora.step(2)
+    lat.lb_structure_factor(L.LB_SK_SAMPLE, -1)
+    S, ns = lat.lb_structure_factor(L.LB_SK_READ, 0)
+    assert ns == 1
+    rng = np.random.default_rng(11)
+    kxs = [0, 1, nx // 2] + [int(v) for v in rng.integers(2, nx // 2, size=3)]
+    kys = [0, 1, ny // 2] + [int(v) for v in rng.integers(2, ny, size=3)]
+    px = [a for a in kxs for b in kys]
+    py = [b for a in kxs for b in kys]
+    got = S[:, torch.tensor(py, device=S.device), torch.tensor(px, device=S.device)].cpu().numpy()
+    del S
+    lat.close()
+    mo = ora.moments()
+    del ora
+    e0, err = np.zeros(9), np.zeros(9)
+    for a in range(9):
+        want = O.power_at(mo[a], px, py)
+        var = mo[a].var()
+        e0[a] = abs(got[a, 0] - want[0]) / max(want[0], var)
+        err[a] = np.abs(got[a, 1:] - want[1:]).max() / var
+        worst = np.argsort(-np.abs(got[a] - want))[:3]
+        say("8192^2 S(k) mode", a, "k=0 rel err", e0[a], "err / var", err[a], "worst (kx, ky, got, want):",
+            [(px[i], py[i], float(got[a, i]), float(want[i])) for i in worst])
+    assert e0[:3].max() < 1e-5 and e0[3:].max() < 1e-3
+    assert err.max() < 1e-4
 
 
 # ------------------------------------------------------------------ equipartition on the GPU

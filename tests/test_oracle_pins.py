@@ -582,6 +582,27 @@ def test_radial_spectrum_parseval_and_counts():
         assert np.isclose((mean * counts).sum(), ((rho - rho.mean()) ** 2).sum(), rtol=1e-12)
 
 
+def test_power_at_equals_numpy_fft_and_a_plane_wave():
+    """The oracle's single-k power (the double sum) equals numpy's FFT at every half-plane k
+    of random fields, wraps negative and large indices, and puts a plane wave's power
+    (a n / 2)^2 / n at +-k only."""
+    rng = np.random.default_rng(9)
+    for nx, ny in [(16, 32), (8, 8), (32, 4)]:
+        f = rng.standard_normal((ny, nx))
+        want = np.abs(np.fft.rfft2(f)) ** 2 / (nx * ny)
+        KY, KX = np.mgrid[0:ny, 0:nx // 2 + 1]
+        got = O.power_at(f, KX.ravel(), KY.ravel()).reshape(KY.shape)
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * want.max())
+        # |a(k)|^2 = |a(-k)|^2 and k is periodic
+        assert np.allclose(O.power_at(f, [-1, 1 + nx], [-2, 2 + ny]), O.power_at(f, [1, 1], [2, 2]), rtol=1e-12)
+    nx, ny, a = 64, 32, 1e-3
+    y, x = np.mgrid[0:ny, 0:nx]
+    w = a * np.cos(2 * np.pi * (3 * x / nx + 5 * y / ny))
+    p = O.power_at(w, [3, 61, 3, 4], [5, 27, 6, 5])
+    assert np.allclose(p[:2], (a * nx * ny / 2) ** 2 / (nx * ny), rtol=1e-12)
+    assert np.all(p[2:] < 1e-24)
+
+
 def test_radial_spectrum_of_a_plane_wave():
     nx = ny = 64
     a = 1e-3
