@@ -118,7 +118,7 @@ def cpu_baseline(torch, L, cfg, steps):
     return out, err
 
 
-def cpu_baseline_one_core(cfg, side=2048, steps=2):
+def cpu_baseline_one_core(cfg, side=2048, steps=4):
     """The oracle on one host core (a child process with OMP_NUM_THREADS=1) on a side x side
     crop of the same workload."""
     import subprocess
@@ -146,7 +146,7 @@ def main():
     ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-sk", action="store_true", help="skip timing one S(k) sample")
     ap.add_argument("--no-correlated", action="store_true",
                     help="skip timing the same lattice with spatially correlated noise")
