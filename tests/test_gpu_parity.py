@@ -685,6 +685,31 @@ def test_correlated_noise_parity(precision):
         assert e.max() < 2e-3
 
 
+CN_SHAPES = [(8192, 16, 4), (16, 8192, 4), (2048, 2048, 2)]
+
+
+@pytest.mark.parametrize("shape", CN_SHAPES, ids=[f"{a}x{b}" for a, b, _ in CN_SHAPES])
+@pytest.mark.parametrize("precision", [2, 0])
+def test_correlated_noise_parity_long_lines(precision, shape):
+    """The correlated-noise filter at the bench's line lengths: 8192-point rows (one block per
+    row) and columns (several adjacent columns per block for the 16 narrow ones), and a 2048^2
+    lattice, on the bench's single-phase parameters with the exact Xi(k) noise, against the
+    oracle's numpy-FFT fields and FP64 step.  FP32-shifted gate 1e-4 of the fluctuation range:
+    the fields go through FP32 transforms (rounding ~ 3e-7 of their scale) on top of FP32
+    normals (3e-6 per draw)."""
+    nx, ny, steps = shape
+    cfg = dict(W.cfg3(), nx=nx, ny=ny, noise="correlated", seed=17)
+    mg, mo = run_pair(cfg, precision, steps, chunks=2)
+    e = rel_err(mg, mo)
+    if precision == 0:
+        ok, err = abs_ok(mg, mo)
+        say("correlated", nx, ny, "fp64 abs err", err.max(), "normalised", e.max())
+        assert ok
+    else:
+        say("correlated", nx, ny, "fp32s err", e)
+        assert e.max() < 1e-4
+
+
 def test_correlated_and_uncorrelated_replicas_in_one_handle():
     L = _L()
     cfgs = [W.e3(32, 32, kT=1e-6, seed=1), W.e4(48, 40, kT=1e-7, seed=2),
