@@ -163,7 +163,10 @@ lb_status lb_moments(lb_handle *h, int32_t rep, double *d_m9, double *h_totals);
  * notation), for k on the half plane kx = 0..nx/2, ky = 0..ny-1, to FP64 accumulators;
  * LB_SK_READ copies the mean, [9][ny][nx/2+1] FP64, to the device pointer out and the
  * sample count to *nsamples (synchronous); LB_SK_RESET zeroes.  rep = -1 addresses every
- * replica for RESET and SAMPLE (one batched pass over all of them).
+ * replica for RESET and SAMPLE (one batched pass over all of them).  The transforms run
+ * in the storage precision (FP32 for LB_FP32 and LB_FP32_SHIFTED) on the moments relative
+ * to a reference state (the mean of the pulled populations of row 0), so that their
+ * rounding is ~1e-7 of the spectrum's scale; k = 0 and the accumulation are FP64.
  * LB_SK_SNAPSHOT (rep >= 0; synchronous) bins |rho(k)|^2 of the current state radially (an
  * isotropic average of S_rho(k), e.g. to follow density modes growing after a quench to
  * c_s^2 < 0, where M(k) of eq. lb-lang-ft has eigenvalues above 1): with L = min(nx, ny) and the shell
