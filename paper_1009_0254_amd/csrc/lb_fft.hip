@@ -45,9 +45,24 @@ int cn_threads(int points) { return points >= 4096 ? 1024 : 256; }
 // columns per column block: adjacent x, up to CN_COL_POINTS points (one column if longer)
 int cn_cols_per_block(int nx, int ny) { return ny >= CN_COL_POINTS ? 1 : (CN_COL_POINTS / ny < nx ? CN_COL_POINTS / ny : nx); }
 
+// cos(2 pi j / n) for j < n: FP64 for FP64 storage; the hardware cosine (argument in
+// revolutions) in FP32
+template <typename R> __device__ __forceinline__ R cos_2pi(int j, int n);
+template <> __device__ __forceinline__ double cos_2pi<double>(int j, int n) { return cospi(2.0 * j / n); }
+template <> __device__ __forceinline__ float cos_2pi<float>(int j, int n)
+{
+    return __builtin_amdgcn_cosf((float)j / (float)n);
+}
+__device__ __forceinline__ double sqrt_r(double v) { return sqrt(v); }
+__device__ __forceinline__ float sqrt_r(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ double div_r(double a, double b) { return a / b; }
+__device__ __forceinline__ float div_r(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // rows: generate xi(k) of row ky, transform along kx, store the row [ky][x] to A.  The
-// transforms run in the precision R of the storage: double for FP64 storage (parity with
-// FP64 references), float otherwise (the step consumes the fields in float).
+// transforms and the per-k Cholesky factors run in the precision R of the storage: double
+// for FP64 storage (parity with FP64 references), float otherwise (the step consumes the
+// fields in float; their rounding, ~1e-7 of the noise amplitude, is far below the FP32
+// normals' 3e-6).
 template <typename R>
 __global__ void __launch_bounds__(CN_THREADS) k_cn_rows(void *__restrict__ Av, const RepDesc *__restrict__ reps,
                                                         int rep_index, const double2 *__restrict__ twx,
@@ -58,46 +73,47 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_rows(void *__restrict__ Av, c
     __shared__ TwCacheT<R> T;
     C *X = reinterpret_cast<C *>(smem_raw);
     const RepDesc &d = reps[rep_index];
-    const Consts<double> &c = d.cd;
+    const Consts<R> &c = consts<R>(d);
     const int nx = d.nx, ny = d.ny, ky = blockIdx.x;
     const unsigned long long t = tdev[0] + (unsigned long long)toff;
     tw_cache_load(T, twx, nx);
     const int my = (ny - ky) & (ny - 1);
-    const double cy = cospi(2.0 * ky / ny);
-    const double pre = c.kT3 * c.rho0;
-    const double rs = 0.70710678118654752440;   // 1/sqrt(2)
+    const R cy = cos_2pi<R>(ky, ny);
+    const R pre = c.kT3 * c.rho0;
+    const R rs = (R)0.70710678118654752440;   // 1/sqrt(2)
     const int sh = lds_pad_shift(d.lognx);
     for (int kx = threadIdx.x; kx < nx; kx += blockDim.x) {
         const int mx = (nx - kx) & (nx - 1);
         const unsigned idx = (unsigned)ky * nx + kx, midx = (unsigned)my * nx + mx;
         R g[6];
         normals6<R>(idx < midx ? idx : midx, d.rep_id | 0x80000000u, t, d.seed_lo, d.seed_hi, g);
-        double n4r, n4i, n9r, n9i;
+        R n4r, n4i, n9r, n9i;
         if (idx == midx) {
-            n4r = (double)g[0];
-            n9r = (double)g[1];
-            n4i = n9i = 0.0;
+            n4r = g[0];
+            n9r = g[1];
+            n4i = n9i = 0;
         } else {
-            const double sg = idx < midx ? 1.0 : -1.0;
-            n4r = rs * (double)g[0];
-            n4i = sg * rs * (double)g[1];
-            n9r = rs * (double)g[2];
-            n9i = sg * rs * (double)g[3];
+            const R sg = idx < midx ? (R)1 : (R)-1;
+            n4r = rs * g[0];
+            n4i = sg * rs * g[1];
+            n9r = rs * g[2];
+            n9i = sg * rs * g[3];
         }
         // minus the App. B Laplacian symbol, and c_s^2(k) = c_s^2 + rho0 kappa k^2
-        const double cx = cospi(2.0 * kx / nx);
-        const double k2 = -3.0 * ((4.0 / 9.0) * (cx + cy) + (2.0 / 9.0) * cx * cy - 10.0 / 9.0);
-        const double cs2k = c.cs2_0 + c.rho0 * c.kappa * k2;
-        const double x44 = pre * c.k44 * (2.0 - 3.0 * cs2k);
-        const double x49 = pre * c.k49 * (cs2k - 1.0 / 3.0);
-        const double x99 = pre * c.k99 * (1.25 - 0.75 * cs2k);
-        const double l44 = sqrt(fmax(x44, 0.0));
-        const double l94 = l44 > 0 ? x49 / l44 : 0.0;
-        const double l99 = sqrt(fmax(x99 - l94 * l94, 0.0));
+        const R cx = cos_2pi<R>(kx, nx);
+        const R k2 = (R)-3 * ((R)(4.0 / 9.0) * (cx + cy) + (R)(2.0 / 9.0) * cx * cy - (R)(10.0 / 9.0));
+        const R cs2k = c.cs2_0 + c.rho0 * c.kappa * k2;
+        const R x44 = pre * c.k44 * ((R)2 - (R)3 * cs2k);
+        const R x49 = pre * c.k49 * (cs2k - (R)(1.0 / 3.0));
+        const R x99 = pre * c.k99 * ((R)1.25 - (R)0.75 * cs2k);
+        const R l44 = sqrt_r(x44 > 0 ? x44 : (R)0);
+        const R l94 = l44 > 0 ? div_r(x49, l44) : (R)0;
+        const R r99 = x99 - l94 * l94;
+        const R l99 = sqrt_r(r99 > 0 ? r99 : (R)0);
         // Z = xi_4(k) + i xi_9(k), xi_4 = l44 nu_4, xi_9 = l94 nu_4 + l99 nu_9
-        const double x4r = l44 * n4r, x4i = l44 * n4i;
-        const double x9r = l94 * n4r + l99 * n9r, x9i = l94 * n4i + l99 * n9i;
-        X[lds_at(bitrev((unsigned)kx, d.lognx), sh)] = mk2((R)(x4r - x9i), (R)(x4i + x9r));
+        const R x4r = l44 * n4r, x4i = l44 * n4i;
+        const R x9r = l94 * n4r + l99 * n9r, x9i = l94 * n4i + l99 * n9i;
+        X[lds_at(bitrev((unsigned)kx, d.lognx), sh)] = mk2(x4r - x9i, x4i + x9r);
     }
     __syncthreads();
     fft_lds<false, R>(X, nx, d.lognx, 1, T, nx);
