@@ -35,7 +35,9 @@ __global__ void k_fill(double *p, long long n, double v)
 // complex (g0 + i g1)/sqrt2, (g2 + i g3)/sqrt2 where k != -k, real g0, g1 where k = -k.  The
 // pair k, -k uses the Philox block of the member with the smaller index ky nx + kx (counter
 // (index, replica | 2^31, t)); the other member takes the conjugate.  Both real fields go
-// back in one complex transform: xi_4 + i xi_9 = n^-1/2 sum_k exp(-i k.r) (xi_4(k) + i xi_9(k)).
+// back in one complex transform: xi_4 + i xi_9 = n^-1/2 sum_k exp(-i k.r) (xi_4(k) + i xi_9(k)),
+// taken along ky in the kernel that draws the noise (its columns stored contiguously) and
+// then along kx in the kernel that stores the fields (its rows stored contiguously).
 
 constexpr int CN_THREADS = 1024;
 constexpr int CN_COL_POINTS = 4096;   // points per column block when columns are short
@@ -58,15 +60,57 @@ __device__ __forceinline__ float sqrt_r(float v) { return __builtin_amdgcn_sqrtf
 __device__ __forceinline__ double div_r(double a, double b) { return a / b; }
 __device__ __forceinline__ float div_r(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
-// rows: generate xi(k) of row ky, transform along kx, store the row [ky][x] to A.  The
-// transforms and the per-k Cholesky factors run in the precision R of the storage: double
-// for FP64 storage (parity with FP64 references), float otherwise (the step consumes the
-// fields in float; their rounding, ~1e-7 of the noise amplitude, is far below the FP32
-// normals' 3e-6).
+// Z = xi_4(k) + i xi_9(k) at k = (2 pi kx / nx, 2 pi ky / ny), step t.  The per-k Cholesky
+// factors run in R: double for FP64 storage (parity with FP64 references), float otherwise
+// (the step consumes the fields in float; their rounding, ~1e-7 of the noise amplitude, is
+// far below the FP32 normals' 3e-6).
 template <typename R>
-__global__ void __launch_bounds__(CN_THREADS) k_cn_rows(void *__restrict__ Av, const RepDesc *__restrict__ reps,
-                                                        int rep_index, const double2 *__restrict__ twx,
-                                                        const unsigned long long *__restrict__ tdev, int toff)
+__device__ __forceinline__ typename V2<R>::type cn_z(const RepDesc &d, const Consts<R> &c, int kx, int ky,
+                                                     unsigned long long t)
+{
+    const int nx = d.nx, ny = d.ny;
+    const int mx = (nx - kx) & (nx - 1), my = (ny - ky) & (ny - 1);
+    const unsigned idx = (unsigned)ky * nx + kx, midx = (unsigned)my * nx + mx;
+    R g[6];
+    normals6<R>(idx < midx ? idx : midx, d.rep_id | 0x80000000u, t, d.seed_lo, d.seed_hi, g);
+    const R rs = (R)0.70710678118654752440;   // 1/sqrt(2)
+    R n4r, n4i, n9r, n9i;
+    if (idx == midx) {
+        n4r = g[0];
+        n9r = g[1];
+        n4i = n9i = 0;
+    } else {
+        const R sg = idx < midx ? (R)1 : (R)-1;
+        n4r = rs * g[0];
+        n4i = sg * rs * g[1];
+        n9r = rs * g[2];
+        n9i = sg * rs * g[3];
+    }
+    // minus the App. B Laplacian symbol, and c_s^2(k) = c_s^2 + rho0 kappa k^2
+    const R cx = cos_2pi<R>(kx, nx), cy = cos_2pi<R>(ky, ny);
+    const R k2 = (R)-3 * ((R)(4.0 / 9.0) * (cx + cy) + (R)(2.0 / 9.0) * cx * cy - (R)(10.0 / 9.0));
+    const R cs2k = c.cs2_0 + c.rho0 * c.kappa * k2;
+    const R pre = c.kT3 * c.rho0;
+    const R x44 = pre * c.k44 * ((R)2 - (R)3 * cs2k);
+    const R x49 = pre * c.k49 * (cs2k - (R)(1.0 / 3.0));
+    const R x99 = pre * c.k99 * ((R)1.25 - (R)0.75 * cs2k);
+    const R l44 = sqrt_r(x44 > 0 ? x44 : (R)0);
+    const R l94 = l44 > 0 ? div_r(x49, l44) : (R)0;
+    const R r99 = x99 - l94 * l94;
+    const R l99 = sqrt_r(r99 > 0 ? r99 : (R)0);
+    // xi_4 = l44 nu_4, xi_9 = l94 nu_4 + l99 nu_9
+    const R x4r = l44 * n4r, x4i = l44 * n4i;
+    const R x9r = l94 * n4r + l99 * n9r, x9i = l94 * n4i + l99 * n9i;
+    return mk2(x4r - x9i, x4i + x9r);
+}
+
+// columns first: Z(k) of C adjacent kx columns, transformed along ky in LDS, stored to A as
+// [kx][y] (each block's columns are one contiguous run).  Transforms in the storage
+// precision R.
+template <typename R>
+__global__ void __launch_bounds__(CN_THREADS) k_cn_gen(void *__restrict__ Av, const RepDesc *__restrict__ reps,
+                                                       int rep_index, int cpb, const double2 *__restrict__ twy,
+                                                       const unsigned long long *__restrict__ tdev, int toff)
 {
     typedef typename V2<R>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -74,58 +118,30 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_rows(void *__restrict__ Av, c
     C *X = reinterpret_cast<C *>(smem_raw);
     const RepDesc &d = reps[rep_index];
     const Consts<R> &c = consts<R>(d);
-    const int nx = d.nx, ny = d.ny, ky = blockIdx.x;
+    const int nx = d.nx, ny = d.ny, logny = d.logny;
+    const long long lb = xcd_logical((nx + cpb - 1) / cpb);
+    if (lb < 0) return;
+    const int x0 = (int)lb * cpb, Cn = min(cpb, nx - x0);
     const unsigned long long t = tdev[0] + (unsigned long long)toff;
-    tw_cache_load(T, twx, nx);
-    const int my = (ny - ky) & (ny - 1);
-    const R cy = cos_2pi<R>(ky, ny);
-    const R pre = c.kT3 * c.rho0;
-    const R rs = (R)0.70710678118654752440;   // 1/sqrt(2)
-    const int sh = lds_pad_shift(d.lognx);
-    for (int kx = threadIdx.x; kx < nx; kx += blockDim.x) {
-        const int mx = (nx - kx) & (nx - 1);
-        const unsigned idx = (unsigned)ky * nx + kx, midx = (unsigned)my * nx + mx;
-        R g[6];
-        normals6<R>(idx < midx ? idx : midx, d.rep_id | 0x80000000u, t, d.seed_lo, d.seed_hi, g);
-        R n4r, n4i, n9r, n9i;
-        if (idx == midx) {
-            n4r = g[0];
-            n9r = g[1];
-            n4i = n9i = 0;
-        } else {
-            const R sg = idx < midx ? (R)1 : (R)-1;
-            n4r = rs * g[0];
-            n4i = sg * rs * g[1];
-            n9r = rs * g[2];
-            n9i = sg * rs * g[3];
-        }
-        // minus the App. B Laplacian symbol, and c_s^2(k) = c_s^2 + rho0 kappa k^2
-        const R cx = cos_2pi<R>(kx, nx);
-        const R k2 = (R)-3 * ((R)(4.0 / 9.0) * (cx + cy) + (R)(2.0 / 9.0) * cx * cy - (R)(10.0 / 9.0));
-        const R cs2k = c.cs2_0 + c.rho0 * c.kappa * k2;
-        const R x44 = pre * c.k44 * ((R)2 - (R)3 * cs2k);
-        const R x49 = pre * c.k49 * (cs2k - (R)(1.0 / 3.0));
-        const R x99 = pre * c.k99 * ((R)1.25 - (R)0.75 * cs2k);
-        const R l44 = sqrt_r(x44 > 0 ? x44 : (R)0);
-        const R l94 = l44 > 0 ? div_r(x49, l44) : (R)0;
-        const R r99 = x99 - l94 * l94;
-        const R l99 = sqrt_r(r99 > 0 ? r99 : (R)0);
-        // Z = xi_4(k) + i xi_9(k), xi_4 = l44 nu_4, xi_9 = l94 nu_4 + l99 nu_9
-        const R x4r = l44 * n4r, x4i = l44 * n4i;
-        const R x9r = l94 * n4r + l99 * n9r, x9i = l94 * n4i + l99 * n9i;
-        X[lds_at(bitrev((unsigned)kx, d.lognx), sh)] = mk2(x4r - x9i, x4i + x9r);
+    tw_cache_load(T, twy, ny);
+    const int tot = Cn << logny, sh = lds_pad_shift(logny);
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int cc = e >> logny, ky = e & (ny - 1);
+        X[lds_at(cc * ny + bitrev((unsigned)ky, logny), sh)] = cn_z<R>(d, c, x0 + cc, ky, t);
     }
     __syncthreads();
-    fft_lds<false, R>(X, nx, d.lognx, 1, T, nx);
-    C *row = reinterpret_cast<C *>(Av) + (long long)ky * nx;
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) row[x] = X[lds_at(x, sh)];
+    fft_lds<false, R>(X, ny, logny, Cn, T, ny);
+    C *A = reinterpret_cast<C *>(Av) + (long long)x0 * ny;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) A[e] = X[lds_at(e, sh)];
 }
 
-// columns: transform C adjacent columns of A along ky, scale by n^-1/2, store xi_4, xi_9
+// rows second: row y of A gathered across kx (stride ny; consecutive rows, which share
+// cache lines, are kept on one XCD), transformed along kx, scaled by n^-1/2 and stored as
+// the xi_4, xi_9 pairs of the row (contiguous).
 template <typename S>
-__global__ void __launch_bounds__(CN_THREADS) k_cn_cols(const void *__restrict__ Av, S *__restrict__ xi,
-                                                        const RepDesc *__restrict__ reps, int rep_index, int cpb,
-                                                        const double2 *__restrict__ twy)
+__global__ void __launch_bounds__(CN_THREADS) k_cn_out(const void *__restrict__ Av, S *__restrict__ xi,
+                                                       const RepDesc *__restrict__ reps, int rep_index,
+                                                       const double2 *__restrict__ twx)
 {
     typedef typename V2<S>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -133,39 +149,40 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_cols(const void *__restrict__
     C *X = reinterpret_cast<C *>(smem_raw);
     const C *A = reinterpret_cast<const C *>(Av);
     const RepDesc &d = reps[rep_index];
-    const int nx = d.nx, ny = d.ny;
-    const long long lb = xcd_logical((nx + cpb - 1) / cpb);
-    if (lb < 0) return;
-    const int x0 = (int)lb * cpb, Cn = min(cpb, nx - x0);
-    tw_cache_load(T, twy, ny);
-    const int tot = Cn * ny, sh = lds_pad_shift(d.logny);
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int y = e / Cn, cc = e - y * Cn;
-        X[lds_at(cc * ny + bitrev((unsigned)y, d.logny), sh)] = A[(long long)y * nx + x0 + cc];
+    const int nx = d.nx, ny = d.ny, lognx = d.lognx;
+    const long long ly = xcd_logical(ny);
+    if (ly < 0) return;
+    const int y = (int)ly;
+    tw_cache_load(T, twx, nx);
+    const int sh = lds_pad_shift(lognx);
+    for (int k0 = threadIdx.x; k0 < nx; k0 += 4 * blockDim.x) {
+        C v[4];
+        for (int u = 0; u < 4; ++u) v[u] = A[(long long)min(k0 + u * (int)blockDim.x, nx - 1) * ny + y];
+        for (int u = 0; u < 4; ++u) {
+            const int kx = k0 + u * (int)blockDim.x;
+            if (kx < nx) X[lds_at(bitrev((unsigned)kx, lognx), sh)] = v[u];
+        }
     }
     __syncthreads();
-    fft_lds<false, S>(X, ny, d.logny, Cn, T, ny);
+    fft_lds<false, S>(X, nx, lognx, 1, T, nx);
     const S s = (S)rsqrt((double)nx * (double)ny);
-    S *out = xi + 2 * d.xi_off;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int y = e / Cn, cc = e - y * Cn;
-        const C v = X[lds_at(cc * ny + y, sh)];
-        const long long o = 2 * ((long long)y * nx + x0 + cc);
-        out[o] = v.x * s;
-        out[o + 1] = v.y * s;
+    C *out = reinterpret_cast<C *>(xi + 2 * d.xi_off) + (long long)y * nx;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+        const C v = X[lds_at(x, sh)];
+        out[x] = mk2(v.x * s, v.y * s);
     }
 }
 
 hipError_t set_fft_lds_limit(int max_nx, int max_col_points)
 {
     const int rows = (int)(sizeof(double2) * lds_padded(max_nx)), cols = (int)(sizeof(double2) * lds_padded(max_col_points));
-    hipError_t e = hipFuncSetAttribute((const void *)k_cn_rows<double>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
+    hipError_t e = hipFuncSetAttribute((const void *)k_cn_out<double>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_cn_rows<float>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
+        e = hipFuncSetAttribute((const void *)k_cn_out<float>, hipFuncAttributeMaxDynamicSharedMemorySize, rows);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_cn_cols<double>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
+        e = hipFuncSetAttribute((const void *)k_cn_gen<double>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_cn_cols<float>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
+        e = hipFuncSetAttribute((const void *)k_cn_gen<float>, hipFuncAttributeMaxDynamicSharedMemorySize, cols);
     return e;
 }
 
@@ -181,15 +198,15 @@ hipError_t launch_correlated_noise(int precision, const RepDesc *d_reps, const R
     const int cpb = cn_cols_per_block(nx, ny);
     const unsigned ncb = xcd_grid((nx + cpb - 1) / cpb);
     if (precision == 0) {
-        hipLaunchKernelGGL(k_cn_rows<double>, dim3(ny), dim3(cn_threads(nx)), sizeof(double2) * lds_padded(nx), s, (void *)work,
-                           d_reps, rep_index, twx, tdev, toff);
-        hipLaunchKernelGGL(k_cn_cols<double>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(double2) * lds_padded(cpb * ny), s,
-                           (const void *)work, (double *)xi_base, d_reps, rep_index, cpb, twy);
+        hipLaunchKernelGGL(k_cn_gen<double>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(double2) * lds_padded(cpb * ny),
+                           s, (void *)work, d_reps, rep_index, cpb, twy, tdev, toff);
+        hipLaunchKernelGGL(k_cn_out<double>, dim3(xcd_grid(ny)), dim3(cn_threads(nx)), sizeof(double2) * lds_padded(nx),
+                           s, (const void *)work, (double *)xi_base, d_reps, rep_index, twx);
     } else {
-        hipLaunchKernelGGL(k_cn_rows<float>, dim3(ny), dim3(cn_threads(nx)), sizeof(float2) * lds_padded(nx), s, (void *)work,
-                           d_reps, rep_index, twx, tdev, toff);
-        hipLaunchKernelGGL(k_cn_cols<float>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(float2) * lds_padded(cpb * ny), s,
-                           (const void *)work, (float *)xi_base, d_reps, rep_index, cpb, twy);
+        hipLaunchKernelGGL(k_cn_gen<float>, dim3(ncb), dim3(cn_threads(cpb * ny)), sizeof(float2) * lds_padded(cpb * ny),
+                           s, (void *)work, d_reps, rep_index, cpb, twy, tdev, toff);
+        hipLaunchKernelGGL(k_cn_out<float>, dim3(xcd_grid(ny)), dim3(cn_threads(nx)), sizeof(float2) * lds_padded(nx),
+                           s, (const void *)work, (float *)xi_base, d_reps, rep_index, twx);
     }
     return hipGetLastError();
 }
