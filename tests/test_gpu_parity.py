@@ -537,6 +537,55 @@ def test_full_size_8192_structure_factor_sampled():
     assert err.max() < 1e-4
 
 
+FULL_GATES = {"cfg2": 2e-4, "cfg5": 6e-4}   # the FP32 floors of the two-phase slab and the quench
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg5"])
+def test_full_size_two_phase_workloads_sampled(name):
+    """The 2048^2 slab and the 16384^2 spinodal quench at full size, in the launch configuration
+    bench.py times (FP32-shifted, autotuned tiles): two steps against the oracle at 200,000
+    sampled nodes, whose moments the oracle forms there from its pre-collision populations.
+    Gates: the FP32 floors of these states (O(1) density contrast; growth after a quench)."""
+    L = _L()
+    cfg = getattr(W, name)()
+    nx, ny = cfg["nx"], cfg["ny"]
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, nx * ny, size=200_000)
+    lat = L.Lattice(cfg, precision=2)
+    lat.step(2)
+    mg, _ = lat.lb_moments(0, True)
+    mg = mg.reshape(9, -1)[:, torch.from_numpy(idx).to(mg.device)].cpu().numpy()
+    lat.close()
+    ora = O.Oracle(cfg)
+    ora.step(2)
+    T = O.tables()[0]
+    mo = T @ ora.f.reshape(9, -1)[:, idx]
+    del ora
+    scale = np.abs(mo - mo.mean(axis=1, keepdims=True)).max(axis=1)
+    e = np.abs(mg - mo).max(axis=1) / scale
+    say(name, "full size, 2 steps, err", e)
+    assert e.max() < FULL_GATES[name]
+
+
+def test_full_size_ensemble_sampled_replicas():
+    """The bench's 336-replica ensemble (256 x 128^2, 64 x 256^2, 16 x 512^2, kT over two
+    decades) in one launch, FP32-shifted: two steps against the oracle for the first and last
+    replica of each size class."""
+    L = _L()
+    cfgs = W.cfg4()
+    lat = L.Lattice(cfgs, precision=2)
+    lat.step(2)
+    worst = 0.0
+    for r in (0, 255, 256, 319, 320, 335):
+        o = O.Oracle(cfgs[r])
+        o.step(2)
+        e = rel_err(lat.moments(r), o.moments())
+        say("ensemble replica", r, cfgs[r]["nx"], "kT", cfgs[r]["kT"], "err", e.max())
+        worst = max(worst, e.max())
+    lat.close()
+    assert worst < 1e-5
+
+
 # ------------------------------------------------------------------ equipartition on the GPU
 
 
