@@ -40,7 +40,7 @@ namespace {
 
 constexpr int SK_THREADS = 1024;   // upper bound; launches use fewer for short lines
 
-// long lines get a full CU (one workgroup fits in LDS); short ones 256 lanes
+// lines of 4096 points or more get 1024 lanes; shorter ones 256
 int sk_threads(int line) { return line >= 4096 ? 1024 : 256; }
 
 template <int F> __device__ __forceinline__ long long sk_key(const SkRep &q)
@@ -168,9 +168,10 @@ __global__ void __launch_bounds__(SK_REF_THREADS)
 
 // Transforms run in Tt (float for FP32 storage, double for FP64) on m_a(r) - m_a(vref) (the
 // reference of k_sk_ref); a constant only moves the k = 0 coefficient, which the column pass
-// restores in FP64 as X(0) + n m_a(vref + shift).  CACHE: a lane's node pairs (at most SK_CACHE_PAIRS) are pulled once and
-// their nine moments kept in registers for all mode groups; otherwise each group of G modes
-// pulls the row again (the repeats hit L2 or the MALL).
+// restores in FP64 as X(0) + n m_a(vref + shift).  CACHE: a lane's node pairs (at most
+// SK_CACHE_PAIRS) are pulled once and their nine moments kept in registers for all mode
+// groups; otherwise each group of G modes pulls the row again (the repeats hit L2 or the
+// MALL).
 template <typename S, typename Tt, int RMAX, bool CACHE>
 __global__ void __launch_bounds__(SK_THREADS)
     k_sk_rows(const S *__restrict__ f, const RepDesc *__restrict__ reps, const SkRep *__restrict__ sk, int r0, int r1,
