@@ -304,7 +304,8 @@ def stationary_covariance_uncorrelated(kx, ky, lam, cs2, rho0, kappa, kT, diagon
 
 
 def transient_covariance(kx, ky, lam, cs2, rho0, kappa, kT, t, noise="k0"):
-    """sum_{s<t} M^s Q M^{H s}: covariance after t noisy steps from a noise-free start."""
+    """sum_{s<t} M^s Q M^{H s}: covariance after t noisy steps from a noise-free start, with
+    Q = A(-k) Xi A(-k)^H (eq. lb-lang-ft, one step at a time)."""
     M = step_matrix(kx, ky, lam, cs2, rho0, kappa)
     Am = advection(-kx, -ky)
     if noise == "k0":
@@ -318,6 +319,33 @@ def transient_covariance(kx, ky, lam, cs2, rho0, kappa, kT, t, noise="k0"):
     for _ in range(t):
         G = M @ G @ M.conj().T + Q
     return G
+
+
+def transient_covariance_batch(kx, ky, lam, cs2, rho0, kappa, kT, t):
+    """The same sum for the k = 0 noise at many k (arrays kx, ky) by doubling:
+    with P_s = M^s and G_s the covariance after s steps, G_{s1+s2} = G_{s2} + P_{s2} G_{s1}
+    P_{s2}^H and P_{s1+s2} = P_{s2} P_{s1}; t is built from its binary digits.
+    Returns [K, 9, 9]."""
+    kx = np.atleast_1d(np.asarray(kx, dtype=float))
+    ky = np.atleast_1d(np.asarray(ky, dtype=float))
+    X = noise_matrix_closed(0.0, 0.0, lam, cs2, rho0, 0.0, kT)
+    M = np.stack([step_matrix(a, b, lam, cs2, rho0, kappa) for a, b in zip(kx, ky)])
+    Am = np.stack([advection(-a, -b) for a, b in zip(kx, ky)])
+    Q = Am @ X @ np.conj(np.swapaxes(Am, 1, 2))
+    H = lambda A: np.conj(np.swapaxes(A, 1, 2))
+    # (Pd, Gd): 2^j steps; (Pa, Ga): the steps taken so far
+    Pd, Gd = M, Q
+    Pa = np.broadcast_to(np.eye(9, dtype=complex), M.shape).copy()
+    Ga = np.zeros_like(Q)
+    while t > 0:
+        if t & 1:
+            Ga = Gd + Pd @ Ga @ H(Pd)
+            Pa = Pd @ Pa
+        t >>= 1
+        if t:
+            Gd = Gd + Pd @ Gd @ H(Pd)
+            Pd = Pd @ Pd
+    return Ga
 
 
 def psd_all_k(kappa, cs2, lam, rho0=1.0, nk=97, tol=1e-12):

@@ -571,6 +571,64 @@ def test_radial_shell_matches_exact_definition(nx, ny):
             assert int(O.radial_shell(kx, ky, nx, ny)) == b, (kx, ky)
 
 
+def _unc_params(c):
+    lam = th.relaxation_rates(c["tau_bulk"], c["tau_shear"], c["tau_q"], c["tau_eps"])
+    cs2 = th.sound_speed2(c["rho0"], c["c0sq"], c["A"], c["B"], c["rhoc"])
+    return lam, cs2
+
+
+def test_transient_covariance_batch_equals_step_loop():
+    """The doubling form of sum_{s<t} M^s Q M^{H s} equals the step-by-step recursion."""
+    c = W.single_phase(8, 8)
+    lam, cs2 = _unc_params(c)
+    ks = [(0.3, 0.1), (2.0, -1.1), (np.pi, 0.4), (0.01, 0.02), (1.0, np.pi)]
+    for t in (1, 6, 37, 200):
+        Gb = th.transient_covariance_batch([k[0] for k in ks], [k[1] for k in ks], lam, cs2, c["rho0"], c["kappa"],
+                                           c["kT"], t)
+        for i, (a, b) in enumerate(ks):
+            Gs = th.transient_covariance(a, b, lam, cs2, c["rho0"], c["kappa"], c["kT"], t)
+            assert np.abs(Gb[i] - Gs).max() <= 1e-13 * np.abs(Gs).max()
+
+
+def test_transient_covariance_reaches_the_stationary_one():
+    """After many steps the transient covariance is the solution of G = M G M^H + Q (the
+    stationary covariance, solved as a linear system)."""
+    c = W.single_phase(8, 8)
+    lam, cs2 = _unc_params(c)
+    for kx, ky in [(1.3, 0.7), (2.5, -2.0)]:
+        Gt = th.transient_covariance(kx, ky, lam, cs2, c["rho0"], c["kappa"], c["kT"], 3000)
+        Gs = th.stationary_covariance_uncorrelated(kx, ky, lam, cs2, c["rho0"], c["kappa"], c["kT"])
+        assert np.abs(Gt - Gs).max() <= 1e-10 * np.abs(Gs).max()
+
+
+def test_transient_covariance_against_oracle_ensemble():
+    """S_a(k) of the oracle three steps after a quiescent start, averaged over 200 seeds of a
+    32 x 16 lattice, against sum_{s<3} M^s Q M^{H s}: per mode the k-summed ratio within 2%
+    (standard error ~0.5%).  The stationary covariance is no substitute this early: for rho,
+    j_x, j_y it is off by more than 10%."""
+    nx, ny, t, nseed = 32, 16, 3, 200
+    c = W.single_phase(nx, ny, kT=1e-5)
+    lam, cs2 = _unc_params(c)
+    acc = np.zeros((9, ny, nx // 2 + 1))
+    for sd in range(nseed):
+        o = O.Oracle(dict(c, seed=1000 + sd))
+        o.step(t)
+        acc += O.power_spectrum(o.moments())
+    S = acc / nseed
+    KY, KX = np.mgrid[0:ny, 0:nx // 2 + 1]
+    keep = ((KX != 0) | (KY != 0)) & ~((KX == nx // 2) & (KY == 0)) & ~((KX == 0) & (KY == ny // 2))
+    kx, ky = 2 * np.pi * KX[keep] / nx, 2 * np.pi * KY[keep] / ny
+    Gt = np.real(np.diagonal(th.transient_covariance_batch(kx, ky, lam, cs2, c["rho0"], c["kappa"], c["kT"], t),
+                             axis1=1, axis2=2))
+    Gs = np.array([np.real(np.diag(th.stationary_covariance_uncorrelated(a, b, lam, cs2, c["rho0"], c["kappa"],
+                                                                            c["kT"]))) for a, b in zip(kx, ky)])
+    Sk = S[:, keep].T
+    r = Sk.sum(0) / Gt.sum(0)
+    rs = Sk.sum(0) / Gs.sum(0)
+    assert np.abs(r - 1).max() < 0.02, r
+    assert np.all(np.abs(rs[:3] - 1) > 0.10), rs
+
+
 def test_radial_spectrum_parseval_and_counts():
     rng = np.random.default_rng(5)
     for nx, ny in [(64, 64), (128, 16), (8, 64)]:
