@@ -321,11 +321,11 @@ def transient_covariance(kx, ky, lam, cs2, rho0, kappa, kT, t, noise="k0"):
     return G
 
 
-def transient_covariance_batch(kx, ky, lam, cs2, rho0, kappa, kT, t):
+def transient_covariance_batch(kx, ky, lam, cs2, rho0, kappa, kT, t, power=False):
     """The same sum for the k = 0 noise at many k (arrays kx, ky) by doubling:
     with P_s = M^s and G_s the covariance after s steps, G_{s1+s2} = G_{s2} + P_{s2} G_{s1}
     P_{s2}^H and P_{s1+s2} = P_{s2} P_{s1}; t is built from its binary digits.
-    Returns [K, 9, 9]."""
+    Returns [K, 9, 9], and with power=True also M^t [K, 9, 9]."""
     kx = np.atleast_1d(np.asarray(kx, dtype=float))
     ky = np.atleast_1d(np.asarray(ky, dtype=float))
     X = noise_matrix_closed(0.0, 0.0, lam, cs2, rho0, 0.0, kT)
@@ -345,7 +345,7 @@ def transient_covariance_batch(kx, ky, lam, cs2, rho0, kappa, kT, t):
         if t:
             Gd = Gd + Pd @ Gd @ H(Pd)
             Pd = Pd @ Pd
-    return Ga
+    return (Ga, Pa) if power else Ga
 
 
 def psd_all_k(kappa, cs2, lam, rho0=1.0, nk=97, tol=1e-12):

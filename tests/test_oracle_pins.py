@@ -585,9 +585,13 @@ def test_transient_covariance_batch_equals_step_loop():
     for t in (1, 6, 37, 200):
         Gb = th.transient_covariance_batch([k[0] for k in ks], [k[1] for k in ks], lam, cs2, c["rho0"], c["kappa"],
                                            c["kT"], t)
+        _, Pb = th.transient_covariance_batch([k[0] for k in ks], [k[1] for k in ks], lam, cs2, c["rho0"],
+                                              c["kappa"], c["kT"], t, power=True)
         for i, (a, b) in enumerate(ks):
             Gs = th.transient_covariance(a, b, lam, cs2, c["rho0"], c["kappa"], c["kT"], t)
             assert np.abs(Gb[i] - Gs).max() <= 1e-13 * np.abs(Gs).max()
+            Ps = np.linalg.matrix_power(th.step_matrix(a, b, lam, cs2, c["rho0"], c["kappa"]), t)
+            assert np.abs(Pb[i] - Ps).max() <= 1e-12 * max(np.abs(Ps).max(), 1.0)
 
 
 def test_transient_covariance_reaches_the_stationary_one():
