@@ -135,11 +135,6 @@ def structure_factor(kx, ky, cs2, rho0, kappa, kT):
     return rho0 * kT / cs2_k(kx, ky, cs2, rho0, kappa)
 
 
-def bulk_viscosity(kx, ky, cs2, rho0, kappa, tau_bulk):
-    """zeta(k) = rho0 sigma_s^2 (tau_b - 1/2) [2 - c_s^2(k)/sigma_s^2], eq. (bulkv-yeo)."""
-    return rho0 * SIGMA_S2 * (tau_bulk - 0.5) * (2.0 - cs2_k(kx, ky, cs2, rho0, kappa) / SIGMA_S2)
-
-
 def shear_viscosity(rho0, tau_shear):
     """eta = rho0 sigma_s^2 (tau_s - 1/2), Sec. III.C."""
     return rho0 * SIGMA_S2 * (tau_shear - 0.5)
@@ -270,12 +265,6 @@ def stress_noise_variances_appC(lam, cs2, rho0, kT):
     v5 = -4.0 * kT * rho0 * SIGMA_S2 * (2 * ls + ls * ls)
     v6 = -1.0 * kT * rho0 * SIGMA_S2 * (2 * ls + ls * ls)
     return v4, v5, v6
-
-
-def noise_cholesky_k0(lam, cs2, rho0, kT):
-    """Lower-triangular L with L L^T = Xi(0) on the 6x6 block of modes 4..9 (Sec. IV)."""
-    X = noise_matrix_closed(0.0, 0.0, lam, cs2, rho0, 0.0, kT)[3:, 3:]
-    return np.linalg.cholesky(X)
 
 
 def step_matrix(kx, ky, lam, cs2, rho0, kappa):
