@@ -434,15 +434,19 @@ lb_status autotune(lb_handle *h)
     // warm-up, the three fastest are timed again, and among those re-timings a later one
     // replaces an earlier one only when at least 2% faster, so that near-ties resolve the
     // same way on every device
+    // trial length: at least ~3 ms of steps (short trials of small lattices are noisy), from
+    // the first candidate's time per step; *ms is the time per step
+    int trial = 4;
     auto time_shape = [&](int bx, int rows, float *ms) -> lb_status {
         if (set_tiles(h, bx, rows) != LB_OK) return LB_EINVAL;
         if (step_once(h, h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
         (void)hipEventRecord(e0, h->stream);
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < trial; ++k)
             if (step_once(h, h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
         (void)hipEventRecord(e1, h->stream);
         if (hipEventSynchronize(e1) != hipSuccess) return LB_EDEVICE;
         (void)hipEventElapsedTime(ms, e0, e1);
+        *ms /= (float)trial;
         return LB_OK;
     };
     const int widths[] = {512, 256, 128, 64};
@@ -463,6 +467,7 @@ lb_status autotune(lb_handle *h)
                     lb_status st = time_shape(bx, rows, &ms);
                     if (st == LB_EDEVICE) return st;
                 }
+                if (ms > 0) trial = std::max(4, std::min(64, (int)ceilf(3.0f / ms)));
                 warmed = true;
             }
             lb_status st = time_shape(bx, rows, &ms);
