@@ -58,6 +58,26 @@ int main(void) {
                    P.init_arg.offset]
 
 
+def test_header_is_strict_c99_and_cxx(tmp_path):
+    """The header compiles alone as pedantic C99 and as C++11, with every warning an error."""
+    src = tmp_path / "h.c"
+    src.write_text('#include "lbfluct.h"\nint main(void) { lb_handle *h = 0; lb_free(h); return (int)sizeof(lb_params) == 0; }\n')
+    inc = ["-I", os.path.join(ROOT, "include")]
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", *inc, "-c", str(src),
+                    "-o", str(tmp_path / "h.o")], check=True)
+    subprocess.run(["g++", "-std=c++11", "-x", "c++", "-Wall", "-Wextra", "-pedantic", "-Werror", *inc, "-c",
+                    str(src), "-o", str(tmp_path / "hpp.o")], check=True)
+
+
+def test_c_client_builds_against_the_header_and_library(tmp_path):
+    """A C program that uses only the header, the library and the HIP runtime compiles and
+    links; run without arguments it prints its usage (no device call)."""
+    from conftest import build_c_client
+    exe = build_c_client(tmp_path)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 2 and "usage" in r.stderr
+
+
 def test_strerror():
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert isinstance(L.lb_strerror(code), str) and L.lb_strerror(code)
