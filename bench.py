@@ -82,9 +82,10 @@ def traffic_from_counters(tile=None):
         return None
     if c.get("kernel_src_sha") != kernel_sha():
         return None
-    if tile is not None and c.get("tile") != "%d,%d" % tile:
-        return None
-    return c.get("hbm_bytes_per_launch")
+    if tile is None:
+        return c.get("hbm_bytes_per_launch")
+    t = c.get("per_tile", {}).get("%d,%d" % tile)
+    return t.get("hbm_bytes_per_launch") if t else None
 
 
 def cpu_baseline(torch, L, cfg, steps):
@@ -196,7 +197,7 @@ def main():
                    "tile": {"strip_width": tune[0], "rows": tune[1], "tiles": tune[2]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters((tune[0], tune[1])),
-                     "kernel": "k_step<float,float,false,false>", "tile": "%d,%d" % (tune[0], tune[1]),
+                     "kernel": "k_step<float,float,false,false,false>", "tile": "%d,%d" % (tune[0], tune[1]),
                      "bytes_per_update": BYTES_PER_UPDATE[prec]},
         "status_flags": flags,
     }

@@ -25,7 +25,7 @@ namespace {
 constexpr size_t ALIGN = 256;
 constexpr int MAX_RED_BLOCKS = 1024;
 constexpr int GRAPH_STEPS = 32;   // steps per captured graph (even: buffers return to place)
-constexpr int MIN_BX = 64, MIN_H = 8;
+constexpr int MIN_BX = 64, MIN_H = 4;
 constexpr int CN_MAX = 8192;        // longest side with correlated noise
 constexpr int SAMPLE_GRAPH_MAX = 256;   // longest sampling interval captured as one graph
 
@@ -220,6 +220,7 @@ struct lb_handle {
     Tile *tiles_d = nullptr;
     std::vector<Tile> tiles_h;
     int ntiles = 0, bx = 256, rows = 32;
+    bool whole = false;   // some replica fits one strip of the current tile list
     unsigned long long *tdev = nullptr;
     unsigned *flags = nullptr;
     double *partials = nullptr, *tot = nullptr, *rho_tmp = nullptr;
@@ -314,6 +315,8 @@ lb_status set_tiles(lb_handle *h, int bx, double rows)
         return LB_EDEVICE;
     h->ntiles = (int)h->tiles_h.size();
     h->bx = bx;
+    h->whole = false;
+    for (const auto &d : h->reps) h->whole = h->whole || d.nx <= bx;
     h->rows = (int)ceil(rows - 1e-9);
     return LB_OK;
 }
@@ -337,6 +340,7 @@ hipError_t step_once(lb_handle *h, int par, int toff, hipStream_t s)
     a.ntiles = h->ntiles;
     a.bx = h->bx;
     a.plain = h->precision == LB_FP32 ? 1 : 0;
+    a.whole = h->whole ? 1 : 0;
     return launch_step(h->precision, a, s);
 }
 
@@ -419,7 +423,7 @@ lb_status autotune(lb_handle *h)
     }
     int bx0 = 256;
     while (bx0 > MIN_BX && bx0 / 2 >= min_nx) bx0 /= 2;
-    if (h->L.nodes < (1ll << 22)) return set_tiles(h, bx0, h->L.nodes < (1ll << 16) ? MIN_H : 16);
+    if (h->L.nodes < (1ll << 22)) return set_tiles(h, bx0, h->L.nodes < (1ll << 16) ? 8 : 16);
     struct Events {   // destroyed on every return path
         hipEvent_t a = nullptr, b = nullptr;
         ~Events()
@@ -450,7 +454,7 @@ lb_status autotune(lb_handle *h)
         return LB_OK;
     };
     const int widths[] = {512, 256, 128, 64};
-    const int heights[] = {16, 8, 32, 64};
+    const int heights[] = {16, 8, 4, 32, 64};
     struct Cand {
         int bx, rows, order;
         float ms;

@@ -97,6 +97,7 @@ struct StepLaunch {
     int32_t ntiles;
     int32_t bx;
     int32_t plain;   // 1: stored values are f_i (sub_i = w_i rho0); 0: stored f_i - w_i rho0
+    int32_t whole;   // 1: some replica fits one strip (nx <= bx): launch the whole-row variant
 };
 
 // the fused step's tiles for strips of bx lanes and tiles of about h rows (lb_tiles.hip)

@@ -6,7 +6,8 @@
 // Each workgroup owns a strip of blockDim.x columns and marches down rows y0..y1-1,
 // keeping the density of rows y-1, y, y+1 in a 4-slot LDS ring so that the 9-point
 // stencils (App. B Laplacian; isotropic gradient) never re-read populations from HBM.
-// The two halo columns of the strip are pulled by lanes 0 and 1 of the first wave.
+// The two halo columns of the strip are pulled by lanes 0 and 1 of the first wave (a strip
+// that spans its whole row reads them from its own columns instead).
 // Loads run two rows ahead: while row y collides, the populations of row y+2 are in
 // flight (on gfx950 a workgroup barrier only waits for LDS, not for global loads).
 // Populations are row-interleaved ([y][i][x], see pop_at): a row of the lattice is one
@@ -193,7 +194,7 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
 
 // ------------------------------------------------------------------ fused step kernel
 
-template <typename S, typename R, bool PLAIN, bool CN>
+template <typename S, typename R, bool PLAIN, bool CN, bool WHOLE>
 __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S *__restrict__ fin, S *__restrict__ fout,
                                               const RepDesc *__restrict__ reps, const Tile *__restrict__ tiles,
                                               const unsigned long long *__restrict__ tdev,
@@ -224,8 +225,17 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
     const unsigned c0 = xw * ES;
     const unsigned cp = (xw == nx - 1 ? 0 : xw + 1) * ES;
     const bool store = xg < nx;
-    // halo columns of the strip, pulled by lanes 0 (left) and 1 (right)
-    const bool halo = tid < 2;
+    // A strip that spans its whole row (x0 = 0, nx <= BX; only in the WHOLE variant) has its
+    // halo densities among its own columns: the lane of column nx - 1 also writes the west
+    // halo slot 0 and the lane of column 0 the east halo slot nx + 1, the slot that lane
+    // nx - 1 reads.  Such a strip pulls no halo columns, and its whole waves past the row
+    // (x >= nx) only keep the barriers.  Other strips pull the two halo columns with lanes 0
+    // (left) and 1 (right).
+    const bool whole = WHOLE && tl.x0 == 0 && nx <= BX;
+    const bool idle = WHOLE && __builtin_amdgcn_readfirstlane(whole && (tid & ~63u) >= nx);   // uniform per wave
+    const bool xtra = whole && (tid == 0 || tid == nx - 1);
+    const unsigned xslot = tid == 0 ? nx + 1 : 0;
+    const bool halo = !whole && tid < 2;
     const unsigned hxw = tid == 0 ? ((unsigned)tl.x0 + nx - 1) % nx : ((unsigned)tl.x0 + BX) % nx;
     const unsigned hcm = (hxw == 0 ? nx - 1 : hxw - 1) * ES;
     const unsigned hc0 = hxw * ES;
@@ -301,34 +311,48 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
     R fa[Q], fb[Q], hv[Q];
     // prologue: densities of rows y0-1 and y0 (own and halo columns), populations of row y0
     const Rows ra = rows_of(y0 - 1), rb = rows_of(y0);
-    pull(ra, c0, cm, cp, fb);
-    ring[((unsigned)(y0 - 1) & 3u) * WL + tid + 1] = dens(fb);
-    if (halo) {
-        pull(ra, hc0, hcm, hcp, hv);
-        ring[((unsigned)(y0 - 1) & 3u) * WL + hslot] = dens(hv);
-        pull(rb, hc0, hcm, hcp, hv);
-        ring[((unsigned)y0 & 3u) * WL + hslot] = dens(hv);
+    // the lane's density of row yy into the ring (and, in a whole-row strip, into a halo slot)
+    auto put = [&](int yy, R v) {
+        const unsigned sl = ((unsigned)yy & 3u) * WL;
+        ring[sl + tid + 1] = v;
+        if (xtra) ring[sl + xslot] = v;
+    };
+    if (!idle) {
+        pull(ra, c0, cm, cp, fb);
+        put(y0 - 1, dens(fb));
+        if (halo) {
+            pull(ra, hc0, hcm, hcp, hv);
+            ring[((unsigned)(y0 - 1) & 3u) * WL + hslot] = dens(hv);
+            pull(rb, hc0, hcm, hcp, hv);
+            ring[((unsigned)y0 & 3u) * WL + hslot] = dens(hv);
+        }
+        pull(rb, c0, cm, cp, fa);
+        put(y0, dens(fa));
     }
-    pull(rb, c0, cm, cp, fa);
-    ring[((unsigned)y0 & 3u) * WL + tid + 1] = dens(fa);
 
     // row y+1 is already in flight when row y starts; row y+2 is issued before the barrier
     // and lands while row y collides
     R fcq[Q];
     const Rows rc = rows_of(y0 + 1);
-    pull(rc, c0, cm, cp, fb);
-    if (halo) pull(rc, hc0, hcm, hcp, hv);
+    if (!idle) {
+        pull(rc, c0, cm, cp, fb);
+        if (halo) pull(rc, hc0, hcm, hcp, hv);
+    }
     auto row = [&](int y, R cur[Q], R nxt[Q], R nn[Q]) {
         const unsigned sp = ((unsigned)(y + 1) & 3u) * WL;
-        ring[sp + tid + 1] = dens(nxt);
-        if (halo) ring[sp + hslot] = dens(hv);
+        if (!idle) {
+            put(y + 1, dens(nxt));
+            if (halo) ring[sp + hslot] = dens(hv);
+        }
         if (y + 1 < y1) {
             const Rows rn = rows_of(y + 2);
-            pull(rn, c0, cm, cp, nn);
-            if (halo) pull(rn, hc0, hcm, hcp, hv);
+            if (!idle) {
+                pull(rn, c0, cm, cp, nn);
+                if (halo) pull(rn, hc0, hcm, hcp, hv);
+            }
         }
         __syncthreads();
-        finish_row(y, cur, sp);
+        if (!idle) finish_row(y, cur, sp);
     };
     for (int y = y0; y < y1; y += 3) {
         row(y, fa, fb, fcq);
@@ -558,13 +582,18 @@ static void launch_step_t(const StepLaunch &a, hipStream_t s)
 {
     const dim3 grid(a.ntiles), block(a.bx);
     const size_t lds = 4 * (a.bx + 2) * sizeof(R);
-    hipLaunchKernelGGL((k_step<S, R, PLAIN, CN>), grid, block, lds, s, (const S *)a.xi, (const S *)a.fin, (S *)a.fout,
-                       a.reps, a.tiles, a.tdev, a.flags, a.toff);
+    if (a.whole)
+        hipLaunchKernelGGL((k_step<S, R, PLAIN, CN, true>), grid, block, lds, s, (const S *)a.xi, (const S *)a.fin,
+                           (S *)a.fout, a.reps, a.tiles, a.tdev, a.flags, a.toff);
+    else
+        hipLaunchKernelGGL((k_step<S, R, PLAIN, CN, false>), grid, block, lds, s, (const S *)a.xi, (const S *)a.fin,
+                           (S *)a.fout, a.reps, a.tiles, a.tdev, a.flags, a.toff);
 }
 
 hipError_t launch_step(int precision, const StepLaunch &a, hipStream_t s)
 {
-    // the correlated-noise read is compiled only into the variant for handles that have it
+    // the correlated-noise read is compiled only into the variant for handles that have it,
+    // the whole-row strip handling only into the variant for tile lists that have such strips
     const bool cn = a.xi != nullptr;
     if (precision == 0)
         cn ? launch_step_t<double, double, false, true>(a, s) : launch_step_t<double, double, false, false>(a, s);

@@ -10,6 +10,11 @@ namespace lbf {
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror & Shaw, SC'11: 10 rounds of two 32x32->64 products with the
 // multipliers 0xD2511F53 / 0xCD9E8D57 and a Weyl key schedule 0x9E3779B9 / 0xBB67AE85.
+// The three-way exclusive or of a round is one gfx950 v_bitop3_b32 (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -22,7 +27,10 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
         const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c.z;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        if (r == 0)   // the counter words above the first are uniform in the callers: scalar ops
+            c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        else
+            c = make_uint4(xor3(hi1, c.y, k0), lo1, xor3(hi0, c.w, k1), lo0);
     }
     return c;
 }
