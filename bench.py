@@ -71,16 +71,16 @@ def time_precision(torch, L, cfg, precision, steps, warmup):
     return wall, ev_ms, flags, tune
 
 
-def traffic_from_counters(tile=None):
+def traffic_from_counters(workload, tile=None):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
     scaled by the same counters' reading of a plain copy of known size; null when the
-    kernel source has changed since the counters were taken, or when this run's tile shape
-    (strip width, rows) is not the one profiled."""
+    kernel source has changed since the counters were taken, or when this run's workload or
+    tile shape (strip width, rows) is not one profiled."""
     try:
         c = json.load(open(COUNTERS))
     except (OSError, ValueError):
         return None
-    if c.get("kernel_src_sha") != kernel_sha():
+    if c.get("kernel_src_sha") != kernel_sha() or c.get("workload_key") != workload:
         return None
     if tile is None:
         return c.get("hbm_bytes_per_launch")
@@ -143,7 +143,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -196,8 +196,12 @@ def main():
                    "nx": reps[0]["nx"], "ny": reps[0]["ny"], "precision": prec, "parallelism": "single GPU",
                    "tile": {"strip_width": tune[0], "rows": tune[1], "tiles": tune[2]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_counters((tune[0], tune[1])),
-                     "kernel": "k_step<float,float,false,false,false>", "tile": "%d,%d" % (tune[0], tune[1]),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_counters(args.workload, (tune[0], tune[1])),
+                     # the whole-row-strip variant runs when some replica fits one strip
+                     "kernel": "k_step<float,float,false,false,%s>" % (
+                         "true" if any(r["nx"] <= tune[0] for r in reps) else "false"),
+                     "tile": "%d,%d" % (tune[0], tune[1]),
                      "bytes_per_update": BYTES_PER_UPDATE[prec]},
         "status_flags": flags,
     }

@@ -140,8 +140,9 @@ lb_status lb_workspace_size(const lb_params *p, int32_t n_rep, int32_t precision
  * unknown precision, init or noise kind, replica >= 2^31, correlated noise on a lattice
  * whose sides are not powers of two in [4, 8192] (LB_EINVAL); Xi(0) at rho0 not PSD (for
  * LB_NOISE_DIAGONAL: a negative diagonal entry), or for correlated noise Xi(k) not PSD at
- * some lattice k (LB_ENOTPSD).
- * Synchronous.  On success *out owns host memory only; release it with lb_free. */
+ * some lattice k (LB_ENOTPSD).  It also picks the step's launch shape (lb_tuning) and
+ * captures the HIP graph that lb_step replays.
+ * Synchronous.  On success *out owns host memory and HIP graphs; release them with lb_free. */
 lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t features,
                   void *d_workspace, size_t bytes, void *stream, lb_handle **out);
 

@@ -733,6 +733,13 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
             return LB_EDEVICE;
         }
     }
+    // capture the multi-step graph now, so that the first long lb_step does not pay for it
+    // (a few ms: several percent of a 300-step run of a 12 M-node ensemble)
+    if ((st = capture_graph(h, h->par)) != LB_OK) {
+        drop_graphs(h);
+        delete h;
+        return st;
+    }
     *out = h;
     return LB_OK;
 }
