@@ -186,7 +186,7 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
         L.sk_nmax = std::max(L.max_nx, L.max_ny);
         L.sk_G = sk_modes_per_pass(precision, L.max_nx);
         L.sk_ptot = 0;
-        for (int r = 0; r < n_rep; ++r) L.sk_ptot += (long long)p[r].ny * (p[r].nx / 2 + 1);
+        for (int r = 0; r < n_rep; ++r) L.sk_ptot += (long long)p[r].ny * sk_nh_padded(p[r].nx);
         L.sk_tw = o; o += align_up(sizeof(double) * 2 * (size_t)(L.sk_nmax / 2));
         L.sk_reps = o; o += align_up(sizeof(SkRep) * n_rep);
         L.spec = o; o += align_up((size_t)sk_elem(precision) * 9 * (size_t)L.sk_ptot);
@@ -717,7 +717,7 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
             rows += (q.ny + q.rpb - 1) / q.rpb;
             max_row = std::max(max_row, q.rpb * q.nx);
             cols += (long long)q.split * ((nh + q.cpb - 1) / q.cpb);
-            soff += (long long)q.ny * nh;
+            soff += (long long)q.ny * sk_nh_padded(q.nx);
             max_col = std::max(max_col, q.cpb * (q.ny / q.split));
             h->sk.push_back(q);
         }

@@ -131,6 +131,17 @@ int cn_col_points(int nx, int ny);
 // [r0, r1) of replicas with one launch per kernel, whatever their sizes.
 constexpr int SK_MAX = 16384;       // largest side the sampler transforms
 
+// One mode's row spectrum of a replica is stored in chunks of SK_KG adjacent kx: [chunk][ky][SK_KG]
+// complex values, so that the column pass reads each chunk's rows as one contiguous run (a
+// plain [ky][nh] layout puts consecutive ky of one kx a row apart and every read in another
+// HBM page).  nh = nx/2 + 1 is padded to a multiple of SK_KG.
+constexpr int SK_KG = 16;
+__host__ __device__ inline long long sk_nh_padded(int nx) { return (long long)((nx / 2 + SK_KG) / SK_KG) * SK_KG; }
+__host__ __device__ inline long long sk_at(int ky, int kx, int ny)
+{
+    return ((long long)(kx / SK_KG) * ny + ky) * SK_KG + (kx % SK_KG);
+}
+
 struct SkRep {
     int32_t nx, ny, lognx, logny;
     int32_t split;      // column blocks per kx: 1, or 2 (one per output parity) when a column does not fit
@@ -139,7 +150,7 @@ struct SkRep {
     int32_t logrpb;     // log2(rpb)
     int64_t row0;       // first row block of this replica (prefix of ceil(ny / rpb))
     int64_t col0;       // first column block (prefix of split * ceil(nh / cpb)), nh = nx/2 + 1
-    int64_t soff;       // offset (complex elements) of its [ny][nh] spectrum inside one mode slot
+    int64_t soff;       // offset (complex elements) of its spectrum (sk_at layout) inside one mode slot
     int64_t acc_off;    // offset (double) of its [9][nh][ny] accumulators
 };
 
@@ -153,7 +164,7 @@ struct SkLaunch {
     int32_t lds_rows;         // most row points per block in the range (rpb * nx)
     int32_t lds_cols;         // most column points per block in the range (cpb * ny, or ny/2 if split)
     int32_t G;                // modes per transform group of the row kernel
-    int64_t Ptot;             // complex elements per mode slot (sum of ny * nh over all replicas)
+    int64_t Ptot;             // complex elements per mode slot (sum of ny * sk_nh_padded(nx) over all replicas)
     void *spec;               // nine mode slots of row spectra (float2 for FP32 storage, else double2)
     double *acc;
     double *base;             // [replica][18]: reference moments (FP64) and populations of the last sample

@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(SK_THREADS)
     const int r = sk_find<0>(sk, r0, r1, gr);
     const SkRep &q = sk[r];
     const RepDesc &d = reps[r];
-    const int nx = q.nx, ny = q.ny, M = nx >> 1, logM = q.lognx - 1, nh = M + 1;
+    const int nx = q.nx, ny = q.ny, M = nx >> 1, logM = q.lognx - 1;
     const int y0 = (int)(gr - q.row0) * q.rpb;
     const int R = min(q.rpb, ny - y0);          // rows of this block
     const int Rp = q.rpb, lRp = q.logrpb;       // transform (c, rr) at X[(c Rp + rr) M]
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(SK_THREADS)
             const C E = mk2(h * (Zk.x + Zm.x), h * (Zk.y - Zm.y));
             const C O = mk2(h * (Zk.y + Zm.y), -h * (Zk.x - Zm.x));
             const C W = k < M ? twiddle(T, k * wstride) : mk2((Tt)-1, (Tt)0);
-            spec[(a0 + c) * Ptot + q.soff + (long long)(y0 + rr) * nh + k] = cadd(E, cmul(W, O));
+            spec[(a0 + c) * Ptot + q.soff + sk_at(y0 + rr, k, ny)] = cadd(E, cmul(W, O));
         };
         for (int idx = threadIdx.x; idx < nt << logM; idx += blockDim.x) untangle(idx >> logM, idx & (M - 1));
         for (int t = threadIdx.x; t < nt; t += blockDim.x) untangle(t, M);
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(SK_THREADS)
     const int kx0 = grp * q.cpb;
     const int C_ = min(q.cpb, nh - kx0);         // columns of this block
     const int a = a_first + blockIdx.y;
-    const C *S0 = spec + a * Ptot + q.soff + kx0;    // (y, c) at S0[y * nh + c]
+    const C *S0 = spec + a * Ptot + q.soff;    // (y, kx) at S0[sk_at(y, kx, ny)]
     const double inv_n = 1.0 / ((double)q.nx * (double)ny);
     // added to the real part of output 0 of this block when that output is k = 0
     const double k0 = kx0 == 0 && par == 0 ? (double)q.nx * (double)ny * base[18 * r + a] : 0.0;
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(SK_THREADS)
             for (int u = 0; u < 4; ++u) {
                 const int e = min(e0 + u * (int)blockDim.x, tot - 1), y = e >> lCp;
                 const int c = min(e & ((1 << lCp) - 1), C_ - 1);
-                v[u] = S0[(long long)y * nh + c];
+                v[u] = S0[sk_at(y, kx0 + c, ny)];
             }
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u * (int)blockDim.x, y = e >> lCp, c = e & ((1 << lCp) - 1);
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(SK_THREADS)
         // X_{2k+p} = sum_n [x_n + (-1)^p x_{n+L}] W^{pn} exp(-2 pi i n k / L), W = exp(-2 pi i / ny)
         const int wstride = nmax / ny;
         for (int n = threadIdx.x; n < L; n += blockDim.x) {
-            const C u = S0[(long long)n * nh], v = S0[(long long)(n + L) * nh];
+            const C u = S0[sk_at(n, kx0, ny)], v = S0[sk_at(n + L, kx0, ny)];
             X[lds_at(bitrev((unsigned)n, logL), sh)] = par == 0 ? cadd(u, v) : cmul(csub(u, v), twiddle(T, n * wstride));
         }
     }
