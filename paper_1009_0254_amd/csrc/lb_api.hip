@@ -7,6 +7,7 @@
 // multi-step runs.
 
 #include "lb_internal.h"
+#include "lb_sklayout.h"
 #include "lbfluct.h"
 
 #include <math.h>

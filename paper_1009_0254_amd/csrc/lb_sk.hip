@@ -33,6 +33,7 @@
 
 #include "lb_fftcore.h"
 #include "lb_internal.h"
+#include "lb_sklayout.h"
 
 namespace lbf {
 
