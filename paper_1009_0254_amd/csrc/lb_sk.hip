@@ -474,7 +474,8 @@ template <typename K> hipError_t lds_limit(K kernel, size_t bytes)
 template <typename S, typename Tt> hipError_t lds_limits_of(size_t rows, size_t cols)
 {
     hipError_t e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, false>, rows);
-    if (e == hipSuccess && sizeof(Tt) == 4) e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, true>, rows);
+    if constexpr (sizeof(Tt) == 4)   // the register-cached row variant exists for FP32 only
+        if (e == hipSuccess) e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, true>, rows);
     if (e == hipSuccess) e = lds_limit(k_sk_cols<Tt, false, SK_COL_RADIX<Tt>>, cols);
     if (e == hipSuccess) e = lds_limit(k_sk_cols<Tt, true, SK_COL_RADIX<Tt>>, cols);
     return e;
