@@ -567,6 +567,47 @@ def test_full_size_8192_sampled_parity():
     lat.close()
 
 
+@pytest.mark.parametrize("shape,tile", [((1 << 24, 3), None), ((3, 1 << 24), "64,64")], ids=["widest", "tallest"])
+def test_extreme_lattice_shapes_sampled(monkeypatch, shape, tile):
+    """The widest lattice the ABI admits (nx = 2^24: a row of 9 nx FP64 values is the largest
+    range a buffer descriptor addresses here) and a three-column lattice 2^24 rows tall, 50 M
+    nodes each, noisy: two steps in FP32-shifted and FP64 storage against the oracle at
+    sampled nodes, and exact mass conservation."""
+    L = _L()
+    if tile:
+        monkeypatch.setenv("LBF_TILE", tile)
+    nx, ny = shape
+    cfg = W.wave(W.single_phase(nx, ny, kT=1e-5, seed=5), 3, 1, 1e-4, 1e-4, 0)
+    ora = O.Oracle(cfg)
+    ora.step(2)
+    mo_all = ora.moments().reshape(9, -1)
+    del ora
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([rng.integers(0, nx * ny, size=200_000), [0, nx - 1, nx * ny - 1, nx * (ny - 1)]])
+    mo = mo_all[:, idx]
+    scale = np.abs(mo - mo.mean(axis=1, keepdims=True)).max(axis=1)
+    for precision in (2, 0):
+        say("extreme shape", nx, ny, "precision", precision)
+        lat = L.Lattice(cfg, precision=precision)
+        lat.step(1)
+        lat.step(1)
+        mg, _ = lat.lb_moments(0, True)
+        mg = mg.reshape(9, -1)[:, torch.from_numpy(idx).to(mg.device)].cpu().numpy()
+        t = lat.totals()
+        assert lat.lb_status_flags() == (0, 2)
+        lat.close()
+        if precision == 0:
+            err = np.abs(mg - mo).max(axis=1) / np.maximum(1.0, np.abs(mo).max(axis=1))
+            say("  fp64 abs err", err.max())
+            assert err.max() <= 2e-12
+            assert abs(t[0] - nx * ny) / (nx * ny) < 1e-13
+        else:
+            e = np.abs(mg - mo).max(axis=1) / scale
+            say("  fp32s err", e)
+            assert e.max() < 2e-3
+            assert abs(t[0] - nx * ny) / (nx * ny) < 1e-9
+
+
 def test_full_size_8192_structure_factor_sampled():
     """One S(k) sample of the bench workload (8192^2 single phase, FP32-shifted storage, the
     batched launch bench.py times) after two steps against the oracle's |m_a(k)|^2 / n of its
