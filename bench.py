@@ -144,7 +144,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=64)
-    ap.add_argument("--workload", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--workload", default="single_phase_8192", choices=["slab_2048", "single_phase_8192", "ensemble_336", "quench_16384"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
@@ -166,7 +166,7 @@ def main():
     from paper_1009_0254_amd import lbfluct as L
     from paper_1009_0254_amd import workloads as W
 
-    cfg = {"cfg2": W.cfg2, "cfg3": W.cfg3, "cfg4": W.cfg4, "cfg5": W.cfg5}[args.workload]()
+    cfg = {"slab_2048": W.slab_2048, "single_phase_8192": W.single_phase_8192, "ensemble_336": W.ensemble_336, "quench_16384": W.quench_16384}[args.workload]()
     prec = "fp32s"
     reps = cfg if isinstance(cfg, list) else [cfg]
     n = sum(r["nx"] * r["ny"] for r in reps)

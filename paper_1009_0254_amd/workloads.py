@@ -86,22 +86,22 @@ def wave(base: dict, kx: int, ky: int, a_rho: float = 0.0, a_ux: float = 0.0, a_
 
 
 # the five lattice workloads, in order
-def cfg1() -> dict:
+def single_phase_64() -> dict:
     """64x64 single phase, kT = 1e-5, seed 1, 2000 steps, FP64."""
     return dict(single_phase(64, 64, kT=1e-5, seed=1), steps=2000, precision="fp64")
 
 
-def cfg2() -> dict:
+def slab_2048() -> dict:
     """2048x2048 two-phase slab, kT = 1e-6, 10k steps, FP64 vs FP32."""
     return dict(slab(2048, 2048, kT=1e-6, seed=1), steps=10000, precision="fp32s")
 
 
-def cfg3(seed: int = 7) -> dict:
+def single_phase_8192(seed: int = 7) -> dict:
     """8192x8192 single phase, kT = 1e-5, FP32-shifted vs FP64, S(k) over 20k steps."""
     return dict(single_phase(8192, 8192, kT=1e-5, seed=seed), steps=20000, precision="fp32s")
 
 
-def cfg4(seed: int = 11) -> list:
+def ensemble_336(seed: int = 11) -> list:
     """Uneven ensemble: 256 x 128^2, 64 x 256^2, 16 x 512^2; kT log-uniform in [1e-6, 1e-4].
 
     The per-replica kT is drawn here from Python's own seeded generator; it is an input
@@ -118,12 +118,12 @@ def cfg4(seed: int = 11) -> list:
     return reps
 
 
-def cfg5(seed: int = 5) -> dict:
+def quench_16384(seed: int = 5) -> dict:
     """16384x16384 spinodal quench, rho = 1 + 0.01 N(0,1), kT = 1e-6, FP32-shifted."""
     return dict(spinodal(16384, 16384, kT=1e-6, seed=seed), steps=50000, precision="fp32s")
 
 
-def e3(nx: int = 128, ny: int = 128, kT: float = 1e-7, seed: int = 4) -> dict:
+def correlated_sec5a(nx: int = 128, ny: int = 128, kT: float = 1e-7, seed: int = 4) -> dict:
     """Correlated-noise equilibration run of Sec. V.A (kappa = 0.08, c_s ~ 0.265, tau = 1).
 
     Double well with rho_V = 0.5, rho_L = 1, beta = 0.14, run in the liquid at rho0 = 1."""
@@ -133,7 +133,7 @@ def e3(nx: int = 128, ny: int = 128, kT: float = 1e-7, seed: int = 4) -> dict:
                 kT=kT, seed=seed, init="uniform", noise="correlated")
 
 
-def e4(nx: int = 128, ny: int = 128, kT: float = 1e-7, seed: int = 3) -> dict:
+def uncorrelated_sec5a(nx: int = 128, ny: int = 128, kT: float = 1e-7, seed: int = 3) -> dict:
     """Uncorrelated-noise equilibration run of Sec. V.A (kappa = 0.03, c_s ~ 0.15, tau = 1).
 
     Double well with rho_V = 0.1, rho_L = 1, beta = 0.015, run in the liquid at rho0 = 1."""

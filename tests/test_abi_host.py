@@ -137,9 +137,9 @@ def test_validation_rejects_bad_precision_and_count():
 
 
 def test_all_workloads_validate():
-    for cfg in (W.cfg1(), W.cfg2(), W.cfg3(), W.cfg5(), W.e4(), W.e3()):
+    for cfg in (W.single_phase_64(), W.slab_2048(), W.single_phase_8192(), W.quench_16384(), W.uncorrelated_sec5a(), W.correlated_sec5a()):
         assert L.lb_workspace_size([cfg], L.LB_FP32_SHIFTED) > 0
-    reps = W.cfg4()
+    reps = W.ensemble_336()
     assert len(reps) == 336
     assert sum(r["nx"] * r["ny"] for r in reps) == 12_582_912
     assert L.lb_workspace_size(reps, L.LB_FP32_SHIFTED) > 2 * 9 * 12_582_912 * 4
@@ -161,7 +161,7 @@ def test_structure_factor_feature_size_rules():
     # accumulators and the FP32 complex row spectra of the nine modes
     n = 16384 * 16384
     want = 2 * 9 * n * 4 + n * 8 + 9 * 16384 * 8193 * 8 + 9 * 16384 * 8193 * 8
-    b = L.lb_workspace_size([W.cfg5()], L.LB_FP32_SHIFTED, F)
+    b = L.lb_workspace_size([W.quench_16384()], L.LB_FP32_SHIFTED, F)
     assert want <= b < want + (64 << 20)
 
 
@@ -206,25 +206,25 @@ def test_bench_traffic_is_tied_to_the_profiled_kernel_workload_and_tile(tmp_path
     sys.path.insert(0, ROOT)
     import bench
     sha = bench.kernel_sha()
-    c = {"kernel_src_sha": sha, "workload_key": "cfg3", "hbm_bytes_per_launch": 1.0,
+    c = {"kernel_src_sha": sha, "workload_key": "single_phase_8192", "hbm_bytes_per_launch": 1.0,
          "per_tile": {"512,8": {"hbm_bytes_per_launch": 5.0}, "256,16": {"hbm_bytes_per_launch": 4.0}}}
     f = tmp_path / "c.json"
     f.write_text(json.dumps(c))
     monkeypatch.setattr(bench, "COUNTERS", str(f))
-    assert bench.traffic_from_counters("cfg3", (512, 8)) == 5.0
-    assert bench.traffic_from_counters("cfg3", (256, 16)) == 4.0
-    assert bench.traffic_from_counters("cfg3", (128, 8)) is None
-    assert bench.traffic_from_counters("cfg4", (512, 8)) is None
+    assert bench.traffic_from_counters("single_phase_8192", (512, 8)) == 5.0
+    assert bench.traffic_from_counters("single_phase_8192", (256, 16)) == 4.0
+    assert bench.traffic_from_counters("single_phase_8192", (128, 8)) is None
+    assert bench.traffic_from_counters("ensemble_336", (512, 8)) is None
     c["kernel_src_sha"] = "0" * 16
     f.write_text(json.dumps(c))
-    assert bench.traffic_from_counters("cfg3", (512, 8)) is None
+    assert bench.traffic_from_counters("single_phase_8192", (512, 8)) is None
     assert len(sha) == 16
 
 
 def test_committed_counters_name_their_workload_and_tiles():
     import json
     c = json.load(open(os.path.join(ROOT, "profiles", "k_step_fp32s_8192_counters.json")))
-    assert c["workload_key"] == "cfg3" and c["tile"] in c["per_tile"]
+    assert c["workload_key"] == "single_phase_8192" and c["tile"] in c["per_tile"]
     for t, v in c["per_tile"].items():
         w, r = (int(s) for s in t.split(","))
         assert w % 64 == 0 and r >= 4 and v["hbm_bytes_per_launch"] > 72 * 8192 * 8192 * 0.9

@@ -179,11 +179,11 @@ def test_fp32_plain_is_reported():
 
 
 NOISY = [
-    ("cfg1_64", lambda: W.cfg1(), 2000),
+    ("single_phase_64", lambda: W.single_phase_64(), 2000),
     ("ragged", lambda: W.single_phase(72, 50, kT=1e-5, seed=17, replica=3), 500),
     ("tiny", lambda: W.single_phase(3, 5, kT=1e-5, seed=2), 300),
     ("slab", lambda: W.slab(64, 128, kT=1e-6, seed=5), 500),
-    ("e4", lambda: W.e4(64, 64, kT=1e-7), 500),
+    ("uncorrelated_sec5a", lambda: W.uncorrelated_sec5a(64, 64, kT=1e-7), 500),
     ("diagonal", lambda: W.single_phase(64, 48, kT=1e-5, seed=9, c0sq=0.0, A=0.05, noise="diagonal"), 400),
 ]
 
@@ -348,7 +348,7 @@ def test_conservation_fp64_and_fp32s():
 
 def test_status_flags_clean_and_clamp():
     L = _L()
-    lat = L.Lattice(W.cfg1(), precision=2)
+    lat = L.Lattice(W.single_phase_64(), precision=2)
     lat.step(100)
     f, t = lat.lb_status_flags()
     assert f == 0 and t == 100
@@ -520,7 +520,7 @@ def test_radial_snapshot_16384_plane_wave_closed_form():
     L = _L()
     nx = ny = 16384
     a = 0.02
-    cfg = W.wave(W.cfg5(), 3, 4, a)
+    cfg = W.wave(W.quench_16384(), 3, 4, a)
     say("snapshot 16384^2 wave")
     lat = L.Lattice(cfg, precision=2, structure_factor=True)
     out = lat.lb_structure_factor(L.LB_SK_SNAPSHOT, 0).cpu().numpy()
@@ -547,7 +547,7 @@ def test_full_size_8192_sampled_parity():
     """The bench workload (8192^2 single phase, FP32-shifted, autotuned tiles): one and
     two steps against the oracle on the full lattice, compared at sampled nodes."""
     L = _L()
-    cfg = W.cfg3()
+    cfg = W.single_phase_8192()
     lat = L.Lattice(cfg, precision=2)
     ora = O.Oracle(cfg)
     rng = np.random.default_rng(0)
@@ -619,7 +619,7 @@ def test_full_size_8192_structure_factor_sampled():
     whose X(0) = sum_r m_a(r) adds the FP32 trajectory's per-node differences (1.6e-7 of the
     range after two steps) coherently, up to ~ sqrt(n) 1.6e-7 ~ 1e-2 in the worst case."""
     L = _L()
-    cfg = W.cfg3()
+    cfg = W.single_phase_8192()
     nx, ny = cfg["nx"], cfg["ny"]
     lat = L.Lattice(cfg, precision=2, structure_factor=True)
     ora = O.Oracle(cfg)
@@ -658,7 +658,7 @@ def test_full_size_8192_equipartition_transient():
     noise (the stationary one is still far away for the slow modes), at 60,000 random k of the
     half plane: per mode the k-summed ratio within 2% (standard error ~0.5%)."""
     L = _L()
-    cfg = W.cfg3()
+    cfg = W.single_phase_8192()
     nx, ny, t = cfg["nx"], cfg["ny"], 200
     lat = L.Lattice(cfg, precision=2, structure_factor=True)
     lat.step(t)
@@ -685,7 +685,7 @@ def test_full_size_8192_equipartition_transient():
 
 
 def test_full_size_16384_quench_growth_follows_linear_theory():
-    """The 16384^2 quench (the bench's cfg5 workload at full size, FP32-shifted) after 50 steps,
+    """The 16384^2 quench (the bench's quench_16384 workload at full size, FP32-shifted) after 50 steps,
     radially binned: in shells across the unstable band and beyond it, S(t) = S(0)
     <|[M(k)^t v(k)]_rho|^2> + <G_rho,rho(k, t)> over the shell's k, with v(k) the linearised
     Table II of a pure density perturbation (the initial state) and G the noise's transient
@@ -693,7 +693,7 @@ def test_full_size_16384_quench_growth_follows_linear_theory():
     total and the nonlinear corrections at this amplitude (delta rho ~ 0.02) ~0.7%.  The shell
     counts equal the exact integer enumeration."""
     L = _L()
-    cfg = W.cfg5()
+    cfg = W.quench_16384()
     nx, ny, t = cfg["nx"], cfg["ny"], 50
     lat = L.Lattice(cfg, precision=2, structure_factor=True)
     s0 = lat.lb_structure_factor(L.LB_SK_SNAPSHOT, 0).cpu().numpy()
@@ -723,10 +723,10 @@ def test_full_size_16384_quench_growth_follows_linear_theory():
         assert abs(s1[0][sh] / want - 1) < 0.03
 
 
-FULL_GATES = {"cfg2": 2e-4, "cfg5": 6e-4}   # the FP32 floors of the two-phase slab and the quench
+FULL_GATES = {"slab_2048": 2e-4, "quench_16384": 6e-4}   # the FP32 floors of the two-phase slab and the quench
 
 
-@pytest.mark.parametrize("name", ["cfg2", "cfg5"])
+@pytest.mark.parametrize("name", ["slab_2048", "quench_16384"])
 def test_full_size_two_phase_workloads_sampled(name):
     """The 2048^2 slab and the 16384^2 spinodal quench at full size, in the launch configuration
     bench.py times (FP32-shifted, autotuned tiles): two steps against the oracle at 200,000
@@ -758,7 +758,7 @@ def test_full_size_ensemble_sampled_replicas():
     decades) in one launch, FP32-shifted: two steps against the oracle for the first and last
     replica of each size class."""
     L = _L()
-    cfgs = W.cfg4()
+    cfgs = W.ensemble_336()
     lat = L.Lattice(cfgs, precision=2)
     lat.step(2)
     worst = 0.0
@@ -869,7 +869,7 @@ def test_uncorrelated_noise_run_of_sec_VA_at_128(precision):
     as G_unc / G predicts, where the text reports < 10%."""
     L = _L()
     nx = ny = 128
-    cfg = W.e4(nx, ny, kT=1e-7, seed=61 + precision)
+    cfg = W.uncorrelated_sec5a(nx, ny, kT=1e-7, seed=61 + precision)
     lat = L.Lattice(cfg, precision=precision, structure_factor=True)
     lat.lb_set_sampling(10, 15000)
     lat.step(15000 + 30000)
@@ -907,7 +907,7 @@ def test_uncorrelated_noise_run_of_sec_VA_at_128(precision):
 def test_correlated_noise_parity(precision):
     """Exact Xi(k) noise: the GPU's FFT-filtered fields and step against the oracle's numpy-FFT
     fields and FP64 step, same Philox streams."""
-    cfg = W.e3(32, 16, kT=1e-6, seed=12)
+    cfg = W.correlated_sec5a(32, 16, kT=1e-6, seed=12)
     cfg["replica"] = 3
     mg, mo = run_pair(cfg, precision, 120, chunks=2)
     e = rel_err(mg, mo)
@@ -933,7 +933,7 @@ def test_correlated_noise_parity_long_lines(precision, shape):
     the fields go through FP32 transforms (rounding ~ 3e-7 of their scale) on top of FP32
     normals (3e-6 per draw)."""
     nx, ny, steps = shape
-    cfg = dict(W.cfg3(), nx=nx, ny=ny, noise="correlated", seed=17)
+    cfg = dict(W.single_phase_8192(), nx=nx, ny=ny, noise="correlated", seed=17)
     mg, mo = run_pair(cfg, precision, steps, chunks=2)
     e = rel_err(mg, mo)
     if precision == 0:
@@ -947,8 +947,8 @@ def test_correlated_noise_parity_long_lines(precision, shape):
 
 def test_correlated_and_uncorrelated_replicas_in_one_handle():
     L = _L()
-    cfgs = [W.e3(32, 32, kT=1e-6, seed=1), W.e4(48, 40, kT=1e-7, seed=2),
-            dict(W.e3(16, 64, kT=1e-6, seed=3), replica=2)]
+    cfgs = [W.correlated_sec5a(32, 32, kT=1e-6, seed=1), W.uncorrelated_sec5a(48, 40, kT=1e-7, seed=2),
+            dict(W.correlated_sec5a(16, 64, kT=1e-6, seed=3), replica=2)]
     lat = L.Lattice(cfgs, precision=0)
     lat.step(70)
     for r, c in enumerate(cfgs):
@@ -967,7 +967,7 @@ def test_correlated_noise_equilibrates_to_paper_G_at_all_k(precision, nx):
     reach G(k) of eq. (g-mat-yeo) at every k -- here within 1% on average and 5% per shell."""
     L = _L()
     ny = nx
-    cfg = W.e3(nx, ny, kT=1e-6, seed=77 + precision + nx)
+    cfg = W.correlated_sec5a(nx, ny, kT=1e-6, seed=77 + precision + nx)
     lat = L.Lattice(cfg, precision=precision, structure_factor=True)
     # burn-in and sampling interval grow with the slowest relaxation time, ~ (nx / 2 pi)^2 / nu
     burn, every, nsamp = (2000, 8, 3000) if nx == 64 else (8000, 20, 3000)
@@ -1076,7 +1076,7 @@ def test_ensemble_size_class_equipartition():
     linear model) is 1 within 0.5% for every mode, and the replicas agree with each other
     (the spread of the per-replica means is the sampling error's, not a kT trend)."""
     L = _L()
-    reps = [r for r in W.cfg4() if r["nx"] == 128]
+    reps = [r for r in W.ensemble_336() if r["nx"] == 128]
     assert len(reps) == 256
     lat = L.Lattice(reps, precision="fp32s", structure_factor=True)
     burn, every, nsamp = 16000, 20, 500

@@ -18,7 +18,7 @@ from paper_1009_0254_amd import workloads as W
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _cfg1_like(nx, ny, **kw):
+def _single_phase_like(nx, ny, **kw):
     return W.single_phase(nx, ny, **kw)
 
 
@@ -88,7 +88,7 @@ def test_normals_depend_on_every_counter_field():
 @pytest.mark.parametrize("kxi,kyi", [(1, 0), (3, 2), (8, 8), (5, 7)])
 def test_laplacian_symbol_appB(kxi, kyi):
     nx = ny = 16
-    cfg = _cfg1_like(nx, ny)
+    cfg = _single_phase_like(nx, ny)
     kx, ky = 2 * np.pi * kxi / nx, 2 * np.pi * kyi / ny
     y, x = np.mgrid[0:ny, 0:nx]
     rho = np.cos(kx * x + ky * y)
@@ -113,7 +113,7 @@ def test_linearised_equilibrium(c0sq, A):
     """Table II linearised on a small density wave gives {d rho, 0, 0, d(k) d rho, 0,0,0,0, -d(k) d rho},
     eq. (eq-mom-yeo)."""
     nx = ny = 16
-    cfg = _cfg1_like(nx, ny, c0sq=c0sq, A=A)
+    cfg = _single_phase_like(nx, ny, c0sq=c0sq, A=A)
     kx, ky = 2 * np.pi * 3 / nx, 2 * np.pi * 1 / ny
     eps = 1e-7
     y, x = np.mgrid[0:ny, 0:nx]
@@ -130,7 +130,7 @@ def test_linearised_equilibrium(c0sq, A):
 
 
 def test_bulk_thermodynamics():
-    cfg = _cfg1_like(4, 4)
+    cfg = _single_phase_like(4, 4)
     p = O.make_params(cfg)
     for rho in (0.7, 1.0, 1.3):
         assert np.isclose(O.lib().lbo_pressure(p, rho), th.pressure(rho, cfg["c0sq"], cfg["A"], cfg["B"]))
@@ -160,7 +160,7 @@ def test_paper_free_energy_mapping():
 def test_noise_covariance_matches_fdt(c0sq, A, rho):
     """Empirical covariance of the oracle's xi equals Xi(0) = -G Omega^T - Omega G - Omega G Omega^T
     (eq. noise-matrix-k0) built from G (eq. g-mat-yeo) and Omega (eq. coll-op-yeo) at the local rho."""
-    cfg = _cfg1_like(4, 4, c0sq=c0sq, A=A, kT=1e-5, tau_q=0.9, tau_eps=1.3)
+    cfg = _single_phase_like(4, 4, c0sq=c0sq, A=A, kT=1e-5, tau_q=0.9, tau_eps=1.3)
     cs2 = _cs2(cfg, rho)
     n = 200_000
     xi = O.noise_samples(cfg, rho, cs2, t=3, n=n)
@@ -179,7 +179,7 @@ def test_noise_covariance_matches_fdt(c0sq, A, rho):
 
 
 def test_conservation_and_staggered_momentum():
-    cfg = _cfg1_like(24, 16, kT=1e-5, seed=9)
+    cfg = _single_phase_like(24, 16, kT=1e-5, seed=9)
     o = O.Oracle(cfg)
     o.step(5)
     prev = o.totals()
@@ -195,7 +195,7 @@ def test_conservation_and_staggered_momentum():
 
 
 def test_restart_is_bitwise():
-    cfg = _cfg1_like(12, 10, kT=1e-5, seed=4)
+    cfg = _single_phase_like(12, 10, kT=1e-5, seed=4)
     a = O.Oracle(cfg)
     a.step(30)
     b = O.Oracle(cfg)
@@ -221,7 +221,7 @@ LIN_CASES = [
 def test_linear_evolution_matches_M_k(label, over, kk, amps, nx, ny, steps):
     """Small-amplitude waves follow dm(k, t) = M(k)^t dm(k, 0), M = A(-k)(I + Omega(k)),
     eq. (lb-lang-ft) with eq. (coll-op-yeo) and the App. B Laplacian."""
-    base = _cfg1_like(nx, ny, kT=0.0, **over)
+    base = _single_phase_like(nx, ny, kT=0.0, **over)
     cfg = W.wave(base, kk[0], kk[1], *amps)
     kx, ky = 2 * np.pi * kk[0] / nx, 2 * np.pi * kk[1] / ny
     o = O.Oracle(cfg)
@@ -248,7 +248,7 @@ def test_linear_evolution_in_uniform_flow(kk, amps):
     carried along at the flow speed (phase rotation k U per step)."""
     U = 0.02
     nx, ny = 32, 16
-    base = _cfg1_like(nx, ny, kT=0.0, tau_bulk=0.7, tau_shear=0.9)
+    base = _single_phase_like(nx, ny, kT=0.0, tau_bulk=0.7, tau_shear=0.9)
     cfg = W.wave(base, kk[0], kk[1], *amps, U=U)
     kx, ky = 2 * np.pi * kk[0] / nx, 2 * np.pi * kk[1] / ny
     o = O.Oracle(cfg)
@@ -367,7 +367,7 @@ def test_equipartition_uncorrelated_noise():
     Xi(0) (Sec. III.B stationarity, eq. noise-matrix-k0), within sampling error; momentum
     meets <j j> = rho0 kT at small k (eq. momtm-fluct)."""
     nx = ny = 24
-    cfg = _cfg1_like(nx, ny, kT=1e-5, seed=21)
+    cfg = _single_phase_like(nx, ny, kT=1e-5, seed=21)
     o = O.Oracle(cfg)
     o.step(1500)
     acc = np.zeros((9, ny, nx // 2 + 1))
@@ -410,7 +410,7 @@ def test_equipartition_uncorrelated_noise():
 def test_diagonal_noise_covariance():
     """The "ideal-gas-like" variant of Sec. IV: xi has the diagonal of Xi(0) and no 4-9
     cross-correlation."""
-    cfg = _cfg1_like(4, 4, c0sq=0.0, A=-0.01, kT=1e-5, tau_q=0.9, tau_eps=1.3, noise="diagonal")
+    cfg = _single_phase_like(4, 4, c0sq=0.0, A=-0.01, kT=1e-5, tau_q=0.9, tau_eps=1.3, noise="diagonal")
     rho = 1.0
     cs2 = _cs2(cfg, rho)
     n = 200_000
@@ -443,7 +443,7 @@ def test_equipartition_diagonal_noise():
     driven by diag Xi(0) (not the Cholesky one: the targets differ), and the hydrodynamic modes
     reach the paper's G(k) at small k, as Sec. IV reports."""
     nx = ny = 24
-    cfg = _cfg1_like(nx, ny, kT=1e-5, seed=23, c0sq=0.0, A=0.05, noise="diagonal")   # c_s^2 = 0.05
+    cfg = _single_phase_like(nx, ny, kT=1e-5, seed=23, c0sq=0.0, A=0.05, noise="diagonal")   # c_s^2 = 0.05
     o = O.Oracle(cfg)
     o.step(1500)
     acc = np.zeros((9, ny, nx // 2 + 1))
@@ -491,7 +491,7 @@ def test_correlated_noise_fields_have_the_fdt_spectrum():
     """<xi_a(k) xi_b(-k)> of the generated fields equals Xi(k) from the FDT product form
     A G A(-k)^T - (I + Omega) G (I + Omega(-k))^T (eq. noise-matrix) for a, b in {4, 9}."""
     nx, ny = 16, 12
-    cfg = W.e3(nx, ny, kT=1e-6, seed=5)
+    cfg = W.correlated_sec5a(nx, ny, kT=1e-6, seed=5)
     lam = _lam(cfg)
     cs2 = _cs2(cfg)
     acc44 = np.zeros((ny, nx)); acc99 = np.zeros((ny, nx)); acc49 = np.zeros((ny, nx))
@@ -526,7 +526,7 @@ def test_equipartition_with_correlated_noise_matches_paper_G():
     """With the exact Xi(k) every mode equilibrates to the paper's G(k) (eq. g-mat-yeo) at all k
     (Sec. V.A, Fig. 3 parameters: kappa = 0.08, c_s = 0.265, tau = 1)."""
     nx = ny = 16
-    cfg = W.e3(nx, ny, kT=1e-6, seed=9)
+    cfg = W.correlated_sec5a(nx, ny, kT=1e-6, seed=9)
     o = O.Oracle(cfg)
     o.step(300)
     acc = np.zeros((9, ny, nx // 2 + 1))
@@ -746,7 +746,7 @@ def test_paper_parameter_points_lie_in_the_allowed_region():
     equilibration runs of Sec. V.A are inside the PSD region and on the stable side of the
     dashed curve xi = 4 (eq. interf-width), as the text requires."""
     lam = th.relaxation_rates(1.0, 1.0, 1.0, 1.0)
-    for cfg in (W.e3(), W.e4()):
+    for cfg in (W.correlated_sec5a(), W.uncorrelated_sec5a()):
         cs2 = _cs2(cfg)
         assert th.psd_all_k(cfg["kappa"], cs2, lam, nk=33)
         assert th.interface_width_paper(cfg["kappa"], cs2) >= 4.0
