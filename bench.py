@@ -3,7 +3,7 @@
 
 Workload (default): 8192 x 8192 periodic single phase (rho0 = 1, A = 0.05, B = 0.04,
 kappa = 0.02, c0sq = 1/3, tau_s = tau_b = 0.8, kT = 1e-5), populations stored in FP32 as
-deviations from w_i rho0, every step with noise.  A "step" is one pass of the whole
+deviations from the rest state (w_i rho0 here), every step with noise.  A "step" is one pass of the whole
 update (pull-stream, density halo, stencils, equilibrium, Philox noise, MRT relaxation,
 store) over the lattice.  The same workload is also timed with FP64 storage.
 
@@ -30,7 +30,7 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_step_fp32s_8192_counters.json")
 # the byte counters depend on the step kernel (its source, RNG and shared structs) and on the
 # tile list that lb_init builds
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1009_0254_amd", "csrc", f)
-               for f in ("lb_kernels.hip", "lb_rng.h", "lb_internal.h", "lb_tiles.hip")]
+               for f in ("lb_kernels.hip", "lb_collide.h", "lb_rng.h", "lb_internal.h", "lb_tiles.hip")]
 
 
 def log(*a):

@@ -56,11 +56,14 @@ enum {
     LB_ESTATE = -6      /* call not valid in the handle's state (e.g. S(k) not enabled) */
 };
 
-/* storage precision of the populations */
+/* storage precision of the populations.  The shifted storages hold deviations from the
+   model's rest state fbar = T^-1 m^eq(rho0, u = 0) (Table II at rest: density rho0, moment 4
+   at 6 (p0(rho0) - rho0/3), moment 9 at its negative, all others zero), which is w_i rho0
+   when p0(rho0) = rho0/3; the collision works on those deviations throughout. */
 enum {
-    LB_FP64 = 0,          /* double storage of f_i - w_i rho0, double arithmetic */
+    LB_FP64 = 0,          /* double storage of f_i - fbar_i, double arithmetic */
     LB_FP32 = 1,          /* float storage of f_i, float arithmetic */
-    LB_FP32_SHIFTED = 2   /* float storage of f_i - w_i rho0, float arithmetic */
+    LB_FP32_SHIFTED = 2   /* float storage of f_i - fbar_i, float arithmetic */
 };
 
 /* initial condition: f(r, 0) = T^-1 m^eq(rho_init, u_init) with Table II's square-gradient

@@ -178,9 +178,12 @@ static double lam_of(const lbo_params *p, int a)
 static double bulk_pressure(const lbo_params *p, double rho)
 {
     double x = rho - p->rhoc;
-    /* p0 = rho psi' - psi with psi = c0sq rho ln rho + A/2 x^2 + B/4 x^4 */
-    double psi = p->c0sq * rho * log(rho) + 0.5 * p->A * x * x + 0.25 * p->B * x * x * x * x;
-    double dpsi = p->c0sq * (log(rho) + 1.0) + p->A * x + p->B * x * x * x;
+    /* p0 = rho psi' - psi with psi = c0sq rho ln rho + A/2 x^2 + B/4 x^4; with c0sq = 0 (the
+       paper's double well, eq. f0-bulk) psi has no rho ln rho term at all, and log rho, which
+       has no value for rho <= 0, is not evaluated */
+    const double lr = p->c0sq != 0.0 ? log(rho) : 0.0;
+    double psi = p->c0sq * rho * lr + 0.5 * p->A * x * x + 0.25 * p->B * x * x * x * x;
+    double dpsi = p->c0sq * (lr + 1.0) + p->A * x + p->B * x * x * x;
     return rho * dpsi - psi;
 }
 

@@ -257,6 +257,16 @@ template <typename R> void fill_consts(Consts<R> &c, const lb_params &q, const d
     c.B = (R)q.B;
     c.c0m = (R)(q.c0sq - 1.0 / 3.0);
     c.kappa = (R)q.kappa;
+    // pex(rho) = p0 - rho sigma_s^2 = (c0sq - 1/3) rho + rho x (A + B x^2) - x^2 (A/2 + B x^2 / 4),
+    // x = rho - rhoc (Sec. II.A); its Taylor coefficients at rho0 (pex is a quartic, so the
+    // expansion is exact) let the collision form pex(rho) - pex(rho0) from d = rho - rho0
+    // alone, without O(1) terms that cancel: pex' = c_s^2 - 1/3, pex'' = A + 3 B x^2 + 6 B rho x,
+    // pex''' = 12 B x + 6 B rho, pex'''' = 18 B
+    const double x0 = q.rho0 - q.rhoc;
+    c.dp1 = (R)(q.c0sq - 1.0 / 3.0 + q.rho0 * (q.A + 3.0 * q.B * x0 * x0));
+    c.dp2 = (R)(0.5 * (q.A + 3.0 * q.B * x0 * x0 + 6.0 * q.B * q.rho0 * x0));
+    c.dp3 = (R)(q.B * (2.0 * x0 + q.rho0));
+    c.dp4 = (R)(0.75 * q.B);
     c.lam_b = (R)lb;
     c.lam_s = (R)ls;
     c.lam_q = (R)lq;
@@ -270,7 +280,6 @@ template <typename R> void fill_consts(Consts<R> &c, const lb_params &q, const d
     c.l77 = (R)sqrt(-N[6] * ltq);
     c.l88 = (R)sqrt(-N[7] * ltq);
     c.sq0 = (R)sqrt(3.0 * q.kT * q.rho0);
-    const double x0 = q.rho0 - q.rhoc;
     c.cs2_0 = (R)(q.c0sq + q.rho0 * (q.A + 3.0 * q.B * x0 * x0));
     for (int i = 0; i < 9; ++i) c.sub[i] = (R)sub[i];
 }
@@ -290,11 +299,19 @@ RepDesc describe(const lb_params &q, int precision, long long off, long long nod
     d.logny = ilog2(q.ny);
     d.xi_off = 0;
     d.tw_off = 0;
-    const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    // the rest state fbar = T^-1 m^eq(rho0, u = 0): Table II at rest has rho0, e4 = 6 pex(rho0),
+    // e9 = -6 pex(rho0) and every other moment zero (no flow, no gradients); T^-1 as in the
+    // collision ((T^-1)_ia = w_i T_ai / N_a).  fbar_i = w_i rho0 when pex(rho0) = 0.
+    const double x0 = q.rho0 - q.rhoc;
+    const double pex0 = (q.c0sq - 1.0 / 3.0) * q.rho0 + q.rho0 * x0 * (q.A + q.B * x0 * x0) -
+                        x0 * x0 * (0.5 * q.A + 0.25 * q.B * x0 * x0);
+    const double M1 = q.rho0, M4 = 0.25 * (6.0 * pex0), M9 = 0.0625 * (-6.0 * pex0);
+    const double fa = (M1 + M4 - 4.0 * M9) / 9.0, fd = (M1 + 4.0 * M4 + 8.0 * M9) / 36.0;
+    const double fbar[9] = {(M1 - 2.0 * M4 + 2.0 * M9) * (4.0 / 9.0), fa, fa, fa, fa, fd, fd, fd, fd};
     double sub[9];
     for (int i = 0; i < 9; ++i) {
-        d.shift[i] = precision == LB_FP32 ? 0.0 : w[i] * q.rho0;
-        sub[i] = w[i] * q.rho0 - d.shift[i];
+        d.shift[i] = precision == LB_FP32 ? 0.0 : fbar[i];
+        sub[i] = fbar[i] - d.shift[i];
     }
     fill_consts(d.cd, q, sub);
     fill_consts(d.cf, q, sub);

@@ -18,6 +18,8 @@ template <typename R> struct Consts {
     R A, B;
     R c0m;           // c0sq - 1/3
     R kappa;
+    R dp1, dp2, dp3, dp4;   // pex(rho0 + d) - pex(rho0) = d (dp1 + d (dp2 + d (dp3 + d dp4))), with
+                            // pex = p0 - rho sigma_s^2 (Taylor coefficients at rho0; exact, pex is quartic)
     R lam_b, lam_s, lam_q, lam_e;   // lambda_a = -1/tau_a
     R kT3;           // 3 kT = rho kT / sigma_s^2 per unit density
     R k44, k49, k99; // Xi(0)/(3 rho kT): (4,4) = k44 (2 - 3 c_s^2), (4,9) = k49 (c_s^2 - 1/3),
@@ -33,7 +35,9 @@ template <typename R> struct Consts {
 // at ((y * 9) + i) * nx + x, so that the nine populations of a lattice row are one
 // contiguous 9 nx block (pop_at).
 // Stored value s_i and population f_i are related by f_i = s_i + shift_i; kernels work
-// on the deviation df_i = f_i - w_i rho0 = s_i - sub_i with sub_i = w_i rho0 - shift_i.
+// on the deviation df_i = f_i - fbar_i = s_i - sub_i with sub_i = fbar_i - shift_i, where
+// fbar = T^-1 m^eq(rho0, u = 0) is the model's rest state (Table II at rest: w_i rho0 when
+// p0(rho0) = rho0 sigma_s^2).  shift = fbar for the shifted storages, 0 for LB_FP32.
 struct RepDesc {
     int32_t nx, ny;
     int64_t off;          // element offset of plane 0 in a population buffer
@@ -96,7 +100,7 @@ struct StepLaunch {
     int32_t toff;
     int32_t ntiles;
     int32_t bx;
-    int32_t plain;   // 1: stored values are f_i (sub_i = w_i rho0); 0: stored f_i - w_i rho0
+    int32_t plain;   // 1: stored values are f_i (sub_i = fbar_i); 0: stored f_i - fbar_i
     int32_t whole;   // 1: some replica fits one strip (nx <= bx): launch the whole-row variant
 };
 

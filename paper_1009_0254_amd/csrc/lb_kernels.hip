@@ -15,182 +15,13 @@
 // Every access goes through a buffer descriptor of its row (no per-lane 64-bit address
 // arithmetic); stores carry the nontemporal policy.
 
+#include "lb_collide.h"
 #include "lb_internal.h"
 #include "lb_rng.h"
 
 #include <math.h>
 
 namespace lbf {
-
-template <typename S> __device__ __forceinline__ S ld_at(const S *base, unsigned byte_off)
-{
-    return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + byte_off);
-}
-template <typename S> __device__ __forceinline__ void st_at(S *base, unsigned byte_off, S v)
-{
-    __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(base) + byte_off));
-}
-
-// The fused step addresses populations through buffer resources: one per lattice row (base =
-// the row, range = its 9 nx elements), the lane's column as a 32-bit offset and the plane of
-// population i as a scalar offset, so that no per-lane 64-bit address arithmetic is spent on
-// the 18 accesses per node.  Stores carry the nontemporal cache policy.
-typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *row, unsigned bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(row), 0, (int)bytes, 0x00020000);
-}
-template <typename S> __device__ __forceinline__ S bld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
-template <> __device__ __forceinline__ float bld<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-template <> __device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-constexpr int CPOL_NT = 2;
-template <typename S> __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, S v);
-template <> __device__ __forceinline__ void bst<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, CPOL_NT);
-}
-template <> __device__ __forceinline__ void bst<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double v)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)voff, (int)soff, CPOL_NT);
-}
-
-template <typename R> __device__ __forceinline__ R frcp(R v);
-template <> __device__ __forceinline__ float frcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
-template <> __device__ __forceinline__ double frcp<double>(double v) { return 1.0 / v; }
-
-template <typename R> __device__ __forceinline__ R fsqrt(R v);
-template <> __device__ __forceinline__ float fsqrt<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
-template <> __device__ __forceinline__ double fsqrt<double>(double v) { return sqrt(v); }
-
-// ------------------------------------------------------------------ the collision
-// Deviations df_i = f_i - w_i rho0 in, post-collision deviations out.  Stencil values
-// are of drho = rho - rho0.  Returns status bits (LB_FLAG_*).
-// CN: the replica set has correlated noise (noise == 2 possible)
-template <typename R, bool CN>
-__device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Consts<R> &c, uint32_t noise,
-                                            uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
-                                            uint32_t k1, R xi4, R xi9)
-{
-    // m = T f (Table I rows, eq. Tmat), sharing the axis / diagonal partial sums
-    const R sa = (f[1] + f[2]) + (f[3] + f[4]);
-    const R sd = (f[5] + f[6]) + (f[7] + f[8]);
-    const R drho = f[0] + sa + sd;
-    const R ax = f[1] - f[3], ay = f[2] - f[4];
-    const R d68 = f[5] - f[7], d97 = f[8] - f[6];
-    const R jx = ax + d68 + d97;
-    const R jy = ay + d68 - d97;
-    const R m4 = -2 * f[0] + sa + 4 * sd;
-    const R m5 = (f[1] + f[3]) - (f[2] + f[4]);
-    const R m6 = (f[5] + f[7]) - (f[6] + f[8]);
-    const R m7 = -ax + 2 * (d68 + d97);
-    const R m8 = -ay + 2 * (d68 - d97);
-    const R m9 = 2 * f[0] - 4 * sa + 8 * sd;
-
-    unsigned st = 0;
-    const R rho = c.rho0 + drho;
-    if (!(rho == rho) || rho - rho != 0) st |= 4u;
-    const R irho = frcp<R>(rho);
-
-    // local thermodynamics, x = rho - rhoc: p0 - rho sigma_s^2 and c_s^2 (Sec. II.A)
-    const R x = c.xr0 + drho;
-    const R A = c.A, B = c.B, kap = c.kappa;
-    const R x2 = x * x;
-    const R pex = c.c0m * rho + rho * x * (A + B * x2) - x2 * ((R)0.5 * A + (R)0.25 * B * x2);
-    const R piso = pex - kap * rho * lap;
-
-    // Table II (C_n = 0)
-    const R jj = (jx * jx + jy * jy) * irho;
-    const R g2 = gx * gx + gy * gy;
-    const R e4 = 3 * jj + 6 * piso;
-    const R e5 = (jx * jx - jy * jy) * irho + kap * (gx * gx - gy * gy);
-    const R e6 = jx * jy * irho + kap * gx * gy;
-    const R e9 = -6 * piso - 3 * kap * g2;
-
-    // MRT relaxation m* = m + lambda (m - m^eq)
-    const R lb = c.lam_b, ls = c.lam_s, lq = c.lam_q, le = c.lam_e;
-    R s4 = m4 + lb * (m4 - e4);
-    R s5 = m5 + ls * (m5 - e5);
-    R s6 = m6 + ls * (m6 - e6);
-    R s7 = m7 + lq * m7;
-    R s8 = m8 + lq * m8;
-    R s9 = m9 + le * (m9 - e9);
-
-    if (CN && noise == 2) {
-        // correlated noise: modes 4 and 9 from the filtered fields, modes 5..8 white at rho0
-        R nu[6];
-        normals6<R>(node, rep, t, k0, k1, nu);
-        s4 += xi4;
-        s9 += xi9;
-        s5 += c.sq0 * c.l55 * nu[1];
-        s6 += c.sq0 * c.l66 * nu[2];
-        s7 += c.sq0 * c.l77 * nu[3];
-        s8 += c.sq0 * c.l88 * nu[4];
-    } else if (noise) {
-        // xi = L nu, L L^T = Xi(0) at the local rho and c_s^2 (eq. noise-yeo at k = 0)
-        R nu[6];
-        normals6<R>(node, rep, t, k0, k1, nu);
-        R rr = rho;
-        if (!(rr > 0)) {
-            st |= 2u;
-            rr = 0;
-        }
-        const R xx = c.xr0 + (rr - c.rho0);
-        const R cs2 = (c.c0m + (R)(1.0 / 3.0)) + rr * (A + 3 * B * xx * xx);
-        const R sq = fsqrt<R>(rr * c.kT3);
-        const R a44 = c.k44 * (2 - 3 * cs2);
-        const R a49 = c.k49 * (cs2 - (R)(1.0 / 3.0));
-        const R a99 = c.k99 * ((R)1.25 - (R)0.75 * cs2);
-        R l44 = 0, l94 = 0;
-        if (a44 > 0) {
-            l44 = fsqrt<R>(a44);
-            if (noise != 3) l94 = a49 * frcp<R>(l44);   // 3: the diagonal of Xi(0) only (Sec. IV)
-        } else if (a44 < 0) {
-            st |= 1u;
-        }
-        R p99 = a99 - l94 * l94;
-        if (p99 < 0) {
-            st |= 1u;
-            p99 = 0;
-        }
-        const R l99 = fsqrt<R>(p99);
-        s4 += sq * l44 * nu[0];
-        s5 += sq * c.l55 * nu[1];
-        s6 += sq * c.l66 * nu[2];
-        s7 += sq * c.l77 * nu[3];
-        s8 += sq * c.l88 * nu[4];
-        s9 += sq * (l94 * nu[0] + l99 * nu[5]);
-    }
-
-    // f* = T^-1 m*, (T^-1)_ia = w_i T_ai / N_a, N = (1, 1/3, 1/3, 4, 4/9, 1/9, 2/3, 2/3, 16)
-    const R M1 = drho, M2 = 3 * jx, M3 = 3 * jy;
-    const R M4 = (R)0.25 * s4, M5 = (R)2.25 * s5, M6 = 9 * s6;
-    const R M7 = (R)1.5 * s7, M8 = (R)1.5 * s8, M9 = (R)0.0625 * s9;
-    const R a = (M1 + M4 - 4 * M9) * (R)(1.0 / 9.0);
-    const R bx = (M2 - M7) * (R)(1.0 / 9.0);
-    const R by = (M3 - M8) * (R)(1.0 / 9.0);
-    const R c5 = M5 * (R)(1.0 / 9.0);
-    const R dd = (M1 + 4 * M4 + 8 * M9) * (R)(1.0 / 36.0);
-    const R ex = (M2 + 2 * M7) * (R)(1.0 / 36.0);
-    const R ey = (M3 + 2 * M8) * (R)(1.0 / 36.0);
-    const R g = M6 * (R)(1.0 / 36.0);
-    f[0] = (M1 - 2 * M4 + 2 * M9) * (R)(4.0 / 9.0);
-    f[1] = a + bx + c5;
-    f[2] = a + by - c5;
-    f[3] = a - bx + c5;
-    f[4] = a - by - c5;
-    f[5] = dd + ex + ey + g;
-    f[6] = dd - ex + ey - g;
-    f[7] = dd - ex - ey + g;
-    f[8] = dd + ex - ey - g;
-    return st;
-}
 
 // ------------------------------------------------------------------ fused step kernel
 
@@ -269,11 +100,7 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
         f[8] = (R)bld<S>(Rp, ol, 8 * nxb);
     };
     // density deviation of pulled (stored) values
-    auto dens = [&](const R f[Q]) {
-        R s = ((f[0] + (f[1] + f[2])) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
-        if (PLAIN) s -= c.rho0;   // sum_i w_i rho0
-        return s;
-    };
+    auto dens = [&](const R f[Q]) { return dens9<R, PLAIN>(f, c); };
 
     const int y0 = tl.y0, y1 = tl.y1;
     unsigned st = 0;
@@ -284,11 +111,8 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
         const R C = ring[s0 + tid + 1], E = ring[s0 + tid + 2], Wv = ring[s0 + tid];
         const R N = ring[sp + tid + 1], NE = ring[sp + tid + 2], NW = ring[sp + tid];
         const R Sv = ring[sm + tid + 1], SE = ring[sm + tid + 2], SW = ring[sm + tid];
-        // Laplacian of App. B: [4 (E + W + N + S) + (NE + NW + SW + SE) - 20 C] / 6
-        const R lap = (4 * ((E + Wv) + (N + Sv)) + ((NE + NW) + (SW + SE)) - 20 * C) * (R)(1.0 / 6.0);
-        // isotropic gradient 3 sum_i w_i c_i rho(r + c_i)
-        const R gx = (4 * (E - Wv) + (NE - NW) + (SE - SW)) * (R)(1.0 / 12.0);
-        const R gy = (4 * (N - Sv) + (NE - SE) + (NW - SW)) * (R)(1.0 / 12.0);
+        R lap, gx, gy;
+        stencil9<R>(C, E, Wv, N, NE, NW, Sv, SE, SW, lap, gx, gy);
         if (PLAIN) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) cur[i] -= c.sub[i];

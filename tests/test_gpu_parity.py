@@ -8,16 +8,18 @@ Tolerances, derived from the arithmetic of each side:
   80-bit build of the same oracle differs from the FP64 oracle by 1.2e-13 after 400 steps
   of a 1e-4 wave.  The GPU works on deviations f_i - w_i rho0 and is the more precise of
   the two (it agrees with the 80-bit build to that level).
-* FP32-shifted storage, noise-free single-phase runs: the required 1e-5, relative to the
-  fluctuation, err_a = max_r |m_a^gpu - m_a^oracle| / max_r |m_a^oracle - mean(m_a^oracle)|,
-  for rho, j_x, j_y.
-* FP32-shifted storage where FP32 cannot reach 1e-5 of the fluctuation (stated floors,
-  reproduced to within a factor of 2 by a float32 evaluation of the same update on the CPU):
-  the two-phase slab (O(1) density contrast, 500 steps: ~4e-5..7e-5), the spinodal quench
-  (exponential growth of rounding, 300 steps: ~1e-4..2e-4), a 0.02 uniform flow (j_x
-  fluctuation 1e-4 of the mean: ~1e-3..2e-3); gates are 3x the floor.
-* Noisy runs in FP32: the single-precision Box-Muller (hardware log2/sin/cos) differs
-  from the FP64 normals by <= 3e-6 per draw, which the trajectories integrate: gate 2e-3.
+* FP32-shifted storage (deviations from the rest state fbar_i = T^-1 m^eq(rho0, u = 0)),
+  noise-free runs: the required 1e-5, relative to the fluctuation,
+  err_a = max_r |m_a^gpu - m_a^oracle| / max_r |m_a^oracle - mean(m_a^oracle)|, for rho, j_x,
+  j_y: single-phase waves, the two-phase slab's density and the spinodal quench (measured
+  1e-6 to 4e-6).  One derived floor remains: a 0.02 uniform flow carries populations
+  ~0.02 w_i away from rest, whose FP32 rounding (~1e-9) is ~1e-3 of the 1e-4 wave riding on
+  j_x (measured 2.1e-3; gate 6e-3).
+* Noisy runs in FP32: the single-precision Box-Muller (hardware log2/sin/cos) differs from
+  the FP64 normals by <= 3e-6 per draw, which the trajectories integrate; every case is
+  deterministic (same seeds, same bits run after run), so each gate is about 3x the error
+  measured for its case (single phase ~2e-7 to 6e-7; the two-phase slab, whose bulk phases
+  hold O(0.5) deviations from rest, 5.7e-5).
 * Integer work (Philox) is compared bit for bit.
 """
 import os
@@ -128,9 +130,10 @@ def test_initial_moments(cfgf, precision):
     else:
         e = rel_err(mg, mo)
         say("init", cfg["init"], precision, e[:3])
-        # one FP32 rounding of each stored value: |d rho| <= 9 max|s_i| 2^-24, with
-        # |s_i| up to ~0.5 where c0sq = 0 moves the rest state away from w_i rho0
-        assert e[:3].max() < {2: 5e-6, 1: 1e-4}[precision]
+        # one FP32 rounding of each stored value: |d rho| <= 9 max|s_i| 2^-24, s_i the
+        # deviation from the rest state (FP32-shifted; measured <= 3.4e-7 of the range) or the
+        # population itself (plain FP32)
+        assert e[:3].max() < {2: 1e-6, 1: 1e-4}[precision]
 
 
 # ------------------------------------------------------------------ deterministic dynamics
@@ -143,8 +146,8 @@ DET = [
      100, 1e-5),
     ("tiny", lambda: W.wave(W.single_phase(3, 5, kT=0), 1, 1, 1e-4, 1e-4, 0), 4, 1e-5),
     ("flow", lambda: W.wave(W.single_phase(96, 64, kT=0), 2, 1, 1e-4, 0, 1e-4, U=0.02), 300, 6e-3),
-    ("slab", lambda: W.slab(64, 128, kT=0), 500, 2e-4),
-    ("spinodal", lambda: W.spinodal(128, 96, kT=0, amp=0.01, seed=2), 300, 6e-4),
+    ("slab", lambda: W.slab(64, 128, kT=0), 500, 1e-5),
+    ("spinodal", lambda: W.spinodal(128, 96, kT=0, amp=0.01, seed=2), 300, 1e-5),
 ]
 
 
@@ -179,18 +182,19 @@ def test_fp32_plain_is_reported():
 
 
 NOISY = [
-    ("single_phase_64", lambda: W.single_phase_64(), 2000),
-    ("ragged", lambda: W.single_phase(72, 50, kT=1e-5, seed=17, replica=3), 500),
-    ("tiny", lambda: W.single_phase(3, 5, kT=1e-5, seed=2), 300),
-    ("slab", lambda: W.slab(64, 128, kT=1e-6, seed=5), 500),
-    ("uncorrelated_sec5a", lambda: W.uncorrelated_sec5a(64, 64, kT=1e-7), 500),
-    ("diagonal", lambda: W.single_phase(64, 48, kT=1e-5, seed=9, c0sq=0.0, A=0.05, noise="diagonal"), 400),
+    # label, config, steps, FP32-shifted gate (all nine modes; ~3x the measured error)
+    ("single_phase_64", lambda: W.single_phase_64(), 2000, 6e-7),
+    ("ragged", lambda: W.single_phase(72, 50, kT=1e-5, seed=17, replica=3), 500, 6e-7),
+    ("tiny", lambda: W.single_phase(3, 5, kT=1e-5, seed=2), 300, 1.5e-6),
+    ("slab", lambda: W.slab(64, 128, kT=1e-6, seed=5), 500, 1.5e-4),
+    ("uncorrelated_sec5a", lambda: W.uncorrelated_sec5a(64, 64, kT=1e-7), 500, 9e-7),
+    ("diagonal", lambda: W.single_phase(64, 48, kT=1e-5, seed=9, c0sq=0.0, A=0.05, noise="diagonal"), 400, 7e-7),
 ]
 
 
-@pytest.mark.parametrize("label,cfgf,steps", NOISY, ids=[d[0] for d in NOISY])
+@pytest.mark.parametrize("label,cfgf,steps,tol32", NOISY, ids=[d[0] for d in NOISY])
 @pytest.mark.parametrize("precision", [0, 2])
-def test_noisy_parity(label, cfgf, steps, precision):
+def test_noisy_parity(label, cfgf, steps, tol32, precision):
     cfg = cfgf()
     mg, mo = run_pair(cfg, precision, steps, chunks=2)
     e = rel_err(mg, mo)
@@ -200,7 +204,7 @@ def test_noisy_parity(label, cfgf, steps, precision):
         assert ok
     else:
         say(label, "fp32s err all modes", e)
-        assert e.max() < 2e-3
+        assert e.max() < tol32
 
 
 # ------------------------------------------------------------------ ensembles, graphs, determinism
@@ -262,7 +266,7 @@ def test_plain_c_client_matches_binding_and_oracle(tmp_path, precision):
             assert ok
         else:
             say("c client replica", rep, "fp32s err", e)
-            assert (e.max() if c["kT"] > 0 else e[:3].max()) < (2e-3 if c["kT"] > 0 else 1e-5)
+            assert (e.max() if c["kT"] > 0 else e[:3].max()) < (6e-7 if c["kT"] > 0 else 1e-5)
     flags = int(np.frombuffer(raw, np.uint32, 1, off)[0])
     step = int(np.frombuffer(raw, np.int64, 1, off + 4)[0])
     assert off + 12 == len(raw)
@@ -513,10 +517,9 @@ def test_radial_snapshot_16384_plane_wave_closed_form():
     """The 16384^2 quench lattice in FP32-shifted storage: a density wave at (kx, ky) =
     (3, 4) puts |rho(+-k)|^2 = a^2 n / 4 into shell 5 and nothing elsewhere.
 
-    Floor: with c0sq = 0 the rest population holds most of the mass, so the stored
-    f_0 - w_0 rho0 is ~0.556 (FP32 ulp 6e-8); the wave has only 16384 distinct phases, over
-    which that rounding projects onto the amplitude as ~ 6e-8 / sqrt(12) sqrt(2 / 16384) 2 / a
-    = 3.8e-10 / a relative in S (one sigma): 2e-8 at a = 0.02, gated at 1e-6."""
+    Floor: the stored deviations from the rest state are of the wave's size, so their FP32
+    rounding is ~1e-7 of the wave's power, and the FP32 transforms add ~2 x 3e-7 of it
+    (measured 4.5e-8); gate 1e-6."""
     L = _L()
     nx = ny = 16384
     a = 0.02
@@ -604,7 +607,7 @@ def test_extreme_lattice_shapes_sampled(monkeypatch, shape, tile):
         else:
             e = np.abs(mg - mo).max(axis=1) / scale
             say("  fp32s err", e)
-            assert e.max() < 2e-3
+            assert e.max() < 5e-7
             assert abs(t[0] - nx * ny) / (nx * ny) < 1e-9
 
 
@@ -723,7 +726,7 @@ def test_full_size_16384_quench_growth_follows_linear_theory():
         assert abs(s1[0][sh] / want - 1) < 0.03
 
 
-FULL_GATES = {"slab_2048": 2e-4, "quench_16384": 6e-4}   # the FP32 floors of the two-phase slab and the quench
+FULL_GATES = {"slab_2048": 2e-5, "quench_16384": 8e-7}   # ~3x the measured FP32-shifted errors
 
 
 @pytest.mark.parametrize("name", ["slab_2048", "quench_16384"])
@@ -731,7 +734,8 @@ def test_full_size_two_phase_workloads_sampled(name):
     """The 2048^2 slab and the 16384^2 spinodal quench at full size, in the launch configuration
     bench.py times (FP32-shifted, autotuned tiles): two steps against the oracle at 200,000
     sampled nodes, whose moments the oracle forms there from its pre-collision populations.
-    Gates: the FP32 floors of these states (O(1) density contrast; growth after a quench)."""
+    Gates ~3x the measured errors (slab 7.3e-6: its bulk phases hold O(0.5) deviations from
+    the rest state; quench 2.7e-7)."""
     L = _L()
     cfg = getattr(W, name)()
     nx, ny = cfg["nx"], cfg["ny"]
@@ -917,7 +921,7 @@ def test_correlated_noise_parity(precision):
         assert ok
     else:
         say("correlated fp32s err", e)
-        assert e.max() < 2e-3
+        assert e.max() < 7e-7
 
 
 CN_SHAPES = [(8192, 16, 4), (16, 8192, 4), (2048, 2048, 2)]
@@ -929,9 +933,9 @@ def test_correlated_noise_parity_long_lines(precision, shape):
     """The correlated-noise filter at the bench's line lengths: 8192-point rows (one block per
     row) and columns (several adjacent columns per block for the 16 narrow ones), and a 2048^2
     lattice, on the bench's single-phase parameters with the exact Xi(k) noise, against the
-    oracle's numpy-FFT fields and FP64 step.  FP32-shifted gate 1e-4 of the fluctuation range:
-    the fields go through FP32 transforms (rounding ~ 3e-7 of their scale) on top of FP32
-    normals (3e-6 per draw)."""
+    oracle's numpy-FFT fields and FP64 step.  FP32-shifted gate 9e-7 of the fluctuation range
+    (measured 2.3e-7 to 3.0e-7): the fields go through FP32 transforms (rounding ~3e-7 of
+    their scale) on top of FP32 normals (3e-6 per draw)."""
     nx, ny, steps = shape
     cfg = dict(W.single_phase_8192(), nx=nx, ny=ny, noise="correlated", seed=17)
     mg, mo = run_pair(cfg, precision, steps, chunks=2)
@@ -942,7 +946,7 @@ def test_correlated_noise_parity_long_lines(precision, shape):
         assert ok
     else:
         say("correlated", nx, ny, "fp32s err", e)
-        assert e.max() < 1e-4
+        assert e.max() < 9e-7
 
 
 def test_correlated_and_uncorrelated_replicas_in_one_handle():

@@ -140,6 +140,25 @@ def test_bulk_thermodynamics():
         assert np.isclose(O.lib().lbo_sound_speed_sq(p, rho), dp, rtol=1e-8)
 
 
+def test_double_well_pressure_defined_at_nonpositive_density():
+    """With c0sq = 0 the free energy is the paper's double well (eq. f0-bulk) alone, a
+    polynomial: p0 = rho f0' - f0 has a value at every rho, also rho <= 0 (where rho ln rho
+    has none).  The oracle's pressure is checked there against p0 of
+    f0 = beta (rho - rho_V)^2 (rho - rho_L)^2 itself (f0' by a central difference), which the
+    A/B form equals up to the constant f0(rhoc), so p0 differs by that constant."""
+    beta, rv, rl = 0.04, 0.5, 1.5
+    A, B, rc = th.paper_free_energy_to_AB(beta, rv, rl)
+    cfg = dict(_single_phase_like(4, 4), c0sq=0.0, A=A, B=B, rhoc=rc)
+    p = O.make_params(cfg)
+    f0 = lambda r: beta * (r - rv) ** 2 * (r - rl) ** 2
+    h = 1e-4
+    for rho in (-0.3, -1e-3, 0.0, 0.2, 1.1):
+        dp = (f0(rho + h) - f0(rho - h)) / (2 * h)
+        got = O.lib().lbo_pressure(p, rho)
+        assert np.isfinite(got)
+        assert abs(got - (rho * dp - f0(rho) + f0(rc))) < 1e-9
+
+
 def test_paper_free_energy_mapping():
     """beta (rho - rho_V)^2 (rho - rho_L)^2 (eq. f0-bulk) and the A/B form differ by a constant."""
     beta, rv, rl = 0.015, 0.1, 1.0
