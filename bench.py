@@ -30,7 +30,7 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_step_fp32s_8192_counters.json")
 # the byte counters depend on the step kernel (its source, RNG and shared structs) and on the
 # tile list that lb_init builds
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1009_0254_amd", "csrc", f)
-               for f in ("lb_kernels.hip", "lb_collide.h", "lb_rng.h", "lb_internal.h", "lb_tiles.hip")]
+               for f in ("lb_kernels.hip", "lb_step2.hip", "lb_collide.h", "lb_rng.h", "lb_internal.h", "lb_tiles.hip")]
 
 
 def log(*a):

@@ -193,12 +193,19 @@ lb_status lb_set_sampling(lb_handle *h, int64_t every, int64_t first_step);
 /* Accumulated LB_FLAG_* bits since lb_init and the current time step t.  Synchronous. */
 lb_status lb_status_flags(lb_handle *h, uint32_t *flags, int64_t *step);
 
-/* The fused step's launch shape chosen by lb_init: strip width in lanes, rows per tile and
- * number of tiles.  For lattices of 2^22 nodes or more it is picked by timing candidate
- * shapes on the caller's stream; the environment variable LBF_TILE="width,rows" pins it.
- * The shape changes the schedule only: results are bitwise identical for every shape.
+/* The fused step's launch configuration chosen by lb_init: steps per launch (1: one step per
+ * launch; 2: two steps per launch, the post-collision rows of the first kept on chip for the
+ * second, so that HBM holds only every other state), and that kernel's workgroup (strip)
+ * width in lanes, rows per tile and number of workgroups.  An odd step count ends with one
+ * single-step launch.  For lattices of 2^22 nodes or more the configuration is picked by
+ * timing candidates on the caller's stream (smaller ones take two steps per launch); the
+ * environment variables LBF_TILE="width,rows" (one step per launch) and
+ * LBF_TILE2="width,rows" (two) pin a shape, LBF_STEPS_PER_LAUNCH=1 or 2 the kernel.
+ * Handles with correlated noise take one step per launch.  The configuration changes the
+ * schedule only: results are bitwise identical for every shape and either kernel.
  * Host-only; any output pointer may be NULL. */
-lb_status lb_tuning(lb_handle *h, int32_t *strip_width, int32_t *rows_per_tile, int32_t *ntiles);
+lb_status lb_tuning(lb_handle *h, int32_t *strip_width, int32_t *rows_per_tile, int32_t *ntiles,
+                    int32_t *steps_per_launch);
 
 /* The six unit normals nu_4..nu_9 (as [n][6] doubles, device pointer) that the fused
  * step draws at nodes 0..n-1 of a replica with (seed, replica) at time t, computed in

@@ -45,6 +45,8 @@ size_t elem_size(int precision) { return precision == LB_FP64 ? sizeof(double) :
 
 struct Layout {
     size_t fbuf[2], reps, tiles, tdev, flags, partials, tot, rho_tmp;
+    size_t tiles2, wgs2;       // two-step kernel: tiles and workgroup prefix
+    long long max_tiles2;
     size_t sk_tw, sk_reps, spec, acc, sk_base;   // structure factor
     int sk_G, sk_nmax;
     long long sk_ptot;
@@ -164,6 +166,14 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
         L.acc_elems += (size_t)9 * p[r].ny * (p[r].nx / 2 + 1);
     }
     L.max_tiles = max_tiles_for(p, n_rep);
+    {
+        std::vector<int> nxs(n_rep), nys(n_rep);
+        for (int r = 0; r < n_rep; ++r) {
+            nxs[r] = p[r].nx;
+            nys[r] = p[r].ny;
+        }
+        L.max_tiles2 = max_tiles2(nxs, nys);
+    }
     L.cn_nodes = L.cn_max_n = L.cn_tw_elems = 0;
     for (int r = 0; r < n_rep; ++r)
         if (p[r].noise_kind == LB_NOISE_CORRELATED && p[r].kT > 0) {
@@ -178,6 +188,8 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
     L.fbuf[1] = o; o += fb;
     L.reps = o; o += align_up(sizeof(RepDesc) * n_rep);
     L.tiles = o; o += align_up(sizeof(Tile) * L.max_tiles);
+    L.tiles2 = o; o += align_up(sizeof(Tile) * (size_t)L.max_tiles2);
+    L.wgs2 = o; o += align_up(sizeof(int32_t) * (size_t)(L.max_tiles2 + 1));
     L.tdev = o; o += ALIGN;
     L.flags = o; o += ALIGN;
     L.partials = o; o += align_up(sizeof(double) * 6 * MAX_RED_BLOCKS);
@@ -222,6 +234,12 @@ struct lb_handle {
     std::vector<Tile> tiles_h;
     int ntiles = 0, bx = 256, rows = 32;
     bool whole = false;   // some replica fits one strip of the current tile list
+    // two steps per launch (k_step2): its tile list, and whether lb_step uses it (k = 2) or
+    // k_step alone (k = 1); k_step also takes the odd step of an odd count
+    int k = 1;
+    Tile *tiles2_d = nullptr;
+    int32_t *wgs2_d = nullptr;
+    int nwg2 = 0, bx2 = 256, rows2 = 32, gmax2 = 1;
     unsigned long long *tdev = nullptr;
     unsigned *flags = nullptr;
     double *partials = nullptr, *tot = nullptr, *rho_tmp = nullptr;
@@ -362,6 +380,62 @@ hipError_t step_once(lb_handle *h, int par, int toff, hipStream_t s)
     return launch_step(h->precision, a, s);
 }
 
+lb_status set_tiles2(lb_handle *h, int bx, double rows)
+{
+    std::vector<Tile> t;
+    std::vector<int32_t> w;
+    const int gmax = make_tiles2(h->reps, bx, rows, t, w);
+    if ((long long)t.size() > h->L.max_tiles2) return LB_EINVAL;
+    if (hipMemcpyAsync(h->tiles2_d, t.data(), sizeof(Tile) * t.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->wgs2_d, w.data(), sizeof(int32_t) * w.size(), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return LB_EDEVICE;
+    h->nwg2 = (int)w.size() - 1;
+    h->bx2 = bx;
+    h->rows2 = (int)ceil(rows - 1e-9);
+    h->gmax2 = gmax;
+    return LB_OK;
+}
+
+// two steps (times t + toff, t + toff + 1) from buffer par into buffer par ^ 1
+hipError_t step_pair(lb_handle *h, int par, int toff, hipStream_t s)
+{
+    Step2Launch a;
+    a.fin = h->fbuf[par];
+    a.fout = h->fbuf[par ^ 1];
+    a.reps = h->reps_d;
+    a.tiles = h->tiles2_d;
+    a.wgs = h->wgs2_d;
+    a.tdev = h->tdev;
+    a.flags = h->flags;
+    a.toff = toff;
+    a.nwg = h->nwg2;
+    a.bx = h->bx2;
+    a.max_groups = h->gmax2;
+    a.plain = h->precision == LB_FP32 ? 1 : 0;
+    return launch_step2(h->precision, a, s);
+}
+
+// `n` steps from buffer *par on stream s, time offsets toff.. (k_step2 for pairs when k = 2);
+// *par follows the state
+hipError_t enqueue_steps(lb_handle *h, long long n, int *par, int toff, hipStream_t s)
+{
+    long long k = 0;
+    if (h->k == 2)
+        for (; k + 2 <= n; k += 2) {
+            hipError_t e = step_pair(h, *par, toff + (int)k, s);
+            if (e != hipSuccess) return e;
+            *par ^= 1;
+        }
+    for (; k < n; ++k) {
+        hipError_t e = step_once(h, *par, toff + (int)k, s);
+        if (e != hipSuccess) return e;
+        *par ^= 1;
+    }
+    return hipSuccess;
+}
+
 void drop_sample_graphs(lb_handle *h)
 {
     for (int k = 0; k < 2; ++k)
@@ -424,24 +498,51 @@ void radial_metric(int nx, int ny, int *P, int *xwide, int *nbins)
     *nbins = (int)((s + *P) / (2 * *P)) + 1;
 }
 
-// time a few steps of each candidate (strip width, rows per tile) and keep the fastest;
-// the trial steps read the current buffer and overwrite the other, so the state is
-// unchanged.  The shape changes the schedule only, never the arithmetic: results are
-// bitwise the same for every shape.
+// time a few steps of each candidate launch shape and keep the fastest: for k_step (one step
+// per launch) the strip width and rows per tile, for k_step2 (two steps) the workgroup width
+// and rows per tile; then the faster of the two kernels.  The trial steps read the current
+// buffer and overwrite the other, so the state is unchanged.  The shape changes the schedule
+// only, never the arithmetic: results are bitwise the same for every shape and either kernel.
 lb_status autotune(lb_handle *h)
 {
-    int min_nx = 1 << 30;
-    for (auto &d : h->reps) min_nx = std::min(min_nx, d.nx);
-    const char *env = getenv("LBF_TILE");
-    if (env) {
-        int bx = 0;
-        double rows = 0;
-        if (sscanf(env, "%d,%lf", &bx, &rows) == 2 && bx >= MIN_BX && bx <= 512 && bx % 64 == 0 && rows >= MIN_H)
-            return set_tiles(h, bx, rows);
+    int min_nx = 1 << 30, max_nx = 0;
+    for (auto &d : h->reps) {
+        min_nx = std::min(min_nx, d.nx);
+        max_nx = std::max(max_nx, d.nx);
     }
+    // pinned shapes: LBF_TILE="width,rows" (one step per launch), LBF_TILE2="width,rows" (two);
+    // LBF_STEPS_PER_LAUNCH=1 or 2 forces the kernel
+    auto pinned = [](const char *name, int minbx, int minh, int *bx, double *rows) {
+        const char *env = getenv(name);
+        return env && sscanf(env, "%d,%lf", bx, rows) == 2 && *bx >= minbx && *bx <= 512 && *bx % 64 == 0 &&
+               *rows >= minh;
+    };
+    int force_k = 0;
+    if (const char *e = getenv("LBF_STEPS_PER_LAUNCH")) force_k = atoi(e) == 2 ? 2 : (atoi(e) == 1 ? 1 : 0);
+    const bool cn = !h->cn_reps.empty();   // correlated noise: one step per launch only
+    int pbx = 0, pbx2 = 0;
+    double prows = 0, prows2 = 0;
+    const bool pin1 = pinned("LBF_TILE", MIN_BX, MIN_H, &pbx, &prows);
+    const bool pin2 = pinned("LBF_TILE2", STEP2_MIN_BX, STEP2_MIN_H, &pbx2, &prows2);
+    if (!force_k) force_k = pin1 && !pin2 ? 1 : (pin2 && !pin1 ? 2 : 0);
+    if (cn) force_k = 1;
+
     int bx0 = 256;
     while (bx0 > MIN_BX && bx0 / 2 >= min_nx) bx0 /= 2;
-    if (h->L.nodes < (1ll << 22)) return set_tiles(h, bx0, h->L.nodes < (1ll << 16) ? 8 : 16);
+    int bx20 = 256;
+    if (max_nx <= 128) bx20 = 128;
+    if (pin1 || h->L.nodes < (1ll << 22)) {
+        lb_status st = pin1 ? set_tiles(h, pbx, prows) : set_tiles(h, bx0, h->L.nodes < (1ll << 16) ? 8 : 16);
+        if (st != LB_OK) return st;
+    }
+    if (pin2 || h->L.nodes < (1ll << 22)) {
+        lb_status st = pin2 ? set_tiles2(h, pbx2, prows2) : set_tiles2(h, bx20, 16);
+        if (st != LB_OK) return st;
+    }
+    if ((pin1 || h->L.nodes < (1ll << 22)) && (pin2 || h->L.nodes < (1ll << 22))) {
+        h->k = force_k ? force_k : 2;
+        return LB_OK;
+    }
     struct Events {   // destroyed on every return path
         hipEvent_t a = nullptr, b = nullptr;
         ~Events()
@@ -452,71 +553,88 @@ lb_status autotune(lb_handle *h)
     } ev;
     if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) return LB_EDEVICE;
     hipEvent_t e0 = ev.a, e1 = ev.b;
-    // candidates in order of how often they win; every candidate is timed once after a
-    // warm-up, the three fastest are timed again, and among those re-timings a later one
-    // replaces an earlier one only when at least 2% faster, so that near-ties resolve the
-    // same way on every device
-    // trial length: at least ~3 ms of steps (short trials of small lattices are noisy), from
-    // the first candidate's time per step; *ms is the time per step
+    // every candidate is timed once after a warm-up, the three fastest of each kernel are timed
+    // again, and among those re-timings a later one replaces an earlier one only when at least
+    // 2% faster, so that near-ties resolve the same way on every device.  Trial length: at least
+    // ~3 ms of steps (short trials of small lattices are noisy), from the first candidate's time
+    // per step; ms is the time per step.
     int trial = 4;
-    auto time_shape = [&](int bx, int rows, float *ms) -> lb_status {
-        if (set_tiles(h, bx, rows) != LB_OK) return LB_EINVAL;
-        if (step_once(h, h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
+    auto time_shape = [&](int kk, int bx, int rows, float *ms) -> lb_status {
+        if ((kk == 1 ? set_tiles(h, bx, rows) : set_tiles2(h, bx, rows)) != LB_OK) return LB_EINVAL;
+        auto run = [&]() { return kk == 1 ? step_once(h, h->par, 0, h->stream) : step_pair(h, h->par, 0, h->stream); };
+        if (run() != hipSuccess) return LB_EDEVICE;
         (void)hipEventRecord(e0, h->stream);
-        for (int k = 0; k < trial; ++k)
-            if (step_once(h, h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
+        const int launches = kk == 1 ? trial : (trial + 1) / 2;
+        for (int k = 0; k < launches; ++k)
+            if (run() != hipSuccess) return LB_EDEVICE;
         (void)hipEventRecord(e1, h->stream);
         if (hipEventSynchronize(e1) != hipSuccess) return LB_EDEVICE;
         (void)hipEventElapsedTime(ms, e0, e1);
-        *ms /= (float)trial;
+        *ms /= (float)(launches * kk);
         return LB_OK;
     };
-    const int widths[] = {512, 256, 128, 64};
-    const int heights[] = {16, 8, 4, 32, 64};
     struct Cand {
-        int bx, rows, order;
+        int k, bx, rows, order;
         float ms;
     };
-    std::vector<Cand> cands;
     bool warmed = false;
-    for (int bx : widths) {
-        // strips much wider than the narrowest replica only add idle lanes
-        if (bx > std::max(2 * min_nx, 64)) continue;
-        for (int rows : heights) {
-            float ms = 0;
-            if (!warmed) {   // clocks ramp up during the first launches
-                for (int k = 0; k < 3; ++k) {
-                    lb_status st = time_shape(bx, rows, &ms);
-                    if (st == LB_EDEVICE) return st;
+    // candidates of one kernel in order of how often they win; returns the chosen one
+    auto tune = [&](int kk, const std::vector<int> &widths, const std::vector<int> &heights, Cand *best) -> lb_status {
+        std::vector<Cand> cands;
+        for (int bx : widths) {
+            for (int rows : heights) {
+                float ms = 0;
+                if (!warmed) {   // clocks ramp up during the first launches
+                    for (int k = 0; k < 3; ++k) {
+                        lb_status st = time_shape(kk, bx, rows, &ms);
+                        if (st == LB_EDEVICE) return st;
+                    }
+                    if (ms > 0) trial = std::max(4, std::min(64, (int)ceilf(3.0f / ms)));
+                    warmed = true;
                 }
-                if (ms > 0) trial = std::max(4, std::min(64, (int)ceilf(3.0f / ms)));
-                warmed = true;
+                lb_status st = time_shape(kk, bx, rows, &ms);
+                if (st == LB_EDEVICE) return st;
+                if (st == LB_OK) cands.push_back(Cand{kk, bx, rows, (int)cands.size(), ms});
             }
-            lb_status st = time_shape(bx, rows, &ms);
-            if (st == LB_EDEVICE) return st;
-            if (st == LB_OK) cands.push_back(Cand{bx, rows, (int)cands.size(), ms});
         }
-    }
-    if (cands.empty()) return set_tiles(h, bx0, 16);
-    std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
-    if (cands.size() > 3) cands.resize(3);
-    for (auto &c : cands) {
-        float ms = 0;
-        if (time_shape(c.bx, c.rows, &ms) == LB_EDEVICE) return LB_EDEVICE;
-        c.ms = std::min(c.ms, ms);
-    }
-    std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.order < b.order; });
-    float best = 1e30f;
-    int bbx = bx0, brows = 16;
-    for (const auto &c : cands)
-        if (c.ms < 0.98f * best) {
-            best = c.ms;
-            bbx = c.bx;
-            brows = c.rows;
+        if (cands.empty()) return LB_EINVAL;
+        std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+        if (cands.size() > 3) cands.resize(3);
+        for (auto &c : cands) {
+            float ms = 0;
+            if (time_shape(kk, c.bx, c.rows, &ms) == LB_EDEVICE) return LB_EDEVICE;
+            c.ms = std::min(c.ms, ms);
         }
+        std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.order < b.order; });
+        float bm = 1e30f;
+        for (const auto &c : cands)
+            if (c.ms < 0.98f * bm) {
+                bm = c.ms;
+                *best = c;
+            }
+        return LB_OK;
+    };
+    Cand b1{1, bx0, 16, 0, 1e30f}, b2{2, bx20, 16, 0, 1e30f};
+    if (!pin1) {
+        std::vector<int> widths;
+        for (int bx : {512, 256, 128, 64})   // strips much wider than the narrowest replica only add idle lanes
+            if (bx <= std::max(2 * min_nx, 64)) widths.push_back(bx);
+        lb_status st = tune(1, widths, {16, 8, 4, 32, 64}, &b1);
+        if (st == LB_EDEVICE) return st;
+    }
+    if (!pin2 && force_k != 1) {
+        lb_status st = tune(2, {512, 256, 384, 448}, {32, 16, 64}, &b2);
+        if (st == LB_EDEVICE) return st;
+    }
     if (hipMemcpyAsync(h->flags, &h->init_flags, sizeof(unsigned), hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return LB_EDEVICE;
-    return set_tiles(h, bbx, brows);
+    if (!pin1 && set_tiles(h, b1.bx, b1.rows) != LB_OK) return LB_EDEVICE;
+    if (!pin2 && force_k != 1 && set_tiles2(h, b2.bx, b2.rows) != LB_OK) return LB_EDEVICE;
+    if (force_k)
+        h->k = force_k;
+    else
+        h->k = pin1 ? 1 : (pin2 ? 2 : (b2.ms < 0.98f * b1.ms ? 2 : 1));
+    return LB_OK;
 }
 
 lb_status capture_graph(lb_handle *h, int par)
@@ -530,10 +648,8 @@ lb_status capture_graph(lb_handle *h, int par)
         return LB_EDEVICE;
     }
     int p = par;
-    for (int k = 0; k < GRAPH_STEPS; ++k) {
-        if (step_once(h, p, k, cs) != hipSuccess) st = LB_EDEVICE;
-        p ^= 1;
-    }
+    if (enqueue_steps(h, GRAPH_STEPS, &p, 0, cs) != hipSuccess) st = LB_EDEVICE;
+    if (p != par) st = LB_EDEVICE;   // GRAPH_STEPS is a multiple of 4: the state returns to buffer par
     if (launch_advance_time(h->tdev, GRAPH_STEPS, cs) != hipSuccess) st = LB_EDEVICE;
     if (hipStreamEndCapture(cs, &g) != hipSuccess) st = LB_EDEVICE;
     if (st == LB_OK && hipGraphInstantiate(&h->graph[par], g, nullptr, nullptr, 0) != hipSuccess) st = LB_EDEVICE;
@@ -554,10 +670,7 @@ lb_status capture_sample_graph(lb_handle *h, int par)
         return LB_EDEVICE;
     }
     int p = par;
-    for (long long k = 0; k < h->sample_every; ++k) {
-        if (step_once(h, p, (int)k, cs) != hipSuccess) st = LB_EDEVICE;
-        p ^= 1;
-    }
+    if (enqueue_steps(h, h->sample_every, &p, 0, cs) != hipSuccess) st = LB_EDEVICE;
     if (launch_advance_time(h->tdev, h->sample_every, cs) != hipSuccess) st = LB_EDEVICE;
     if (launch_sk_sample(h->precision, sk_launch(h, 0, h->n_rep, p), cs) != hipSuccess) st = LB_EDEVICE;
     if (hipStreamEndCapture(cs, &g) != hipSuccess) st = LB_EDEVICE;
@@ -580,15 +693,15 @@ lb_status run_steps(lb_handle *h, long long nsteps)
         h->t += GRAPH_STEPS;
     }
     if (left > 0) {
-        for (int k = 0; k < left; ++k) {
-            if (step_once(h, h->par, k, h->stream) != hipSuccess) return LB_EDEVICE;
-            h->par ^= 1;
-        }
+        if (enqueue_steps(h, left, &h->par, 0, h->stream) != hipSuccess) return LB_EDEVICE;
         if (launch_advance_time(h->tdev, left, h->stream) != hipSuccess) return LB_EDEVICE;
         h->t += left;
     }
     return LB_OK;
 }
+
+// buffer parity change of `n` steps as enqueue_steps takes them
+int parity_of(const lb_handle *h, long long n) { return (int)((h->k == 2 ? n / 2 + (n & 1) : n) & 1); }
 
 }  // namespace
 
@@ -642,6 +755,8 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
     h->fbuf[1] = h->ws + L.fbuf[1];
     h->reps_d = (RepDesc *)(h->ws + L.reps);
     h->tiles_d = (Tile *)(h->ws + L.tiles);
+    h->tiles2_d = (Tile *)(h->ws + L.tiles2);
+    h->wgs2_d = (int32_t *)(h->ws + L.wgs2);
     h->tdev = (unsigned long long *)(h->ws + L.tdev);
     h->flags = (unsigned *)(h->ws + L.flags);
     h->partials = (double *)(h->ws + L.partials);
@@ -704,6 +819,10 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
             delete h;
             return LB_EDEVICE;
         }
+    }
+    if ((e = set_step2_lds_limit()) != hipSuccess) {
+        delete h;
+        return LB_EDEVICE;
     }
     if ((st = autotune(h)) != LB_OK || (e = hipStreamSynchronize(h->stream)) != hipSuccess) {
         delete h;
@@ -781,7 +900,7 @@ lb_status lb_step(lb_handle *h, int64_t nsteps)
             }
             if (hipGraphLaunch(h->sgraph[h->par], h->stream) != hipSuccess) return LB_EDEVICE;
             h->t += d;
-            h->par ^= (int)(d & 1);
+            h->par ^= parity_of(h, d);
         } else {
             lb_status st = run_steps(h, d);
             if (st != LB_OK) return st;
@@ -872,12 +991,14 @@ lb_status lb_status_flags(lb_handle *h, uint32_t *flags, int64_t *step)
     return LB_OK;
 }
 
-lb_status lb_tuning(lb_handle *h, int32_t *strip_width, int32_t *rows_per_tile, int32_t *ntiles)
+lb_status lb_tuning(lb_handle *h, int32_t *strip_width, int32_t *rows_per_tile, int32_t *ntiles,
+                    int32_t *steps_per_launch)
 {
     if (!h) return LB_EINVAL;
-    if (strip_width) *strip_width = h->bx;
-    if (rows_per_tile) *rows_per_tile = h->rows;
-    if (ntiles) *ntiles = h->ntiles;
+    if (strip_width) *strip_width = h->k == 2 ? h->bx2 : h->bx;
+    if (rows_per_tile) *rows_per_tile = h->k == 2 ? h->rows2 : h->rows;
+    if (ntiles) *ntiles = h->k == 2 ? h->nwg2 : h->ntiles;
+    if (steps_per_launch) *steps_per_launch = h->k;
     return LB_OK;
 }
 

@@ -43,6 +43,12 @@ template <typename R> __device__ __forceinline__ R frcp(R v);
 template <> __device__ __forceinline__ float frcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ __forceinline__ double frcp<double>(double v) { return 1.0 / v; }
 
+// a + b rounded once, never contracted with the product that formed a (the re-shift of plain
+// FP32 storage after the back-transform must round the same way in every kernel)
+template <typename R> __device__ __forceinline__ R add_rn(R a, R b);
+template <> __device__ __forceinline__ float add_rn<float>(float a, float b) { return __fadd_rn(a, b); }
+template <> __device__ __forceinline__ double add_rn<double>(double a, double b) { return __dadd_rn(a, b); }
+
 template <typename R> __device__ __forceinline__ R fsqrt(R v);
 template <> __device__ __forceinline__ float fsqrt<float>(float v) { return __builtin_amdgcn_sqrtf(v); }
 template <> __device__ __forceinline__ double fsqrt<double>(double v) { return sqrt(v); }
@@ -62,6 +68,7 @@ template <typename R, bool PLAIN> __device__ __forceinline__ R dens9(const R f[Q
 template <typename R>
 __device__ __forceinline__ void stencil9(R C, R E, R Wv, R N, R NE, R NW, R Sv, R SE, R SW, R &lap, R &gx, R &gy)
 {
+#pragma clang fp contract(on)
     lap = (4 * ((E + Wv) + (N + Sv)) + ((NE + NW) + (SW + SE)) - 20 * C) * (R)(1.0 / 6.0);
     gx = (4 * (E - Wv) + (NE - NW) + (SE - SW)) * (R)(1.0 / 12.0);
     gy = (4 * (N - Sv) + (NE - SE) + (NW - SW)) * (R)(1.0 / 12.0);
@@ -79,6 +86,10 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
                                             uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
                                             uint32_t k1, R xi4, R xi9)
 {
+    // a product and a sum fuse into one rounding only where they are written in one
+    // expression, so that every kernel inlining the collision rounds it the same way (left
+    // to the optimiser, fusion depends on the surrounding code)
+#pragma clang fp contract(on)
     // m = T f (Table I rows, eq. Tmat), sharing the axis / diagonal partial sums
     const R sa = (f[1] + f[2]) + (f[3] + f[4]);
     const R sd = (f[5] + f[6]) + (f[7] + f[8]);

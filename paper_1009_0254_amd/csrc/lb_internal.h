@@ -107,6 +107,37 @@ struct StepLaunch {
 // the fused step's tiles for strips of bx lanes and tiles of about h rows (lb_tiles.hip)
 std::vector<Tile> make_tiles(const std::vector<RepDesc> &reps, int bx, double h);
 
+// Two steps per launch (lb_step2.hip).  A workgroup of bx lanes holds G lane groups of bx / G
+// lanes, each running one tile: workgroup w runs tiles[wgs[w] .. wgs[w + 1]), G = their
+// count.  A tile's x0 is its first output column (strips of bx / G - 4 output columns); a
+// replica whose row fits a group (nx <= bx / G) has x0 = 0 and whole-row tiles; rep < 0
+// marks an empty group.
+struct Step2Launch {
+    const void *fin;
+    void *fout;
+    const RepDesc *reps;
+    const Tile *tiles;
+    const int32_t *wgs;
+    const unsigned long long *tdev;
+    unsigned *flags;
+    int32_t toff;
+    int32_t nwg;
+    int32_t bx;
+    int32_t max_groups;   // largest G of the list (sizes the LDS)
+    int32_t plain;
+};
+constexpr int STEP2_MIN_BX = 128, STEP2_MIN_H = 8;
+// tiles and workgroup prefix of the two-step kernel for workgroups of bx lanes and tiles of
+// about h rows; returns the largest group count
+int make_tiles2(const std::vector<RepDesc> &reps, int bx, double h, std::vector<Tile> &tiles,
+                std::vector<int32_t> &wgs);
+// upper bound of the tile count of make_tiles2 for any bx >= STEP2_MIN_BX, h >= STEP2_MIN_H
+long long max_tiles2(const std::vector<int> &nx, const std::vector<int> &ny);
+hipError_t launch_step2(int precision, const Step2Launch &a, hipStream_t s);
+size_t step2_lds_bytes(int precision, int bx, int max_groups);
+// allow k_step2 the dynamic LDS of its largest configuration (512 lanes in 8 groups)
+hipError_t set_step2_lds_limit();
+
 // launchers (lb_kernels.hip); all return hipSuccess or the launch error
 hipError_t launch_step(int precision, const StepLaunch &a, hipStream_t s);
 hipError_t launch_advance_time(unsigned long long *tdev, long long by, hipStream_t s);

@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
         const auto W = row_rsrc(Qo + (unsigned long long)(unsigned)y * pitch, rowb);
         if (store) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) bst<S>(W, c0, i * nxb, (S)(PLAIN ? cur[i] + c.sub[i] : cur[i]));
+            for (int i = 0; i < Q; ++i) bst<S>(W, c0, i * nxb, (S)(PLAIN ? add_rn<R>(cur[i], c.sub[i]) : cur[i]));
         }
     };
 

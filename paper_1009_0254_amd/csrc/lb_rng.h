@@ -53,6 +53,7 @@ template <typename R> struct Gauss;
 template <> struct Gauss<float> {
     static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, float &a, float &b)
     {
+#pragma clang fp contract(on)
         const float ue = ((float)be + 0.5f) * 0x1p-21f;
         const float uo = ((float)bo + 0.5f) * 0x1p-21f;
         // -2 ln u = -2 ln(2) log2(u); v_log_f32 is log2, v_sin/v_cos take revolutions
@@ -65,6 +66,7 @@ template <> struct Gauss<float> {
 template <> struct Gauss<double> {
     static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, double &a, double &b)
     {
+#pragma clang fp contract(on)
         const double ue = ((double)be + 0.5) * 0x1p-21;
         const double uo = ((double)bo + 0.5) * 0x1p-21;
         const double r = sqrt(-2.0 * log(ue));

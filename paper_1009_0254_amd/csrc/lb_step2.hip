@@ -1,0 +1,344 @@
+// Two time steps of the fluctuating D2Q9 update per launch (temporal blocking).
+//
+// The update of one step (eq. gen-lbe-m with the noise of eq. noise-yeo at k = 0) is the one
+// of k_step: pull f_i(r, t) = f*_i(r - c_i, t - 1), density, 9-point stencils (App. B
+// Laplacian, isotropic gradient), collision (lb_collide.h).  k_step2 applies it twice, the
+// second time to the post-collision rows of the first while they are still on chip, so that
+// HBM sees one read of f*(t - 1) and one write of f*(t + 1) per two steps: half the traffic
+// of two launches of k_step.  Every node of every step goes through the same arithmetic as in
+// k_step (the same collision, density and stencil expressions, the rounding to the storage
+// type between the steps included), so the results are bitwise those of two k_step launches.
+//
+// A workgroup holds G lane groups of BG = blockDim.x / G lanes (BG a multiple of 64, so a
+// wave is in one group).  Each group runs one tile: rows [y0, y1) of a replica, and either
+//   - the whole row (nx <= BG; lane l is column l, neighbours wrap inside the group), or
+//   - a strip (nx > BG) whose lane l is column x0 - 2 + l: the first step computes all BG
+//     columns, the second step only the inner BG - 4 (it needs the first step's results one
+//     column further out, and those need densities one further), so strips overlap by four
+//     columns and store columns [x0, x0 + BG - 4).
+// The group marches down the rows.  Stage 1 (step t) collides row r; its output row goes to
+// LDS (populations 1, 3, 5, 6, 7, 8, which the pull of step t + 1 takes from the next
+// column) and registers (0, 2, 4, which stay in the column).  Stage 2 (step t + 1) pulls row
+// r - 2 from those (the pull of row y needs output rows y - 1, y, y + 1), forms its density,
+// and collides row r - 3 (whose stencil needs the density of row r - 2).  So a tile of output
+// rows [y0, y1) runs stage 1 on rows [y0 - 2, y1 + 2) and reads rows [y0 - 4, y1 + 4) of
+// f*(t - 1).  Two workgroup barriers per row: after the stage-1 density and the stage-2
+// density of a row are in LDS (A), and after the stage-1 output row is (B).
+//
+// LDS per group, each array padded by one slot on both sides of the BG lanes (W = BG + 2):
+//   ring1[3][W]    rho(t) - rho0 of three consecutive rows (strip halo columns in slots 0, W-1)
+//   ring2[3][W]    rho(t+1) - rho0
+//   F78[2][W]      populations 7, 8 of the last stage-1 row         (stored type S)
+//   F13[3][2][W]   populations 1, 3 of the last three stage-1 rows
+//   F56[3][2][W]   populations 5, 6 of the last three stage-1 rows
+// The loop is unrolled by three so that every ring index is a compile-time constant.
+
+#include "lb_collide.h"
+#include "lb_internal.h"
+#include "lb_rng.h"
+
+#include <type_traits>
+
+namespace lbf {
+
+template <typename S, typename R> constexpr unsigned step2_group_bytes(unsigned W)
+{
+    return W * (6 * (unsigned)sizeof(R) + 14 * (unsigned)sizeof(S));
+}
+
+template <typename S, typename R, bool PLAIN>
+__global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__restrict__ fout,
+                                               const RepDesc *__restrict__ reps, const Tile *__restrict__ tiles,
+                                               const int32_t *__restrict__ wgs,
+                                               const unsigned long long *__restrict__ tdev,
+                                               unsigned *__restrict__ flags, int toff)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const unsigned BX = blockDim.x;
+    const int gbeg = wgs[blockIdx.x];
+    const unsigned G = (unsigned)(wgs[blockIdx.x + 1] - gbeg);
+    const unsigned BG = BX / G;
+    const unsigned tid = threadIdx.x;
+    const unsigned grp = __builtin_amdgcn_readfirstlane(tid / BG);   // uniform per wave
+    const unsigned l = tid - grp * BG;
+    const unsigned W = BG + 2;
+
+    // rows the workgroup marches over: the tallest of its tiles (every group keeps the barriers)
+    int hmax = 0;
+    for (unsigned g = 0; g < G; ++g) {
+        const Tile q = tiles[gbeg + g];
+        if (q.rep >= 0) hmax = max(hmax, q.y1 - q.y0);
+    }
+    const Tile tl = tiles[gbeg + grp];
+    const bool gidle = tl.rep < 0;
+    const RepDesc &d = reps[gidle ? 0 : tl.rep];
+    const Consts<R> &c = consts<R>(d);
+    const unsigned nx = (unsigned)d.nx, ny = (unsigned)d.ny;
+    const unsigned long long pitch = 9ull * nx;
+    constexpr unsigned ES = sizeof(S);
+    const unsigned rowb = 9u * nx * ES, nxb = nx * ES;
+    const unsigned long long t = tdev[0] + (unsigned long long)toff;
+    const S *__restrict__ P = fin + d.off;
+    S *__restrict__ Qo = fout + d.off;
+
+    unsigned char *gb = smem_raw + grp * step2_group_bytes<S, R>(W);
+    R *ring1 = reinterpret_cast<R *>(gb);
+    R *ring2 = ring1 + 3 * W;
+    S *F78 = reinterpret_cast<S *>(ring2 + 3 * W);
+    S *F13 = F78 + 2 * W;
+    S *F56 = F13 + 6 * W;
+
+    // columns.  whole: lane l is column l (lanes past the row duplicate column l mod nx and
+    // never store; whole waves past it only keep the barriers).  strip: lane l is column
+    // x0 - 2 + l (mod nx).
+    const bool whole = nx <= BG;
+    const bool idle = gidle || (whole && (tid - grp * BG) / 64 * 64 >= nx);   // uniform per wave
+    unsigned xw;
+    if (whole) {
+        xw = l < nx ? l : l % nx;
+    } else {
+        const int xs = tl.x0 - 2 + (int)l;
+        xw = (unsigned)(xs < 0 ? xs + (int)nx : (xs >= (int)nx ? xs - (int)nx : xs));
+    }
+    constexpr unsigned ESZ = sizeof(S);
+    const unsigned cm = (xw == 0 ? nx - 1 : xw - 1) * ESZ;
+    const unsigned c0 = xw * ESZ;
+    const unsigned cp = (xw == nx - 1 ? 0 : xw + 1) * ESZ;
+    // LDS slots of the lane and of its two neighbours (row arrays of W slots, lane l at l + 1)
+    const unsigned i0 = l + 1;
+    const unsigned im = whole ? (xw == 0 ? nx - 1 : xw - 1) + 1 : l;
+    const unsigned ip = whole ? (xw == nx - 1 ? 0 : xw + 1) + 1 : l + 2;
+    // ring1 halo densities: whole rows copy the wrap-around neighbours from their own
+    // columns (the lane of column nx - 1 also writes slot 0, the lane of column 0 slot nx + 1);
+    // strips pull the two columns beyond their ends with lanes 0 and 1
+    const bool xtra = whole && (l == 0 || l == nx - 1);
+    const unsigned xslot = l == 0 ? nx + 1 : 0;
+    const bool halo = !whole && l < 2;
+    unsigned hxw = 0;
+    if (!whole) {
+        const int hx = l == 0 ? tl.x0 - 3 : tl.x0 - 2 + (int)BG;
+        hxw = (unsigned)(((hx % (int)nx) + (int)nx) % (int)nx);
+    }
+    const unsigned hcm = (hxw == 0 ? nx - 1 : hxw - 1) * ESZ;
+    const unsigned hc0 = hxw * ESZ;
+    const unsigned hcp = (hxw == nx - 1 ? 0 : hxw + 1) * ESZ;
+    const unsigned hslot = l == 0 ? 0 : BG + 1;
+    // stage 2 stores lanes whose column is inside the tile's output columns
+    const bool store2 = whole ? l < nx : (l >= 2 && l < BG - 2 && (unsigned)(tl.x0 - 2 + (int)l) < nx);
+
+    auto wrapy = [ny](int v) -> unsigned {
+        const int m = v % (int)ny;
+        return (unsigned)(m < 0 ? m + (int)ny : m);
+    };
+    struct Rows {
+        __amdgpu_buffer_rsrc_t m, z, p;
+    };
+    auto rows_of = [&](int yy) -> Rows {
+        return Rows{row_rsrc(P + (unsigned long long)wrapy(yy - 1) * pitch, rowb),
+                    row_rsrc(P + (unsigned long long)wrapy(yy) * pitch, rowb),
+                    row_rsrc(P + (unsigned long long)wrapy(yy + 1) * pitch, rowb)};
+    };
+    auto pull = [&](const Rows &rr, unsigned o0, unsigned ol, unsigned orr, R f[Q]) {
+        f[0] = (R)bld<S>(rr.z, o0, 0);
+        f[1] = (R)bld<S>(rr.z, ol, nxb);
+        f[2] = (R)bld<S>(rr.m, o0, 2 * nxb);
+        f[3] = (R)bld<S>(rr.z, orr, 3 * nxb);
+        f[4] = (R)bld<S>(rr.p, o0, 4 * nxb);
+        f[5] = (R)bld<S>(rr.m, ol, 5 * nxb);
+        f[6] = (R)bld<S>(rr.m, orr, 6 * nxb);
+        f[7] = (R)bld<S>(rr.p, orr, 7 * nxb);
+        f[8] = (R)bld<S>(rr.p, ol, 8 * nxb);
+    };
+    auto dens = [&](const R f[Q]) { return dens9<R, PLAIN>(f, c); };
+
+    const int y0 = tl.y0, y1 = tl.y1;
+    const int ys0 = y0 - 2, ys1 = y1 + 2;   // stage-1 rows [ys0, ys1)
+    const int nit = hmax + 5;               // iterations r = ys0 + k, k < nit (uniform)
+    unsigned st = 0;
+
+    // stage-1 registers: pulled rows r (cur), r + 1 (nxt), r + 2 (in flight)
+    R fa[Q], fb[Q], fc[Q], hv[Q];
+    // stage-1 output populations that stay in the column, rings of three rows (slot = row's k mod 3)
+    S F0r[3], F2r[3], F4r[3];
+    // stage-2 pulled rows: the one pulled in this iteration (gn) and the previous one (go)
+    R gn[Q], go[Q];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F0r[i] = F2r[i] = F4r[i] = (S)0;
+
+    // prologue (as k_step): densities of rows ys0 - 1 and ys0, populations of row ys0, loads of
+    // row ys0 + 1 in flight
+    auto put1 = [&](unsigned slot, R v) {
+        ring1[slot * W + i0] = v;
+        if (xtra) ring1[slot * W + xslot] = v;
+    };
+    {
+        const Rows ra = rows_of(ys0 - 1), rb = rows_of(ys0);
+        if (!idle) {
+            pull(ra, c0, cm, cp, fb);
+            put1(0, dens(fb));
+            if (halo) {
+                pull(ra, hc0, hcm, hcp, hv);
+                ring1[0 * W + hslot] = dens(hv);
+                pull(rb, hc0, hcm, hcp, hv);
+                ring1[1 * W + hslot] = dens(hv);
+            }
+            pull(rb, c0, cm, cp, fa);
+            put1(1, dens(fa));
+        }
+        const Rows rc = rows_of(ys0 + 1);
+        if (!idle) {
+            pull(rc, c0, cm, cp, fb);
+            if (halo) pull(rc, hc0, hcm, hcp, hv);
+        }
+    }
+
+    // one iteration; K = k mod 3 fixes every ring slot (all modulo 3, with r = ys0 + k):
+    //   ring1 (rho(t)):       row rho at slot (rho - ys0 + 1), so row r + j at K + 1 + j
+    //   ring2 (rho(t+1)):     row rho at slot (rho - ys0), so row r - 2 + j at K + 1 + j
+    //   F13, F56, F0r, F2r, F4r (stage-1 output): row rho at slot (rho - ys0), row r at K
+    auto iter = [&](auto Kc, int k, R cur[Q], R nxt[Q], R nn[Q]) {
+        constexpr unsigned K = decltype(Kc)::value;
+        const int r = ys0 + k;
+        const bool s1 = !idle && r < ys1;                               // stage 1 on row r
+        const bool p2 = !idle && r >= ys0 + 3 && r <= ys1;              // stage-2 pull of row r - 2
+        const bool c2 = !idle && r >= ys0 + 5 && r <= ys1;              // stage-2 collision of row r - 3
+        // ---- phase 1: density of row r + 1 into ring1, loads of row r + 2, stage-2 pull
+        if (s1) {
+            put1((K + 2) % 3, dens(nxt));
+            if (halo) ring1[((K + 2) % 3) * W + hslot] = dens(hv);
+        }
+        if (k + 1 < nit && r + 2 <= ys1) {
+            const Rows rn = rows_of(r + 2);
+            if (s1) {
+                pull(rn, c0, cm, cp, nn);
+                if (halo) pull(rn, hc0, hcm, hcp, hv);
+            }
+        }
+        if (p2) {
+            // row y = r - 2: populations 5, 6 from output row y - 1 = r - 3 (slot K), 1, 3 from
+            // row y (slot K + 1), 7, 8 from row y + 1 = r - 1 (F78), 0 / 2 / 4 from the column's
+            // own rows y (slot K + 1), y - 1 (slot K), y + 1 (slot K + 2)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) go[i] = gn[i];
+            const S *f13 = F13 + ((K + 1) % 3) * 2 * W;
+            const S *f56 = F56 + ((K + 0) % 3) * 2 * W;
+            gn[0] = (R)F0r[(K + 1) % 3];
+            gn[1] = (R)f13[im];
+            gn[2] = (R)F2r[(K + 0) % 3];
+            gn[3] = (R)f13[W + ip];
+            gn[4] = (R)F4r[(K + 2) % 3];
+            gn[5] = (R)f56[im];
+            gn[6] = (R)f56[W + ip];
+            gn[7] = (R)F78[ip];
+            gn[8] = (R)F78[W + im];
+            ring2[((K + 1) % 3) * W + i0] = dens(gn);
+        }
+        __syncthreads();
+        // ---- phase 2: stage-1 collision of row r, its output to LDS / registers; stage-2
+        // collision of row r - 3
+        if (s1) {
+            const unsigned s0 = ((K + 1) % 3) * W, sm = (K % 3) * W, sp = ((K + 2) % 3) * W;
+            R lap, gx, gy;
+            stencil9<R>(ring1[s0 + i0], ring1[s0 + i0 + 1], ring1[s0 + i0 - 1], ring1[sp + i0], ring1[sp + i0 + 1],
+                        ring1[sp + i0 - 1], ring1[sm + i0], ring1[sm + i0 + 1], ring1[sm + i0 - 1], lap, gx, gy);
+            if (PLAIN) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) cur[i] -= c.sub[i];
+            }
+            const unsigned yr = wrapy(r);
+            st |= collide<R, false>(cur, lap, gx, gy, c, d.noise, yr * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi,
+                                    (R)0, (R)0);
+            S o[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) o[i] = (S)(PLAIN ? add_rn<R>(cur[i], c.sub[i]) : cur[i]);
+            F0r[K] = o[0];
+            F2r[K] = o[2];
+            F4r[K] = o[4];
+            S *f13 = F13 + K * 2 * W;
+            S *f56 = F56 + K * 2 * W;
+            f13[i0] = o[1];
+            f13[W + i0] = o[3];
+            f56[i0] = o[5];
+            f56[W + i0] = o[6];
+            F78[i0] = o[7];
+            F78[W + i0] = o[8];
+        }
+        // keep the two collisions apart: interleaved, their temporaries would be live together
+        __builtin_amdgcn_sched_barrier(0);
+        if (c2) {
+            // densities of rows r - 4, r - 3, r - 2 at ring2 slots K + 2, K, K + 1
+            const unsigned s0 = K * W, sm = ((K + 2) % 3) * W, sp = ((K + 1) % 3) * W;
+            R lap, gx, gy;
+            stencil9<R>(ring2[s0 + i0], ring2[s0 + ip], ring2[s0 + im], ring2[sp + i0], ring2[sp + ip],
+                        ring2[sp + im], ring2[sm + i0], ring2[sm + ip], ring2[sm + im], lap, gx, gy);
+            if (PLAIN) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) go[i] -= c.sub[i];
+            }
+            const unsigned y = (unsigned)(r - 3);   // inside [y0, y1): no wrap
+            const unsigned s2 = collide<R, false>(go, lap, gx, gy, c, d.noise, y * nx + xw, d.rep_id, t + 1,
+                                                  d.seed_lo, d.seed_hi, (R)0, (R)0);
+            const auto Wr = row_rsrc(Qo + (unsigned long long)y * pitch, rowb);
+            if (store2) {
+                st |= s2;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) bst<S>(Wr, c0, i * nxb, (S)(PLAIN ? add_rn<R>(go[i], c.sub[i]) : go[i]));
+            }
+        }
+        __syncthreads();
+    };
+    // the slots of K are those of k mod 3 relative to the prologue (ring1 rows ys0 - 1, ys0 at
+    // slots 0, 1 = (K + 1 + j) % 3 for K = 0, j = -1, 0)
+    using K0 = std::integral_constant<unsigned, 0>;
+    using K1 = std::integral_constant<unsigned, 1>;
+    using K2 = std::integral_constant<unsigned, 2>;
+    for (int k = 0; k < nit; k += 3) {
+        iter(K0{}, k, fa, fb, fc);
+        if (k + 1 < nit) iter(K1{}, k + 1, fb, fc, fa);
+        if (k + 2 < nit) iter(K2{}, k + 2, fc, fa, fb);
+    }
+    // stage-1 flags of rows outside the output rows are those of the neighbouring tiles' own
+    // output rows (or, for whole rows, of the same nodes): report only stored results
+    if (st && store2) atomicOr(flags, st);
+}
+
+template <typename S, typename R, bool PLAIN> static void launch_step2_t(const Step2Launch &a, hipStream_t s)
+{
+    const size_t lds = (size_t)a.max_groups * step2_group_bytes<S, R>((unsigned)(a.bx / a.max_groups + 2));
+    hipLaunchKernelGGL((k_step2<S, R, PLAIN>), dim3(a.nwg), dim3(a.bx), lds, s, (const S *)a.fin, (S *)a.fout, a.reps,
+                       a.tiles, a.wgs, a.tdev, a.flags, a.toff);
+}
+
+hipError_t set_step2_lds_limit()
+{
+    const int fp32 = (int)(8 * step2_group_bytes<float, float>(512 / 8 + 2));
+    const int fp64 = (int)(8 * step2_group_bytes<double, double>(512 / 8 + 2));
+    hipError_t e = hipFuncSetAttribute((const void *)k_step2<double, double, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, fp64);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_step2<float, float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                fp32);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_step2<float, float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                fp32);
+    return e;
+}
+
+size_t step2_lds_bytes(int precision, int bx, int max_groups)
+{
+    const unsigned W = (unsigned)(bx / max_groups + 2);
+    return (size_t)max_groups * (precision == 0 ? step2_group_bytes<double, double>(W) : step2_group_bytes<float, float>(W));
+}
+
+hipError_t launch_step2(int precision, const Step2Launch &a, hipStream_t s)
+{
+    if (precision == 0)
+        launch_step2_t<double, double, false>(a, s);
+    else if (a.plain)
+        launch_step2_t<float, float, true>(a, s);
+    else
+        launch_step2_t<float, float, false>(a, s);
+    return hipGetLastError();
+}
+
+}  // namespace lbf

@@ -108,4 +108,89 @@ std::vector<Tile> make_tiles(const std::vector<RepDesc> &reps, int bx, double h)
     return out;
 }
 
+// Lane groups per workgroup for a replica of width nx in workgroups of bx lanes: the most
+// groups (at most 8) of a width that is a multiple of 64 and holds the whole row; 1 (a strip)
+// when the row is wider than bx.
+static int groups_for(int nx, int bx)
+{
+    for (int G = 8; G > 1; --G)
+        if (bx % (64 * G) == 0 && bx / G >= nx) return G;
+    return 1;
+}
+
+// The two-step kernel's work list.  Strips of a replica wider than a workgroup overlap by four
+// columns (each stores bx - 4); whole rows of narrower replicas are packed G to a workgroup,
+// G vertically adjacent tiles of one replica (they share boundary rows), with empty groups
+// (rep = -1) after the last tile of a replica.  XCD placement as in make_tiles: a replica
+// with at least 8 strips is split into 8 contiguous strip groups, one per XCD queue; smaller
+// ones go whole to the least-loaded queue; the queues are interleaved (workgroup i runs on
+// XCD i mod 8).
+int make_tiles2(const std::vector<RepDesc> &reps, int bx, double h, std::vector<Tile> &tiles,
+                std::vector<int32_t> &wgs)
+{
+    constexpr int X = 8;
+    typedef std::vector<Tile> WG;
+    std::vector<std::vector<WG>> q(X);
+    std::vector<long long> load(X, 0);
+    std::vector<int> order(reps.size());
+    for (size_t r = 0; r < reps.size(); ++r) order[r] = (int)r;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (long long)reps[a].nx * reps[a].ny > (long long)reps[b].nx * reps[b].ny;
+    });
+    int gmax = 1;
+    for (int r : order) {
+        const RepDesc &d = reps[r];
+        const Bands B(d.ny, h);
+        if (d.nx > bx) {
+            const int w2 = bx - 4;
+            const int ns = (d.nx + w2 - 1) / w2;
+            const int parts = ns >= X ? X : 1;
+            for (int k = 0; k < parts; ++k) {
+                const int qk = parts == X ? k : (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                const int s0 = k * ns / parts, s1 = (k + 1) * ns / parts;
+                for (int j = 0; j < B.nt; ++j)
+                    for (int sidx = s0; sidx < s1; ++sidx) {
+                        q[qk].push_back(WG{Tile{(int32_t)r, sidx * w2, B.y0(j), B.y1(j)}});
+                        load[qk] += (long long)bx * (B.y1(j) - B.y0(j));
+                    }
+            }
+        } else {
+            const int G = groups_for(d.nx, bx);
+            gmax = std::max(gmax, G);
+            const int qk = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            for (int j0 = 0; j0 < B.nt; j0 += G) {
+                WG w;
+                for (int g = 0; g < G; ++g)
+                    w.push_back(j0 + g < B.nt ? Tile{(int32_t)r, 0, B.y0(j0 + g), B.y1(j0 + g)} : Tile{-1, 0, 0, 0});
+                q[qk].push_back(w);
+                load[qk] += (long long)bx * (B.y1(j0) - B.y0(j0));
+            }
+        }
+    }
+    tiles.clear();
+    wgs.clear();
+    size_t common = q[0].size();
+    for (int k = 1; k < X; ++k) common = std::min(common, q[k].size());
+    auto emit = [&](const WG &w) {
+        wgs.push_back((int32_t)tiles.size());
+        tiles.insert(tiles.end(), w.begin(), w.end());
+    };
+    for (size_t j = 0; j < common; ++j)
+        for (int k = 0; k < X; ++k) emit(q[k][j]);
+    for (int k = 0; k < X; ++k)
+        for (size_t j = common; j < q[k].size(); ++j) emit(q[k][j]);
+    wgs.push_back((int32_t)tiles.size());
+    return gmax;
+}
+
+long long max_tiles2(const std::vector<int> &nx, const std::vector<int> &ny)
+{
+    long long t = 0;
+    for (size_t r = 0; r < nx.size(); ++r) {
+        const long long strips = nx[r] > STEP2_MIN_BX ? (nx[r] + STEP2_MIN_BX - 5) / (STEP2_MIN_BX - 4) : 1;
+        t += strips * ((ny[r] + STEP2_MIN_H - 1) / STEP2_MIN_H) + 8;
+    }
+    return t;
+}
+
 }  // namespace lbf

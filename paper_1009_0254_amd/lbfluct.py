@@ -73,7 +73,7 @@ def lib() -> ctypes.CDLL:
         L.lb_noise_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64,
                                        ctypes.c_int32, vp, vp]
         L.lb_philox.argtypes = [ctypes.c_uint32] * 5 + [ctypes.c_int64, vp, vp]
-        L.lb_tuning.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 3
+        L.lb_tuning.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 4
         L.lb_free.argtypes = [vp]
         L.lb_free.restype = None
         L.lb_strerror.argtypes = [ctypes.c_int32]
@@ -201,7 +201,8 @@ class Lattice:
         return f.value, t.value
 
     def lb_tuning(self):
-        v = [ctypes.c_int32(0) for _ in range(3)]
+        """(strip width, rows per tile, workgroups, steps per launch)"""
+        v = [ctypes.c_int32(0) for _ in range(4)]
         _check("lb_tuning", lib().lb_tuning(self._h, *[ctypes.byref(x) for x in v]))
         return tuple(x.value for x in v)
 

@@ -303,6 +303,56 @@ def test_tile_shape_does_not_change_bits(monkeypatch):
         assert np.array_equal(m, res[0])
 
 
+TWO_STEP_CASES = [
+    ("strips", [W.single_phase(1100, 70, kT=1e-5, seed=8)]),
+    ("mixed", [W.single_phase(128, 40, kT=1e-5, seed=21, replica=0),
+               W.single_phase(64, 24, kT=2e-5, seed=22, replica=1),
+               W.single_phase(100, 36, kT=1e-5, seed=23, replica=2),
+               W.single_phase(600, 18, kT=1e-5, seed=24, replica=3),
+               W.wave(W.single_phase(3, 9, kT=0), 1, 1, 1e-4, 0, 1e-4),
+               W.slab(40, 64, kT=1e-6, seed=25, replica=5)]),
+    ("tiny", [W.single_phase(3, 5, kT=1e-5, seed=2)]),
+]
+
+
+@pytest.mark.parametrize("label,cfgs", TWO_STEP_CASES, ids=[c[0] for c in TWO_STEP_CASES])
+@pytest.mark.parametrize("precision", [2, 0, 1])
+def test_two_steps_per_launch_bitwise(monkeypatch, label, cfgs, precision):
+    """The two-steps-per-launch kernel gives the bits of the one-step kernel, for every
+    workgroup width and tile height: overlapping strips (a ragged last strip, tile heights
+    that do not divide ny), whole rows packed 2 to 8 per workgroup with empty groups, a
+    3 x 5 lattice whose tile wraps its rows twice, all three storages; odd step counts end
+    with a one-step launch, 64 steps replay the captured graph.  Flags and time agree too."""
+    L = _L()
+    def run(env):
+        for k in ("LBF_TILE", "LBF_TILE2", "LBF_STEPS_PER_LAUNCH"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        lat = L.Lattice(cfgs, precision=precision)
+        tune = lat.lb_tuning()
+        out = []
+        for n in (37, 64):
+            lat.step(n)
+            out.append(([lat.moments(r) for r in range(len(cfgs))], lat.lb_status_flags()))
+        lat.close()
+        return tune, out
+    t1, ref = run({"LBF_TILE": "256,16", "LBF_STEPS_PER_LAUNCH": "1"})
+    assert t1[3] == 1
+    for tile in ("512,32", "256,16", "128,8", "384,64", "448,24", "320,13"):
+        say("two-step", label, "precision", precision, "tile", tile)
+        t2, got = run({"LBF_TILE": "256,16", "LBF_TILE2": tile, "LBF_STEPS_PER_LAUNCH": "2"})
+        assert t2[3] == 2 and t2[0] == int(tile.split(",")[0])
+        for (mg, fg), (mr, fr) in zip(got, ref):
+            assert fg == fr
+            for r in range(len(cfgs)):
+                assert np.array_equal(mg[r], mr[r]), (tile, r)
+    if precision == 0:
+        o = O.Oracle(cfgs[0])
+        o.step(101)
+        assert abs_ok(ref[1][0][0], o.moments())[0]
+
+
 @pytest.mark.parametrize("precision", [2, 0])
 def test_ensemble_tile_shapes_do_not_change_bits(monkeypatch, precision):
     """Replicas narrower than the strip (whole-row strips, idle waves past the row) and wider
