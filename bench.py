@@ -75,7 +75,7 @@ def traffic_from_counters(workload, tile=None):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
     scaled by the same counters' reading of a plain copy of known size; null when the
     kernel source has changed since the counters were taken, or when this run's workload or
-    tile shape (strip width, rows) is not one profiled."""
+    launch configuration (strip width, rows, steps per launch) is not one profiled."""
     try:
         c = json.load(open(COUNTERS))
     except (OSError, ValueError):
@@ -84,8 +84,16 @@ def traffic_from_counters(workload, tile=None):
         return None
     if tile is None:
         return c.get("hbm_bytes_per_launch")
-    t = c.get("per_tile", {}).get("%d,%d" % tile)
+    t = c.get("per_tile", {}).get("%d,%d,%d" % tile)
     return t.get("hbm_bytes_per_launch") if t else None
+
+
+def kernel_name(tune, reps):
+    """The step kernel that ran: two steps per launch (k_step2), or one (k_step, whose
+    whole-row-strip variant runs when some replica fits one strip)."""
+    if tune[3] == 2:
+        return "k_step2<float,float,false>"
+    return "k_step<float,float,false,false,%s>" % ("true" if any(r["nx"] <= tune[0] for r in reps) else "false")
 
 
 def cpu_baseline(torch, L, cfg, steps):
@@ -149,6 +157,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-sk", action="store_true", help="skip timing one S(k) sample")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip timing the 336-replica ensemble beside a single-lattice workload")
     ap.add_argument("--no-correlated", action="store_true",
                     help="skip timing the same lattice with spatially correlated noise")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -194,17 +204,40 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "nodes": n, "replicas": len(reps),
                    "nx": reps[0]["nx"], "ny": reps[0]["ny"], "precision": prec, "parallelism": "single GPU",
-                   "tile": {"strip_width": tune[0], "rows": tune[1], "tiles": tune[2]}},
+                   "tile": {"strip_width": tune[0], "rows": tune[1], "workgroups": tune[2],
+                            "steps_per_launch": tune[3]}},
+        # achieved: the algorithmic bytes of the lattice updates (one read and one write of the
+        # nine populations per node and step) over the measured time per step; the two-step
+        # kernel moves about half of them through HBM (see traffic)
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_counters(args.workload, (tune[0], tune[1])),
-                     # the whole-row-strip variant runs when some replica fits one strip
-                     "kernel": "k_step<float,float,false,false,%s>" % (
-                         "true" if any(r["nx"] <= tune[0] for r in reps) else "false"),
+                     "traffic": traffic_from_counters(args.workload, (tune[0], tune[1], tune[3])),
+                     "kernel": kernel_name(tune, reps),
                      "tile": "%d,%d" % (tune[0], tune[1]),
-                     "bytes_per_update": BYTES_PER_UPDATE[prec]},
+                     "steps_per_launch": tune[3],
+                     "bytes_per_update": BYTES_PER_UPDATE[prec],
+                     "algorithmic_bytes_per_launch": BYTES_PER_UPDATE[prec] * n * tune[3],
+                     "launch_ms": kern_ms * tune[3]},
         "status_flags": flags,
     }
+    if not args.no_ensemble and args.workload != "ensemble_336":
+        # the batched workload: 256 x 128^2 + 64 x 256^2 + 16 x 512^2 replicas in one launch,
+        # timed over at least 64 steps (graph replay)
+        ens = W.ensemble_336()
+        ne = sum(r["nx"] * r["ny"] for r in ens)
+        se = max(args.steps, 64)
+        we, ee, fe, te = time_precision(torch, L, ens, prec, se, max(args.warmup, 32))
+        ke = ee / se
+        out["ensemble_336"] = {"MLUPS": ne * se / we / 1e6, "ms_per_step": we * 1e3 / se, "steps": se,
+                               "nodes": ne, "replicas": len(ens),
+                               "achieved_GBs": BYTES_PER_UPDATE[prec] * ne / (ke * 1e-3) / 1e9,
+                               "frac": BYTES_PER_UPDATE[prec] * ne / (ke * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "kernel": kernel_name(te, ens),
+                               "tile": {"strip_width": te[0], "rows": te[1], "workgroups": te[2],
+                                        "steps_per_launch": te[3]},
+                               "status_flags": fe}
+        log(f"ensemble_336: {we * 1e3 / se:.4f} ms/step, {ne * se / we / 1e6:.0f} MLUPS, "
+            f"frac {out['ensemble_336']['frac']:.3f}")
     if not args.no_fp64:
         w64, e64, f64, tune64 = time_precision(torch, L, reps, "fp64", max(args.steps // 2, 10), args.warmup // 2 + 1)
         s64 = max(args.steps // 2, 10)
@@ -212,7 +245,7 @@ def main():
         out["fp64"] = {"value": n * s64 / w64 / 1e6, "unit": "MLUPS", "ms_per_step": w64 * 1e3 / s64,
                        "achieved_GBs": BYTES_PER_UPDATE["fp64"] * n / (k64 * 1e-3) / 1e9,
                        "frac": BYTES_PER_UPDATE["fp64"] * n / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                       "tile": {"strip_width": tune64[0], "rows": tune64[1]}}
+                       "tile": {"strip_width": tune64[0], "rows": tune64[1], "steps_per_launch": tune64[3]}}
         out["fp32s_over_fp64"] = out["value"] / out["fp64"]["value"]
         log(f"fp64: {out['fp64']['ms_per_step']:.4f} ms/step, {out['fp64']['value']:.0f} MLUPS")
     if (not args.no_correlated and len(reps) == 1 and max(cfg["nx"], cfg["ny"]) <= 8192

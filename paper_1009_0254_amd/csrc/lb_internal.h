@@ -109,7 +109,7 @@ std::vector<Tile> make_tiles(const std::vector<RepDesc> &reps, int bx, double h)
 
 // Two steps per launch (lb_step2.hip).  A workgroup of bx lanes holds G lane groups of bx / G
 // lanes, each running one tile: workgroup w runs tiles[wgs[w] .. wgs[w + 1]), G = their
-// count.  A tile's x0 is its first output column (strips of bx / G - 4 output columns); a
+// count.  A tile's x0 is its first output column (strips of bx / G - 6 output columns); a
 // replica whose row fits a group (nx <= bx / G) has x0 = 0 and whole-row tiles; rep < 0
 // marks an empty group.
 struct Step2Launch {

@@ -12,26 +12,28 @@
 // A workgroup holds G lane groups of BG = blockDim.x / G lanes (BG a multiple of 64, so a
 // wave is in one group).  Each group runs one tile: rows [y0, y1) of a replica, and either
 //   - the whole row (nx <= BG; lane l is column l, neighbours wrap inside the group), or
-//   - a strip (nx > BG) whose lane l is column x0 - 2 + l: the first step computes all BG
-//     columns, the second step only the inner BG - 4 (it needs the first step's results one
-//     column further out, and those need densities one further), so strips overlap by four
-//     columns and store columns [x0, x0 + BG - 4).
+//   - a strip (nx > BG) whose lane l is column x0 - 3 + l.  Each step loses one column at
+//     each end (a lane needs its neighbours' densities for the stencils, and the second step
+//     pulls from the neighbouring columns of the first step's output): the first step is
+//     valid at lanes 1 .. BG - 2, the second step's densities at 2 .. BG - 3 and its results
+//     at 3 .. BG - 4.  So strips overlap by six columns and store columns [x0, x0 + BG - 6).
 // The group marches down the rows.  Stage 1 (step t) collides row r; its output row goes to
 // LDS (populations 1, 3, 5, 6, 7, 8, which the pull of step t + 1 takes from the next
 // column) and registers (0, 2, 4, which stay in the column).  Stage 2 (step t + 1) pulls row
-// r - 2 from those (the pull of row y needs output rows y - 1, y, y + 1), forms its density,
-// and collides row r - 3 (whose stencil needs the density of row r - 2).  So a tile of output
-// rows [y0, y1) runs stage 1 on rows [y0 - 2, y1 + 2) and reads rows [y0 - 4, y1 + 4) of
-// f*(t - 1).  Two workgroup barriers per row: after the stage-1 density and the stage-2
-// density of a row are in LDS (A), and after the stage-1 output row is (B).
+// r - 2 for its density (the pull of row y reads output rows y - 1, y, y + 1), and collides
+// row r - 3 (whose stencil needs the density of row r - 2), pulling that row again from the
+// same LDS rows and registers, so that no pulled row is held across a barrier.  A tile of
+// output rows [y0, y1) runs stage 1 on rows [y0 - 2, y1 + 2) and reads rows [y0 - 4, y1 + 4)
+// of f*(t - 1).  Two workgroup barriers per row: after the stage-1 and stage-2 densities of
+// a row are in LDS (A), and after the stage-1 output row is (B).
 //
 // LDS per group, each array padded by one slot on both sides of the BG lanes (W = BG + 2):
-//   ring1[3][W]    rho(t) - rho0 of three consecutive rows (strip halo columns in slots 0, W-1)
+//   ring1[3][W]    rho(t) - rho0 of three consecutive rows
 //   ring2[3][W]    rho(t+1) - rho0
-//   F78[2][W]      populations 7, 8 of the last stage-1 row         (stored type S)
-//   F13[3][2][W]   populations 1, 3 of the last three stage-1 rows
-//   F56[3][2][W]   populations 5, 6 of the last three stage-1 rows
-// The loop is unrolled by three so that every ring index is a compile-time constant.
+//   F13[4][2][W]   populations 1, 3 of the last four stage-1 rows (stored type S)
+//   F56[5][2][W]   populations 5, 6 of the last five
+//   F78[3][2][W]   populations 7, 8 of the last three
+// (each kept as long as a density pull or a collision pull still reads it).
 
 #include "lb_collide.h"
 #include "lb_internal.h"
@@ -43,7 +45,7 @@ namespace lbf {
 
 template <typename S, typename R> constexpr unsigned step2_group_bytes(unsigned W)
 {
-    return W * (6 * (unsigned)sizeof(R) + 14 * (unsigned)sizeof(S));
+    return W * (6 * (unsigned)sizeof(R) + 24 * (unsigned)sizeof(S));
 }
 
 template <typename S, typename R, bool PLAIN>
@@ -84,47 +86,35 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__r
     unsigned char *gb = smem_raw + grp * step2_group_bytes<S, R>(W);
     R *ring1 = reinterpret_cast<R *>(gb);
     R *ring2 = ring1 + 3 * W;
-    S *F78 = reinterpret_cast<S *>(ring2 + 3 * W);
-    S *F13 = F78 + 2 * W;
-    S *F56 = F13 + 6 * W;
+    S *F13 = reinterpret_cast<S *>(ring2 + 3 * W);
+    S *F56 = F13 + 8 * W;
+    S *F78 = F56 + 10 * W;
 
     // columns.  whole: lane l is column l (lanes past the row duplicate column l mod nx and
     // never store; whole waves past it only keep the barriers).  strip: lane l is column
-    // x0 - 2 + l (mod nx).
+    // x0 - 3 + l (mod nx).
     const bool whole = nx <= BG;
     const bool idle = gidle || (whole && (tid - grp * BG) / 64 * 64 >= nx);   // uniform per wave
     unsigned xw;
     if (whole) {
         xw = l < nx ? l : l % nx;
     } else {
-        const int xs = tl.x0 - 2 + (int)l;
+        const int xs = tl.x0 - 3 + (int)l;
         xw = (unsigned)(xs < 0 ? xs + (int)nx : (xs >= (int)nx ? xs - (int)nx : xs));
     }
-    constexpr unsigned ESZ = sizeof(S);
-    const unsigned cm = (xw == 0 ? nx - 1 : xw - 1) * ESZ;
-    const unsigned c0 = xw * ESZ;
-    const unsigned cp = (xw == nx - 1 ? 0 : xw + 1) * ESZ;
+    const unsigned cm = (xw == 0 ? nx - 1 : xw - 1) * ES;
+    const unsigned c0 = xw * ES;
+    const unsigned cp = (xw == nx - 1 ? 0 : xw + 1) * ES;
     // LDS slots of the lane and of its two neighbours (row arrays of W slots, lane l at l + 1)
     const unsigned i0 = l + 1;
     const unsigned im = whole ? (xw == 0 ? nx - 1 : xw - 1) + 1 : l;
     const unsigned ip = whole ? (xw == nx - 1 ? 0 : xw + 1) + 1 : l + 2;
-    // ring1 halo densities: whole rows copy the wrap-around neighbours from their own
-    // columns (the lane of column nx - 1 also writes slot 0, the lane of column 0 slot nx + 1);
-    // strips pull the two columns beyond their ends with lanes 0 and 1
+    // ring1 of whole rows: the lane of column nx - 1 also writes slot 0 and the lane of
+    // column 0 slot nx + 1, the wrap-around neighbours of columns 0 and nx - 1
     const bool xtra = whole && (l == 0 || l == nx - 1);
     const unsigned xslot = l == 0 ? nx + 1 : 0;
-    const bool halo = !whole && l < 2;
-    unsigned hxw = 0;
-    if (!whole) {
-        const int hx = l == 0 ? tl.x0 - 3 : tl.x0 - 2 + (int)BG;
-        hxw = (unsigned)(((hx % (int)nx) + (int)nx) % (int)nx);
-    }
-    const unsigned hcm = (hxw == 0 ? nx - 1 : hxw - 1) * ESZ;
-    const unsigned hc0 = hxw * ESZ;
-    const unsigned hcp = (hxw == nx - 1 ? 0 : hxw + 1) * ESZ;
-    const unsigned hslot = l == 0 ? 0 : BG + 1;
-    // stage 2 stores lanes whose column is inside the tile's output columns
-    const bool store2 = whole ? l < nx : (l >= 2 && l < BG - 2 && (unsigned)(tl.x0 - 2 + (int)l) < nx);
+    // stage 2 stores lanes whose column is one of the tile's output columns
+    const bool store2 = whole ? l < nx : (l >= 3 && l < BG - 3 && (unsigned)(tl.x0 - 3 + (int)l) < nx);
 
     auto wrapy = [ny](int v) -> unsigned {
         const int m = v % (int)ny;
@@ -138,18 +128,22 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__r
                     row_rsrc(P + (unsigned long long)wrapy(yy) * pitch, rowb),
                     row_rsrc(P + (unsigned long long)wrapy(yy + 1) * pitch, rowb)};
     };
-    auto pull = [&](const Rows &rr, unsigned o0, unsigned ol, unsigned orr, R f[Q]) {
-        f[0] = (R)bld<S>(rr.z, o0, 0);
-        f[1] = (R)bld<S>(rr.z, ol, nxb);
-        f[2] = (R)bld<S>(rr.m, o0, 2 * nxb);
-        f[3] = (R)bld<S>(rr.z, orr, 3 * nxb);
-        f[4] = (R)bld<S>(rr.p, o0, 4 * nxb);
-        f[5] = (R)bld<S>(rr.m, ol, 5 * nxb);
-        f[6] = (R)bld<S>(rr.m, orr, 6 * nxb);
-        f[7] = (R)bld<S>(rr.p, orr, 7 * nxb);
-        f[8] = (R)bld<S>(rr.p, ol, 8 * nxb);
+    auto pull = [&](const Rows &rr, R f[Q]) {
+        f[0] = (R)bld<S>(rr.z, c0, 0);
+        f[1] = (R)bld<S>(rr.z, cm, nxb);
+        f[2] = (R)bld<S>(rr.m, c0, 2 * nxb);
+        f[3] = (R)bld<S>(rr.z, cp, 3 * nxb);
+        f[4] = (R)bld<S>(rr.p, c0, 4 * nxb);
+        f[5] = (R)bld<S>(rr.m, cm, 5 * nxb);
+        f[6] = (R)bld<S>(rr.m, cp, 6 * nxb);
+        f[7] = (R)bld<S>(rr.p, cp, 7 * nxb);
+        f[8] = (R)bld<S>(rr.p, cm, 8 * nxb);
     };
     auto dens = [&](const R f[Q]) { return dens9<R, PLAIN>(f, c); };
+    auto put1 = [&](unsigned slot, R v) {
+        ring1[slot * W + i0] = v;
+        if (xtra) ring1[slot * W + xslot] = v;
+    };
 
     const int y0 = tl.y0, y1 = tl.y1;
     const int ys0 = y0 - 2, ys1 = y1 + 2;   // stage-1 rows [ys0, ys1)
@@ -157,85 +151,94 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__r
     unsigned st = 0;
 
     // stage-1 registers: pulled rows r (cur), r + 1 (nxt), r + 2 (in flight)
-    R fa[Q], fb[Q], fc[Q], hv[Q];
-    // stage-1 output populations that stay in the column, rings of three rows (slot = row's k mod 3)
-    S F0r[3], F2r[3], F4r[3];
-    // stage-2 pulled rows: the one pulled in this iteration (gn) and the previous one (go)
-    R gn[Q], go[Q];
+    R fa[Q], fb[Q], fc[Q];
+    // stage-1 output populations that stay in the column: rings of three rows (row rho at
+    // slot (rho - ys0) mod 3) and the population 2 of the row before the ring (F2x)
+    S F0r[3], F2r[3], F4r[3], F2x = (S)0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) F0r[i] = F2r[i] = F4r[i] = (S)0;
 
-    // prologue (as k_step): densities of rows ys0 - 1 and ys0, populations of row ys0, loads of
-    // row ys0 + 1 in flight
-    auto put1 = [&](unsigned slot, R v) {
-        ring1[slot * W + i0] = v;
-        if (xtra) ring1[slot * W + xslot] = v;
-    };
+    // prologue: densities of rows ys0 - 1 and ys0, populations of row ys0, loads of row
+    // ys0 + 1 in flight
     {
         const Rows ra = rows_of(ys0 - 1), rb = rows_of(ys0);
         if (!idle) {
-            pull(ra, c0, cm, cp, fb);
+            pull(ra, fb);
             put1(0, dens(fb));
-            if (halo) {
-                pull(ra, hc0, hcm, hcp, hv);
-                ring1[0 * W + hslot] = dens(hv);
-                pull(rb, hc0, hcm, hcp, hv);
-                ring1[1 * W + hslot] = dens(hv);
-            }
-            pull(rb, c0, cm, cp, fa);
+            pull(rb, fa);
             put1(1, dens(fa));
         }
         const Rows rc = rows_of(ys0 + 1);
-        if (!idle) {
-            pull(rc, c0, cm, cp, fb);
-            if (halo) pull(rc, hc0, hcm, hcp, hv);
-        }
+        if (!idle) pull(rc, fb);
     }
 
-    // one iteration; K = k mod 3 fixes every ring slot (all modulo 3, with r = ys0 + k):
-    //   ring1 (rho(t)):       row rho at slot (rho - ys0 + 1), so row r + j at K + 1 + j
-    //   ring2 (rho(t+1)):     row rho at slot (rho - ys0), so row r - 2 + j at K + 1 + j
-    //   F13, F56, F0r, F2r, F4r (stage-1 output): row rho at slot (rho - ys0), row r at K
+    // the nine populations of step t + 1 pulled at row y (stored values, as a load would give
+    // them) from the stage-1 output: own column rows y (0), y - 1 (2), y + 1 (4), LDS rows
+    // y (1, 3), y - 1 (5, 6), y + 1 (7, 8)
+    auto pull2 = [&](S v0, S v2, S v4, const S *f13, const S *f56, const S *f78, R g[Q]) {
+        g[0] = (R)v0;
+        g[1] = (R)f13[im];
+        g[2] = (R)v2;
+        g[3] = (R)f13[W + ip];
+        g[4] = (R)v4;
+        g[5] = (R)f56[im];
+        g[6] = (R)f56[W + ip];
+        g[7] = (R)f78[ip];
+        g[8] = (R)f78[W + im];
+    };
+    // LDS row slots of the stage-1 output row rho = ys0 + j
+    auto s13 = [&](int j) { return F13 + (unsigned)(j & 3) * 2 * W; };
+    auto s56 = [&](int j) { return F56 + (unsigned)(j % 5) * 2 * W; };
+    auto s78 = [&](int j) { return F78 + (unsigned)(j % 3) * 2 * W; };
+
+    // one iteration; K = k mod 3 fixes the slots of the three-row rings (all modulo 3):
+    //   ring1 (rho(t)):    row rho at slot (rho - ys0 + 1), so row r + j at K + 1 + j
+    //   ring2 (rho(t+1)):  row rho at slot (rho - ys0), so row r - 2 + j at K + 1 + j
+    //   F0r, F2r, F4r:     row rho at slot (rho - ys0), row r at K
     auto iter = [&](auto Kc, int k, R cur[Q], R nxt[Q], R nn[Q]) {
         constexpr unsigned K = decltype(Kc)::value;
         const int r = ys0 + k;
-        const bool s1 = !idle && r < ys1;                               // stage 1 on row r
-        const bool p2 = !idle && r >= ys0 + 3 && r <= ys1;              // stage-2 pull of row r - 2
-        const bool c2 = !idle && r >= ys0 + 5 && r <= ys1;              // stage-2 collision of row r - 3
-        // ---- phase 1: density of row r + 1 into ring1, loads of row r + 2, stage-2 pull
-        if (s1) {
-            put1((K + 2) % 3, dens(nxt));
-            if (halo) ring1[((K + 2) % 3) * W + hslot] = dens(hv);
-        }
+        const bool s1 = !idle && r < ys1;                    // stage 1 on row r
+        const bool p2 = !idle && r >= ys0 + 3 && r <= ys1;   // stage-2 density of row r - 2
+        const bool c2 = !idle && r >= ys0 + 5 && r <= ys1;   // stage-2 collision of row r - 3
+        // ---- phase 1: density of row r + 1 into ring1, loads of row r + 2, stage-2 density
+        if (s1) put1((K + 2) % 3, dens(nxt));
         if (k + 1 < nit && r + 2 <= ys1) {
             const Rows rn = rows_of(r + 2);
-            if (s1) {
-                pull(rn, c0, cm, cp, nn);
-                if (halo) pull(rn, hc0, hcm, hcp, hv);
-            }
+            if (s1) pull(rn, nn);
         }
         if (p2) {
-            // row y = r - 2: populations 5, 6 from output row y - 1 = r - 3 (slot K), 1, 3 from
-            // row y (slot K + 1), 7, 8 from row y + 1 = r - 1 (F78), 0 / 2 / 4 from the column's
-            // own rows y (slot K + 1), y - 1 (slot K), y + 1 (slot K + 2)
-#pragma unroll
-            for (int i = 0; i < Q; ++i) go[i] = gn[i];
-            const S *f13 = F13 + ((K + 1) % 3) * 2 * W;
-            const S *f56 = F56 + ((K + 0) % 3) * 2 * W;
-            gn[0] = (R)F0r[(K + 1) % 3];
-            gn[1] = (R)f13[im];
-            gn[2] = (R)F2r[(K + 0) % 3];
-            gn[3] = (R)f13[W + ip];
-            gn[4] = (R)F4r[(K + 2) % 3];
-            gn[5] = (R)f56[im];
-            gn[6] = (R)f56[W + ip];
-            gn[7] = (R)F78[ip];
-            gn[8] = (R)F78[W + im];
-            ring2[((K + 1) % 3) * W + i0] = dens(gn);
+            R g[Q];
+            pull2(F0r[(K + 1) % 3], F2r[K], F4r[(K + 2) % 3], s13(k - 2), s56(k - 3), s78(k - 1), g);
+            ring2[((K + 1) % 3) * W + i0] = dens(g);
         }
         __syncthreads();
-        // ---- phase 2: stage-1 collision of row r, its output to LDS / registers; stage-2
-        // collision of row r - 3
+        // ---- phase 2: stage-2 collision of row r - 3 (pulled again), stage-1 collision of
+        // row r and its output
+        if (c2) {
+            R g[Q];
+            pull2(F0r[K], F2x, F4r[(K + 1) % 3], s13(k - 3), s56(k - 4), s78(k - 2), g);
+            // densities of rows r - 4, r - 3, r - 2 at ring2 slots K + 2, K, K + 1
+            const unsigned s0 = K * W, sm = ((K + 2) % 3) * W, sp = ((K + 1) % 3) * W;
+            R lap, gx, gy;
+            stencil9<R>(ring2[s0 + i0], ring2[s0 + ip], ring2[s0 + im], ring2[sp + i0], ring2[sp + ip],
+                        ring2[sp + im], ring2[sm + i0], ring2[sm + ip], ring2[sm + im], lap, gx, gy);
+            if (PLAIN) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) g[i] -= c.sub[i];
+            }
+            const unsigned y = (unsigned)(r - 3);   // inside [y0, y1): no wrap
+            const unsigned s2 = collide<R, false>(g, lap, gx, gy, c, d.noise, y * nx + xw, d.rep_id, t + 1,
+                                                  d.seed_lo, d.seed_hi, (R)0, (R)0);
+            const auto Wr = row_rsrc(Qo + (unsigned long long)y * pitch, rowb);
+            if (store2) {
+                st |= s2;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) bst<S>(Wr, c0, i * nxb, (S)(PLAIN ? add_rn<R>(g[i], c.sub[i]) : g[i]));
+            }
+        }
+        // keep the two collisions apart: interleaved, their temporaries would be live together
+        __builtin_amdgcn_sched_barrier(0);
         if (s1) {
             const unsigned s0 = ((K + 1) % 3) * W, sm = (K % 3) * W, sp = ((K + 2) % 3) * W;
             R lap, gx, gy;
@@ -246,49 +249,26 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__r
                 for (int i = 0; i < Q; ++i) cur[i] -= c.sub[i];
             }
             const unsigned yr = wrapy(r);
-            st |= collide<R, false>(cur, lap, gx, gy, c, d.noise, yr * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi,
-                                    (R)0, (R)0);
+            const unsigned s1f = collide<R, false>(cur, lap, gx, gy, c, d.noise, yr * nx + xw, d.rep_id, t,
+                                                   d.seed_lo, d.seed_hi, (R)0, (R)0);
+            st |= s1f;
             S o[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) o[i] = (S)(PLAIN ? add_rn<R>(cur[i], c.sub[i]) : cur[i]);
             F0r[K] = o[0];
+            F2x = F2r[K];
             F2r[K] = o[2];
             F4r[K] = o[4];
-            S *f13 = F13 + K * 2 * W;
-            S *f56 = F56 + K * 2 * W;
+            S *f13 = s13(k), *f56 = s56(k), *f78 = s78(k);
             f13[i0] = o[1];
             f13[W + i0] = o[3];
             f56[i0] = o[5];
             f56[W + i0] = o[6];
-            F78[i0] = o[7];
-            F78[W + i0] = o[8];
-        }
-        // keep the two collisions apart: interleaved, their temporaries would be live together
-        __builtin_amdgcn_sched_barrier(0);
-        if (c2) {
-            // densities of rows r - 4, r - 3, r - 2 at ring2 slots K + 2, K, K + 1
-            const unsigned s0 = K * W, sm = ((K + 2) % 3) * W, sp = ((K + 1) % 3) * W;
-            R lap, gx, gy;
-            stencil9<R>(ring2[s0 + i0], ring2[s0 + ip], ring2[s0 + im], ring2[sp + i0], ring2[sp + ip],
-                        ring2[sp + im], ring2[sm + i0], ring2[sm + ip], ring2[sm + im], lap, gx, gy);
-            if (PLAIN) {
-#pragma unroll
-                for (int i = 0; i < Q; ++i) go[i] -= c.sub[i];
-            }
-            const unsigned y = (unsigned)(r - 3);   // inside [y0, y1): no wrap
-            const unsigned s2 = collide<R, false>(go, lap, gx, gy, c, d.noise, y * nx + xw, d.rep_id, t + 1,
-                                                  d.seed_lo, d.seed_hi, (R)0, (R)0);
-            const auto Wr = row_rsrc(Qo + (unsigned long long)y * pitch, rowb);
-            if (store2) {
-                st |= s2;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) bst<S>(Wr, c0, i * nxb, (S)(PLAIN ? add_rn<R>(go[i], c.sub[i]) : go[i]));
-            }
+            f78[i0] = o[7];
+            f78[W + i0] = o[8];
         }
         __syncthreads();
     };
-    // the slots of K are those of k mod 3 relative to the prologue (ring1 rows ys0 - 1, ys0 at
-    // slots 0, 1 = (K + 1 + j) % 3 for K = 0, j = -1, 0)
     using K0 = std::integral_constant<unsigned, 0>;
     using K1 = std::integral_constant<unsigned, 1>;
     using K2 = std::integral_constant<unsigned, 2>;
@@ -297,8 +277,9 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__r
         if (k + 1 < nit) iter(K1{}, k + 1, fb, fc, fa);
         if (k + 2 < nit) iter(K2{}, k + 2, fc, fa, fb);
     }
-    // stage-1 flags of rows outside the output rows are those of the neighbouring tiles' own
-    // output rows (or, for whole rows, of the same nodes): report only stored results
+    // the stage-1 results of a storing lane are those of nodes whose second step it stores (its
+    // column; rows outside the tile are also other tiles' rows), so the flags of every node and
+    // step reach the word through some storing lane
     if (st && store2) atomicOr(flags, st);
 }
 

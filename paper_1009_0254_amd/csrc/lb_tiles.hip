@@ -118,8 +118,8 @@ static int groups_for(int nx, int bx)
     return 1;
 }
 
-// The two-step kernel's work list.  Strips of a replica wider than a workgroup overlap by four
-// columns (each stores bx - 4); whole rows of narrower replicas are packed G to a workgroup,
+// The two-step kernel's work list.  Strips of a replica wider than a workgroup overlap by six
+// columns (each stores bx - 6); whole rows of narrower replicas are packed G to a workgroup,
 // G vertically adjacent tiles of one replica (they share boundary rows), with empty groups
 // (rep = -1) after the last tile of a replica.  XCD placement as in make_tiles: a replica
 // with at least 8 strips is split into 8 contiguous strip groups, one per XCD queue; smaller
@@ -142,7 +142,7 @@ int make_tiles2(const std::vector<RepDesc> &reps, int bx, double h, std::vector<
         const RepDesc &d = reps[r];
         const Bands B(d.ny, h);
         if (d.nx > bx) {
-            const int w2 = bx - 4;
+            const int w2 = bx - 6;
             const int ns = (d.nx + w2 - 1) / w2;
             const int parts = ns >= X ? X : 1;
             for (int k = 0; k < parts; ++k) {
@@ -187,7 +187,7 @@ long long max_tiles2(const std::vector<int> &nx, const std::vector<int> &ny)
 {
     long long t = 0;
     for (size_t r = 0; r < nx.size(); ++r) {
-        const long long strips = nx[r] > STEP2_MIN_BX ? (nx[r] + STEP2_MIN_BX - 5) / (STEP2_MIN_BX - 4) : 1;
+        const long long strips = nx[r] > STEP2_MIN_BX ? (nx[r] + STEP2_MIN_BX - 7) / (STEP2_MIN_BX - 6) : 1;
         t += strips * ((ny[r] + STEP2_MIN_H - 1) / STEP2_MIN_H) + 8;
     }
     return t;

@@ -200,24 +200,26 @@ def test_correlated_noise_validation_follows_the_fig2_region():
 
 def test_bench_traffic_is_tied_to_the_profiled_kernel_workload_and_tile(tmp_path, monkeypatch):
     """bench.py reports counter-measured HBM bytes only for the kernel source, workload and
-    tile shape the committed counters were taken with; anything else gives null."""
+    launch configuration (width, rows, steps per launch) the committed counters were taken
+    with; anything else gives null."""
     import json
     import sys
     sys.path.insert(0, ROOT)
     import bench
     sha = bench.kernel_sha()
     c = {"kernel_src_sha": sha, "workload_key": "single_phase_8192", "hbm_bytes_per_launch": 1.0,
-         "per_tile": {"512,8": {"hbm_bytes_per_launch": 5.0}, "256,16": {"hbm_bytes_per_launch": 4.0}}}
+         "per_tile": {"512,8,1": {"hbm_bytes_per_launch": 5.0}, "256,16,2": {"hbm_bytes_per_launch": 4.0}}}
     f = tmp_path / "c.json"
     f.write_text(json.dumps(c))
     monkeypatch.setattr(bench, "COUNTERS", str(f))
-    assert bench.traffic_from_counters("single_phase_8192", (512, 8)) == 5.0
-    assert bench.traffic_from_counters("single_phase_8192", (256, 16)) == 4.0
-    assert bench.traffic_from_counters("single_phase_8192", (128, 8)) is None
-    assert bench.traffic_from_counters("ensemble_336", (512, 8)) is None
+    assert bench.traffic_from_counters("single_phase_8192", (512, 8, 1)) == 5.0
+    assert bench.traffic_from_counters("single_phase_8192", (256, 16, 2)) == 4.0
+    assert bench.traffic_from_counters("single_phase_8192", (256, 16, 1)) is None
+    assert bench.traffic_from_counters("single_phase_8192", (128, 8, 1)) is None
+    assert bench.traffic_from_counters("ensemble_336", (512, 8, 1)) is None
     c["kernel_src_sha"] = "0" * 16
     f.write_text(json.dumps(c))
-    assert bench.traffic_from_counters("single_phase_8192", (512, 8)) is None
+    assert bench.traffic_from_counters("single_phase_8192", (512, 8, 1)) is None
     assert len(sha) == 16
 
 
@@ -226,5 +228,7 @@ def test_committed_counters_name_their_workload_and_tiles():
     c = json.load(open(os.path.join(ROOT, "profiles", "k_step_fp32s_8192_counters.json")))
     assert c["workload_key"] == "single_phase_8192" and c["tile"] in c["per_tile"]
     for t, v in c["per_tile"].items():
-        w, r = (int(s) for s in t.split(","))
-        assert w % 64 == 0 and r >= 4 and v["hbm_bytes_per_launch"] > 72 * 8192 * 8192 * 0.9
+        w, r, k = (int(s) for s in t.split(","))
+        # a launch moves at least one read and one write of every population (two steps per
+        # launch move the same bytes as one)
+        assert w % 64 == 0 and r >= 4 and k in (1, 2) and v["hbm_bytes_per_launch"] > 72 * 8192 * 8192 * 0.9
