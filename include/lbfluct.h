@@ -162,6 +162,17 @@ lb_status lb_step(lb_handle *h, int64_t nsteps);
  * (host pointer, 6 doubles).  Synchronous. */
 lb_status lb_moments(lb_handle *h, int32_t rep, double *d_m9, double *h_totals);
 
+/* lb_moments for callers that cannot allocate device memory or hand the library scratch
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same outputs, bitwise, but the reduction's scratch -- the partial sums of
+ * at most 1024 workgroups and the six totals, 48.3 KB -- lives in a fixed device array of the
+ * library (one per GPU, held until the process ends, its address resolved by lb_init) instead
+ * of the handle's workspace.  Allocates nothing.  Every lattice the library accepts fits that
+ * scratch (its workgroups stride over the nodes); rep outside [0, n_rep) gives LB_EINVAL.
+ * Calls that overlap on one GPU (two host threads, or two streams) share the array and race;
+ * successive calls need no clearing (each writes all it reads).  Synchronous. */
+lb_status lb_moments_static(lb_handle *h, int32_t rep, double *d_m9, double *h_totals);
+
 /* Static structure factor of all nine modes, the equilibration measurement of Sec. V.A:
  * op = LB_SK_SAMPLE adds |m_a(k)|^2, with a(k) = n^-1/2 sum_r exp(i k.r) a(r) (Sec. III
  * notation), for k on the half plane kx = 0..nx/2, ky = 0..ny-1, to FP64 accumulators;

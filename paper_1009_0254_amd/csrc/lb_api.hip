@@ -16,10 +16,44 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
 using namespace lbf;
+
+// Scratch of lb_moments_static: the partial sums of the moment reduction (6 per workgroup, at
+// most MAX_STATIC_RED_BLOCKS workgroups) and the six totals, in a fixed device array that each
+// GPU holds until the process ends.  Host code uses only the per-device address resolved by
+// static_scratch_of (the array's name is no device address on the host).
+namespace {
+constexpr int MAX_STATIC_RED_BLOCKS = 1024;
+constexpr int STATIC_TOT_OFF = 6 * MAX_STATIC_RED_BLOCKS;   // doubles before the totals
+constexpr int STATIC_SCRATCH_DOUBLES = STATIC_TOT_OFF + 32;
+constexpr int MAX_DEVICES = 64;
+}  // namespace
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch[MAX_DEVICES] = {};
+
+// the device address of `scratch` on the current device, resolved once per device
+lb_status static_scratch_of(int *device, double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return LB_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LB_EDEVICE;
+        g_scratch[dev] = (double *)ptr;
+    }
+    *device = dev;
+    *out = g_scratch[dev];
+    return LB_OK;
+}
+}  // namespace
 
 namespace {
 
@@ -219,6 +253,8 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
 
 struct lb_handle {
     int n_rep = 0, precision = 0;
+    int device = -1;
+    double *static_scratch = nullptr;   // this device's address of the scratch array
     uint32_t features = 0;
     std::vector<RepDesc> reps;
     std::vector<size_t> acc_off;     // element offset of each replica's S(k) accumulator
@@ -745,6 +781,10 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
 
     lb_handle *h = new (std::nothrow) lb_handle();
     if (!h) return LB_ENOMEM;
+    if ((st = static_scratch_of(&h->device, &h->static_scratch)) != LB_OK) {
+        delete h;
+        return st;
+    }
     h->n_rep = n_rep;
     h->precision = precision;
     h->features = features;
@@ -934,6 +974,26 @@ lb_status lb_moments(lb_handle *h, int32_t rep, double *d_m9, double *h_totals)
         return LB_EDEVICE;
     if (h_totals &&
         hipMemcpyAsync(h_totals, h->tot, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
+        return LB_EDEVICE;
+    return hip_ok(hipStreamSynchronize(h->stream));
+}
+
+lb_status lb_moments_static(lb_handle *h, int32_t rep, double *d_m9, double *h_totals)
+{
+    if (!h || rep < 0 || rep >= h->n_rep) return LB_EINVAL;
+    if (!h->static_scratch) return LB_ESTATE;
+    const RepDesc &d = h->reps[rep];
+    const long long n = (long long)d.nx * d.ny;
+    // the reduction's workgroups stride over the nodes, so any lattice fits the fixed scratch
+    const int nb = (int)std::min<long long>(MAX_RED_BLOCKS, (n + 255) / 256);
+    if (nb > MAX_STATIC_RED_BLOCKS) return LB_EINVAL;
+    // every workgroup writes its six partials and the second pass writes the totals: nothing
+    // in the scratch is read before this call writes it
+    double *partials = h->static_scratch, *tot = h->static_scratch + STATIC_TOT_OFF;
+    if (launch_moments(h->precision, h->fbuf[h->par], h->reps_d, d, rep, d_m9, partials, nb, tot, h->stream) !=
+        hipSuccess)
+        return LB_EDEVICE;
+    if (h_totals && hipMemcpyAsync(h_totals, tot, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess)
         return LB_EDEVICE;
     return hip_ok(hipStreamSynchronize(h->stream));
 }

@@ -67,6 +67,7 @@ def lib() -> ctypes.CDLL:
                               ctypes.POINTER(vp)]
         L.lb_step.argtypes = [vp, ctypes.c_int64]
         L.lb_moments.argtypes = [vp, ctypes.c_int32, vp, dp]
+        L.lb_moments_static.argtypes = [vp, ctypes.c_int32, vp, dp]
         L.lb_structure_factor.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int64)]
         L.lb_set_sampling.argtypes = [vp, ctypes.c_int64, ctypes.c_int64]
         L.lb_status_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int64)]
@@ -78,7 +79,7 @@ def lib() -> ctypes.CDLL:
         L.lb_free.restype = None
         L.lb_strerror.argtypes = [ctypes.c_int32]
         L.lb_strerror.restype = ctypes.c_char_p
-        for fn in ("lb_workspace_size", "lb_init", "lb_step", "lb_moments", "lb_structure_factor",
+        for fn in ("lb_workspace_size", "lb_init", "lb_step", "lb_moments", "lb_moments_static", "lb_structure_factor",
                    "lb_set_sampling", "lb_status_flags", "lb_noise_normals", "lb_philox", "lb_tuning"):
             getattr(L, fn).restype = ctypes.c_int32
         _lib = L
@@ -173,6 +174,13 @@ class Lattice:
         m = torch.empty((9, c["ny"], c["nx"]), dtype=torch.float64, device=self.device) if planes else None
         tot = (ctypes.c_double * 6)()
         _check("lb_moments", lib().lb_moments(self._h, rep, m.data_ptr() if planes else None, tot))
+        return m, np.array(tot[:])
+
+    def lb_moments_static(self, rep: int = 0, planes: bool = True):
+        c = self.cfgs[rep]
+        m = torch.empty((9, c["ny"], c["nx"]), dtype=torch.float64, device=self.device) if planes else None
+        tot = (ctypes.c_double * 6)()
+        _check("lb_moments_static", lib().lb_moments_static(self._h, rep, m.data_ptr() if planes else None, tot))
         return m, np.array(tot[:])
 
     def lb_structure_factor(self, op: int, rep: int = -1):
