@@ -309,3 +309,34 @@ def radial_spectrum(rho: np.ndarray):
     sums = np.bincount(b[keep], weights=S[keep], minlength=nb)
     counts = np.bincount(b[keep], minlength=nb)
     return np.where(counts > 0, sums / np.maximum(counts, 1), 0.0), counts
+
+
+def interface_heights(rho: np.ndarray, level: float, rows: int, rising: bool) -> np.ndarray:
+    """The height h(x) of an interface (Sec. V.B): in every column x, the position y at which
+    the density rho[y][x] passes `level` (for the capillary run the midpoint (rho_L + rho_V)/2),
+    searched in rows [rows[0], rows[1]), rising (vapour below, liquid above) or falling, as the
+    first such passage between two neighbouring nodes, placed on the straight line through
+    them.  Plain loops over the columns."""
+    lo, hi = rows
+    ny, nx = rho.shape
+    h = np.empty(nx)
+    for x in range(nx):
+        col = rho[lo:hi, x]
+        found = False
+        for j in range(hi - lo - 1):
+            a, b = col[j], col[j + 1]
+            if (a - level) * (b - level) <= 0 and ((b > a) if rising else (b < a)):
+                h[x] = lo + j + (level - a) / (b - a)
+                found = True
+                break
+        if not found:
+            raise ValueError(f"no {'rising' if rising else 'falling'} passage of {level} in column {x}")
+    return h
+
+
+def height_spectrum(h: np.ndarray) -> np.ndarray:
+    """|h(k)|^2 with h(k) = Lx^-1/2 sum_x (h(x) - <h>) e^{ikx}, k = 2 pi m / Lx, m = 0 .. Lx/2
+    (the spectrum whose mean Sec. V.B compares with kT / (sigma k^2), eq. capill-static);
+    numpy's real FFT as the sum."""
+    H = np.fft.rfft(h - h.mean())
+    return (H.real ** 2 + H.imag ** 2) / h.size

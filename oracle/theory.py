@@ -337,6 +337,44 @@ def transient_covariance_batch(kx, ky, lam, cs2, rho0, kappa, kT, t, power=False
     return (Ga, Pa) if power else Ga
 
 
+def sampled_mean_covariance_batch(kx, ky, lam, cs2, rho0, kappa, kT, t0, every, nsamples):
+    """Mean of the covariance G(t) over the sampling times t = t0 + every s, s = 0 .. N - 1,
+    after a noise-free start (G(0) = 0), for the k = 0 noise at many k (arrays kx, ky):
+    what an S(k) accumulated at those times averages to in the linear model.
+
+    With P = M^every and G(t) = sum_{u<t} M^u Q M^{Hu} (eq. lb-lang-ft from rest),
+    G(t0 + every s) = P^s G(t0) P^{Hs} + G(every s) and G(every s) = sum_{v<s} P^v G(every) P^{Hv},
+    so  N * mean = D_N(G(t0)) + (N - 1) D_N(G(every)) - E_N(G(every))  with
+    D_m(Y) = sum_{v<m} P^v Y P^{Hv} and E_m(Y) = sum_{v<m} v P^v Y P^{Hv}.  A block of a terms
+    followed by one of b combines as D_{a+b} = D_a + P^a D_b P^{Ha},
+    E_{a+b} = E_a + P^a (E_b + a D_b) P^{Ha}; N is built from its binary digits.
+    Returns [K, 9, 9]."""
+    H = lambda A: np.conj(np.swapaxes(A, 1, 2))
+    G0, _ = transient_covariance_batch(kx, ky, lam, cs2, rho0, kappa, kT, t0, power=True)
+    Ge, P = transient_covariance_batch(kx, ky, lam, cs2, rho0, kappa, kT, every, power=True)
+    eye = np.broadcast_to(np.eye(9, dtype=complex), P.shape).copy()
+
+    def block_sums(Y):
+        # (count, P^count, D, E) of the doubling block and of the running total
+        cd, Pd, Dd, Ed = 1, P, Y.copy(), np.zeros_like(Y)
+        ca, Pa, Da, Ea = 0, eye, np.zeros_like(Y), np.zeros_like(Y)
+        n = int(nsamples)
+        while n > 0:
+            if n & 1:
+                # running block (a = ca terms) followed by the doubling block (b = cd terms)
+                Da, Ea = Da + Pa @ Dd @ H(Pa), Ea + Pa @ (Ed + ca * Dd) @ H(Pa)
+                Pa, ca = Pd @ Pa, ca + cd
+            n >>= 1
+            if n:
+                Dd, Ed = Dd + Pd @ Dd @ H(Pd), Ed + Pd @ (Ed + cd * Dd) @ H(Pd)
+                Pd, cd = Pd @ Pd, 2 * cd
+        return Da, Ea
+
+    D0, _ = block_sums(G0)
+    De, Ee = block_sums(Ge)
+    return (D0 + (nsamples - 1) * De - Ee) / nsamples
+
+
 def psd_all_k(kappa, cs2, lam, rho0=1.0, nk=97, tol=1e-12):
     """True when Xi(k) of eq. (noise-yeo) is positive semi-definite at every k with k_x, k_y in
     [0, pi] (the white region of Fig. 2); checked on an nk x nk grid of k (which includes the

@@ -116,9 +116,12 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__r
     // stage 2 stores lanes whose column is one of the tile's output columns
     const bool store2 = whole ? l < nx : (l >= 3 && l < BG - 3 && (unsigned)(tl.x0 - 3 + (int)l) < nx);
 
+    // periodic row index; v is at most a few rows outside [0, ny) (more than one period only
+    // for lattices a few rows tall), so the wrap is a short uniform loop, not a division
     auto wrapy = [ny](int v) -> unsigned {
-        const int m = v % (int)ny;
-        return (unsigned)(m < 0 ? m + (int)ny : m);
+        while (v < 0) v += (int)ny;
+        while (v >= (int)ny) v -= (int)ny;
+        return (unsigned)v;
     };
     struct Rows {
         __amdgpu_buffer_rsrc_t m, z, p;

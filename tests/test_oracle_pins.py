@@ -810,3 +810,55 @@ int main() {
         want = [int(v) for v in line.split()]
         got = [int(v) for v in O.philox4x32_10(c[:4], c[4:])]
         assert got == want, c
+
+
+def test_sampled_mean_covariance_equals_the_step_sum():
+    """The doubling formula for the covariance averaged over sampling times t0 + every s
+    (s < N) equals the average of the step-by-step transient sum_{u<t} M^u Q M^{Hu} at those
+    times (eq. lb-lang-ft from rest), at random k, for several (t0, every, N)."""
+    lam = th.relaxation_rates(0.8, 0.8, 1.0, 1.0)
+    cs2 = th.sound_speed2(1.0, 1.0 / 3.0, 0.05, 0.04)
+    rng = np.random.default_rng(0)
+    kx, ky = rng.uniform(-np.pi, np.pi, 4), rng.uniform(-np.pi, np.pi, 4)
+    for t0, every, n in ((7, 3, 5), (0, 1, 1), (4, 2, 8), (11, 5, 13), (2, 7, 6)):
+        got = th.sampled_mean_covariance_batch(kx, ky, lam, cs2, 1.0, 0.02, 1e-5, t0, every, n)
+        for i in range(len(kx)):
+            want = sum(th.transient_covariance(kx[i], ky[i], lam, cs2, 1.0, 0.02, 1e-5, t0 + every * s)
+                       for s in range(n)) / n
+            assert np.abs(got[i] - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_interface_heights_recover_a_known_wall():
+    """A wall whose density varies linearly across a band of rows, displaced column by column
+    by a known h(x): the linear interpolation of interface_heights is then exact, for rising and
+    falling walls; with tanh walls (eq. interf-width profile) the recovered heights agree to the
+    interpolation error of a tanh of half-width 2.5 sampled at unit spacing (at most 5.1e-3,
+    over the wall's offsets from the nodes)."""
+    nx, ny = 64, 80
+    x = np.arange(nx)
+    h1 = 20.3 + 0.7 * np.cos(2 * np.pi * 3 * x / nx) + 0.2 * np.sin(2 * np.pi * 5 * x / nx)
+    h2 = 55.6 - 0.4 * np.cos(2 * np.pi * 2 * x / nx)
+    y = np.arange(ny)[:, None]
+    ramp = lambda d: np.clip(0.5 + d / 8.0, 0.0, 1.0)       # linear across 8 rows
+    rho = 0.5 + 0.5 * (ramp(y - h1[None, :]) - ramp(y - h2[None, :]))
+    assert np.abs(O.interface_heights(rho, 0.75, (5, 40), True) - h1).max() < 1e-12
+    assert np.abs(O.interface_heights(rho, 0.75, (40, 75), False) - h2).max() < 1e-12
+    w = 2.5
+    rho = 0.5 + 0.25 * (np.tanh((y - h1[None, :]) / w) - np.tanh((y - h2[None, :]) / w))
+    err = np.abs(O.interface_heights(rho, 0.75, (5, 40), True) - h1).max()
+    assert err < 6e-3, err
+
+
+def test_height_spectrum_of_a_single_wave():
+    """h(x) = c + a cos(2 pi m x / Lx): |h(k_m)|^2 = a^2 Lx / 4 at k_m, nothing elsewhere (the
+    mean is removed); Parseval for a random h."""
+    nx, a, m = 256, 0.3, 7
+    h = 4.0 + a * np.cos(2 * np.pi * m * np.arange(nx) / nx)
+    S = O.height_spectrum(h)
+    assert S.shape == (nx // 2 + 1,)
+    assert abs(S[m] - a * a * nx / 4) < 1e-12
+    assert np.delete(S, m).max() < 1e-24
+    r = np.random.default_rng(3).normal(size=nx)
+    S = O.height_spectrum(r)
+    full = S[0] + S[nx // 2] + 2 * S[1:nx // 2].sum()
+    assert abs(full - ((r - r.mean()) ** 2).sum()) < 1e-9
