@@ -26,7 +26,9 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS and % HBM roofline, FP32-shifted vs FP64, at stated S(k)/moment error"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = {"fp32s": 72, "fp32": 72, "fp64": 144}   # read + write of 9 populations
-COUNTERS = os.path.join(ROOT, "profiles", "k_step_fp32s_8192_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "k_step2_fp32s_8192_counters.json")
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles, 2.4 GHz
+VALU_PEAK_WAVE_INSTS = 256 * 4 / 4 * 2.4e9
 # the byte counters depend on the step kernel (its source, RNG and shared structs) and on the
 # tile list that lb_init builds
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1009_0254_amd", "csrc", f)
@@ -71,20 +73,23 @@ def time_precision(torch, L, cfg, precision, steps, warmup):
     return wall, ev_ms, flags, tune
 
 
-def traffic_from_counters(workload, tile=None):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary,
-    scaled by the same counters' reading of a plain copy of known size; null when the
-    kernel source has changed since the counters were taken, or when this run's workload or
-    launch configuration (strip width, rows, steps per launch) is not one profiled."""
+def counters_for(workload, tile):
+    """The committed rocprofv3 counters of this kernel source, workload and launch
+    configuration (strip width, rows, steps per launch), or None when the kernel source has
+    changed since they were taken or this configuration is not one profiled."""
     try:
         c = json.load(open(COUNTERS))
     except (OSError, ValueError):
         return None
     if c.get("kernel_src_sha") != kernel_sha() or c.get("workload_key") != workload:
         return None
-    if tile is None:
-        return c.get("hbm_bytes_per_launch")
-    t = c.get("per_tile", {}).get("%d,%d,%d" % tile)
+    return c.get("per_tile", {}).get("%d,%d,%d" % tile)
+
+
+def traffic_from_counters(workload, tile):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counters, each scaled by
+    the same counter's reading of a plain copy of known size; null as in counters_for."""
+    t = counters_for(workload, tile)
     return t.get("hbm_bytes_per_launch") if t else None
 
 
@@ -220,6 +225,13 @@ def main():
                      "launch_ms": kern_ms * tune[3]},
         "status_flags": flags,
     }
+    ctr = counters_for(args.workload, (tune[0], tune[1], tune[3]))
+    if ctr and ctr.get("valu_wave_insts_per_launch"):
+        # the kernel's own bound: VALU instructions per launch (SQ_INSTS_VALU of the committed
+        # counters, fixed by the code and the launch shape) over the measured launch time
+        a = ctr["valu_wave_insts_per_launch"] / (kern_ms * tune[3] * 1e-3)
+        out["roofline"]["alu"] = {"bound": "alu", "achieved": a, "peak": VALU_PEAK_WAVE_INSTS,
+                                  "unit": "wave64 VALU instructions/s", "frac": a / VALU_PEAK_WAVE_INSTS}
     if not args.no_ensemble and args.workload != "ensemble_336":
         # the batched workload: 256 x 128^2 + 64 x 256^2 + 16 x 512^2 replicas in one launch,
         # timed over at least 64 steps (graph replay)

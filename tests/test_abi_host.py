@@ -225,7 +225,7 @@ def test_bench_traffic_is_tied_to_the_profiled_kernel_workload_and_tile(tmp_path
 
 def test_committed_counters_name_their_workload_and_tiles():
     import json
-    c = json.load(open(os.path.join(ROOT, "profiles", "k_step_fp32s_8192_counters.json")))
+    c = json.load(open(os.path.join(ROOT, "profiles", "k_step2_fp32s_8192_counters.json")))
     assert c["workload_key"] == "single_phase_8192" and c["tile"] in c["per_tile"]
     for t, v in c["per_tile"].items():
         w, r, k = (int(s) for s in t.split(","))
