@@ -329,6 +329,13 @@ template <typename R> void fill_consts(Consts<R> &c, const lb_params &q, const d
     c.k44 = (R)(-N[3] * ltb);
     c.k49 = (R)(-12.0 * ltbe);
     c.k99 = (R)(-N[8] * lte);
+    c.k44x2 = (R)(-2.0 * N[3] * ltb);
+    c.k44n3 = (R)(3.0 * N[3] * ltb);
+    c.k49m = (R)(12.0 * ltbe / 3.0);
+    c.k99x125 = (R)(-1.25 * N[8] * lte);
+    c.k99n075 = (R)(0.75 * N[8] * lte);
+    c.c0sq = (R)q.c0sq;
+    c.B3 = (R)(3.0 * q.B);
     c.l55 = (R)sqrt(-N[4] * lts);
     c.l66 = (R)sqrt(-N[5] * lts);
     c.l77 = (R)sqrt(-N[6] * ltq);

@@ -107,22 +107,23 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
 
     unsigned st = 0;
     const R rho = c.rho0 + drho;
-    if (!(rho == rho) || rho - rho != 0) st |= 4u;
+    if (!__builtin_isfinite(rho)) st |= 4u;
     const R irho = frcp<R>(rho);
 
     // local thermodynamics (Sec. II.A): pex = p0 - rho sigma_s^2 relative to its rest value,
     // from the exact Taylor expansion at rho0 in drho
-    const R A = c.A, B = c.B, kap = c.kappa;
+    const R kap = c.kappa;
     const R pex = drho * (c.dp1 + drho * (c.dp2 + drho * (c.dp3 + drho * c.dp4)));
     const R piso = pex - kap * rho * lap;
 
     // Table II (C_n = 0), minus the rest values mbar_4 = 6 pex(rho0), mbar_9 = -6 pex(rho0)
-    const R jj = (jx * jx + jy * jy) * irho;
-    const R g2 = gx * gx + gy * gy;
+    const R jxx = jx * jx, jyy = jy * jy;
+    const R gxx = gx * gx, gyy = gy * gy;
+    const R jj = (jxx + jyy) * irho;
     const R e4 = 3 * jj + 6 * piso;
-    const R e5 = (jx * jx - jy * jy) * irho + kap * (gx * gx - gy * gy);
+    const R e5 = (jxx - jyy) * irho + kap * (gxx - gyy);
     const R e6 = jx * jy * irho + kap * gx * gy;
-    const R e9 = -6 * piso - 3 * kap * g2;
+    const R e9 = -6 * piso - 3 * kap * (gxx + gyy);
 
     // MRT relaxation m* = m + lambda (m - m^eq)
     const R lb = c.lam_b, ls = c.lam_s, lq = c.lam_q, le = c.lam_e;
@@ -135,29 +136,30 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
 
     if (CN && noise == 2) {
         // correlated noise: modes 4 and 9 from the filtered fields, modes 5..8 white at rho0
+        // (normals scaled by sqrt(3 kT rho0))
         R nu[6];
-        normals6<R>(node, rep, t, k0, k1, nu);
+        normals6s<R>(node, rep, t, k0, k1, c.sq0, nu);
         s4 += xi4;
         s9 += xi9;
-        s5 += c.sq0 * c.l55 * nu[1];
-        s6 += c.sq0 * c.l66 * nu[2];
-        s7 += c.sq0 * c.l77 * nu[3];
-        s8 += c.sq0 * c.l88 * nu[4];
+        s5 += c.l55 * nu[1];
+        s6 += c.l66 * nu[2];
+        s7 += c.l77 * nu[3];
+        s8 += c.l88 * nu[4];
     } else if (noise) {
-        // xi = L nu, L L^T = Xi(0) at the local rho and c_s^2 (eq. noise-yeo at k = 0)
-        R nu[6];
-        normals6<R>(node, rep, t, k0, k1, nu);
+        // xi = L nu, L L^T = Xi(0) at the local rho and c_s^2 (eq. noise-yeo at k = 0); the
+        // normals come scaled by sqrt(rho kT / sigma_s^2)
         R rr = rho;
         if (!(rr > 0)) {
             st |= 2u;
             rr = 0;
         }
         const R xx = c.xr0 + (rr - c.rho0);
-        const R cs2 = (c.c0m + (R)(1.0 / 3.0)) + rr * (A + 3 * B * xx * xx);
-        const R sq = fsqrt<R>(rr * c.kT3);
-        const R a44 = c.k44 * (2 - 3 * cs2);
-        const R a49 = c.k49 * (cs2 - (R)(1.0 / 3.0));
-        const R a99 = c.k99 * ((R)1.25 - (R)0.75 * cs2);
+        const R cs2 = c.c0sq + rr * (c.A + c.B3 * (xx * xx));
+        const R a44 = c.k44x2 + c.k44n3 * cs2;        // k44 (2 - 3 c_s^2)
+        const R a49 = c.k49 * cs2 + c.k49m;           // k49 (c_s^2 - 1/3)
+        const R a99 = c.k99x125 + c.k99n075 * cs2;    // k99 (5/4 - 3 c_s^2 / 4)
+        R nu[6];
+        normals6s<R>(node, rep, t, k0, k1, fsqrt<R>(rr * c.kT3), nu);
         R l44 = 0, l94 = 0;
         if (a44 > 0) {
             l44 = fsqrt<R>(a44);
@@ -171,35 +173,45 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
             p99 = 0;
         }
         const R l99 = fsqrt<R>(p99);
-        s4 += sq * l44 * nu[0];
-        s5 += sq * c.l55 * nu[1];
-        s6 += sq * c.l66 * nu[2];
-        s7 += sq * c.l77 * nu[3];
-        s8 += sq * c.l88 * nu[4];
-        s9 += sq * (l94 * nu[0] + l99 * nu[5]);
+        s4 += l44 * nu[0];
+        s5 += c.l55 * nu[1];
+        s6 += c.l66 * nu[2];
+        s7 += c.l77 * nu[3];
+        s8 += c.l88 * nu[4];
+        s9 += l94 * nu[0] + l99 * nu[5];
     }
 
-    // f* = T^-1 m*, (T^-1)_ia = w_i T_ai / N_a, N = (1, 1/3, 1/3, 4, 4/9, 1/9, 2/3, 2/3, 16)
-    const R M1 = drho, M2 = 3 * jx, M3 = 3 * jy;
-    const R M4 = (R)0.25 * s4, M5 = (R)2.25 * s5, M6 = 9 * s6;
-    const R M7 = (R)1.5 * s7, M8 = (R)1.5 * s8, M9 = (R)0.0625 * s9;
-    const R a = (M1 + M4 - 4 * M9) * (R)(1.0 / 9.0);
-    const R bx = (M2 - M7) * (R)(1.0 / 9.0);
-    const R by = (M3 - M8) * (R)(1.0 / 9.0);
-    const R c5 = M5 * (R)(1.0 / 9.0);
-    const R dd = (M1 + 4 * M4 + 8 * M9) * (R)(1.0 / 36.0);
-    const R ex = (M2 + 2 * M7) * (R)(1.0 / 36.0);
-    const R ey = (M3 + 2 * M8) * (R)(1.0 / 36.0);
-    const R g = M6 * (R)(1.0 / 36.0);
-    f[0] = (M1 - 2 * M4 + 2 * M9) * (R)(4.0 / 9.0);
-    f[1] = a + bx + c5;
-    f[2] = a + by - c5;
-    f[3] = a - bx + c5;
-    f[4] = a - by - c5;
-    f[5] = dd + ex + ey + g;
-    f[6] = dd - ex + ey - g;
-    f[7] = dd - ex - ey + g;
-    f[8] = dd + ex - ey - g;
+    // f* = T^-1 m*, (T^-1)_ia = w_i T_ai / N_a with N = (1, 1/3, 1/3, 4, 4/9, 1/9, 2/3, 2/3, 16),
+    // the factors w_i / N_a gathered per term:
+    //   f1,3 = a + c5 +- bx, f2,4 = a - c5 +- by, a = drho/9 + (s4 - s9)/36, c5 = s5/4,
+    //          bx = jx/3 - s7/6, by = jy/3 - s8/6
+    //   f5..8 = dd +- g +- ex +- ey, dd = (drho + s4)/36 + s9/72, g = s6/4,
+    //          ex = (jx + s7)/12 = (jx - 2 bx)/4, ey = (jy - 2 by)/4
+    //   f0 = 4/9 drho - 2/9 s4 + 1/18 s9 = drho - 4 (a + dd)
+    // The last two forms return the conserved moments exactly (sum_i f_i = f0 + 4 a + 4 dd,
+    // sum_i c_ix f_i = 2 bx + 4 ex) up to the rounding of one subtraction; with rounded
+    // constants 1/3, 1/12, 4/9 they would come back scaled by 1 + O(1e-8) every step, a drift of
+    // mass and momentum that grows linearly with time in FP32.
+    const R aa = drho * (R)(1.0 / 9.0) + (s4 - s9) * (R)(1.0 / 36.0);
+    const R c5 = s5 * (R)0.25;
+    const R bx = jx * (R)(1.0 / 3.0) + s7 * (R)(-1.0 / 6.0);
+    const R by = jy * (R)(1.0 / 3.0) + s8 * (R)(-1.0 / 6.0);
+    const R dd = (drho + s4) * (R)(1.0 / 36.0) + s9 * (R)(1.0 / 72.0);
+    const R g = s6 * (R)0.25;
+    const R ex = (jx - 2 * bx) * (R)0.25;
+    const R ey = (jy - 2 * by) * (R)0.25;
+    const R ap = aa + c5, am = aa - c5;
+    const R dp = dd + g, dm = dd - g;
+    const R u = ex + ey, v = ex - ey;
+    f[0] = drho - 4 * (aa + dd);
+    f[1] = ap + bx;
+    f[2] = am + by;
+    f[3] = ap - bx;
+    f[4] = am - by;
+    f[5] = dp + u;
+    f[6] = dm - v;
+    f[7] = dp - u;
+    f[8] = dm + v;
     return st;
 }
 

@@ -24,6 +24,8 @@ template <typename R> struct Consts {
     R kT3;           // 3 kT = rho kT / sigma_s^2 per unit density
     R k44, k49, k99; // Xi(0)/(3 rho kT): (4,4) = k44 (2 - 3 c_s^2), (4,9) = k49 (c_s^2 - 1/3),
                      // (9,9) = k99 (5/4 - 3 c_s^2 / 4)
+    R k44x2, k44n3, k49m, k99x125, k99n075;   // 2 k44, -3 k44, -k49/3, 5/4 k99, -3/4 k99
+    R c0sq, B3;      // c0sq, 3 B: c_s^2 = c0sq + rho (A + 3 B x^2)
     R l55, l66, l77, l88;   // sqrt of Xi(0)_aa / (3 rho kT), a = 5..8
     R sq0;           // sqrt(3 kT rho0): noise scale of the homogeneous state (correlated noise)
     R cs2_0;         // c_s^2(rho0)

@@ -77,6 +77,42 @@ template <> struct Gauss<double> {
     }
 };
 
+// Box-Muller with the radius scaled: scale * (the pair above)
+template <typename R> __device__ __forceinline__ void gauss_pair_scaled(uint32_t be, uint32_t bo, R scale, R &a, R &b);
+template <> __device__ __forceinline__ void gauss_pair_scaled<float>(uint32_t be, uint32_t bo, float scale, float &a, float &b)
+{
+#pragma clang fp contract(on)
+    const float ue = ((float)be + 0.5f) * 0x1p-21f;
+    const float uo = ((float)bo + 0.5f) * 0x1p-21f;
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ue)) * scale;
+    a = r * __builtin_amdgcn_cosf(uo);
+    b = r * __builtin_amdgcn_sinf(uo);
+}
+template <> __device__ __forceinline__ void gauss_pair_scaled<double>(uint32_t be, uint32_t bo, double scale, double &a, double &b)
+{
+#pragma clang fp contract(on)
+    const double ue = ((double)be + 0.5) * 0x1p-21;
+    const double uo = ((double)bo + 0.5) * 0x1p-21;
+    const double r = sqrt(-2.0 * log(ue)) * scale;
+    double s, c;
+    sincospi(2.0 * uo, &s, &c);
+    a = r * c;
+    b = r * s;
+}
+
+// the six normals of (node, rep, t), each multiplied by `scale`
+template <typename R>
+__device__ __forceinline__ void normals6s(uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
+                                          uint32_t k1, R scale, R nu[6])
+{
+    const uint4 x = philox10(make_uint4(node, rep, (uint32_t)t, (uint32_t)(t >> 32)), k0, k1);
+    uint32_t b[6];
+    bits21(x, b);
+    gauss_pair_scaled<R>(b[0], b[1], scale, nu[0], nu[1]);
+    gauss_pair_scaled<R>(b[2], b[3], scale, nu[2], nu[3]);
+    gauss_pair_scaled<R>(b[4], b[5], scale, nu[4], nu[5]);
+}
+
 template <typename R>
 __device__ __forceinline__ void normals6(uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
                                          uint32_t k1, R nu[6])

@@ -12,14 +12,14 @@ Tolerances, derived from the arithmetic of each side:
   noise-free runs: the required 1e-5, relative to the fluctuation,
   err_a = max_r |m_a^gpu - m_a^oracle| / max_r |m_a^oracle - mean(m_a^oracle)|, for rho, j_x,
   j_y: single-phase waves, the two-phase slab's density and the spinodal quench (measured
-  1e-6 to 4e-6).  One derived floor remains: a 0.02 uniform flow carries populations
-  ~0.02 w_i away from rest, whose FP32 rounding (~1e-9) is ~1e-3 of the 1e-4 wave riding on
-  j_x (measured 2.1e-3; gate 6e-3).
+  3e-7 to 1.4e-6).  One derived floor remains: a 0.02 uniform flow carries populations
+  ~0.02 w_i away from rest, whose FP32 rounding (~1e-9) is ~1e-4 of the 1e-4 wave riding on
+  j_x (measured 2.0e-4; gate 6e-4).
 * Noisy runs in FP32: the single-precision Box-Muller (hardware log2/sin/cos) differs from
   the FP64 normals by <= 3e-6 per draw, which the trajectories integrate; every case is
   deterministic (same seeds, same bits run after run), so each gate is about 3x the error
-  measured for its case (single phase ~2e-7 to 6e-7; the two-phase slab, whose bulk phases
-  hold O(0.5) deviations from rest, 5.7e-5).
+  measured for its case (single phase 1.8e-7 to 2.5e-7; the two-phase slab, whose bulk phases
+  hold O(0.5) deviations from rest, 8.9e-6).
 * Integer work (Philox) is compared bit for bit.
 """
 import os
@@ -145,7 +145,7 @@ DET = [
     ("wave_ragged", lambda: W.wave(W.single_phase(100, 37, kT=0, tau_bulk=0.7, tau_q=0.9), 3, 2, 1e-4, 1e-4, 0),
      100, 1e-5),
     ("tiny", lambda: W.wave(W.single_phase(3, 5, kT=0), 1, 1, 1e-4, 1e-4, 0), 4, 1e-5),
-    ("flow", lambda: W.wave(W.single_phase(96, 64, kT=0), 2, 1, 1e-4, 0, 1e-4, U=0.02), 300, 6e-3),
+    ("flow", lambda: W.wave(W.single_phase(96, 64, kT=0), 2, 1, 1e-4, 0, 1e-4, U=0.02), 300, 6e-4),
     ("slab", lambda: W.slab(64, 128, kT=0), 500, 1e-5),
     ("spinodal", lambda: W.spinodal(128, 96, kT=0, amp=0.01, seed=2), 300, 1e-5),
 ]
@@ -185,9 +185,9 @@ NOISY = [
     # label, config, steps, FP32-shifted gate (all nine modes; ~3x the measured error)
     ("single_phase_64", lambda: W.single_phase_64(), 2000, 6e-7),
     ("ragged", lambda: W.single_phase(72, 50, kT=1e-5, seed=17, replica=3), 500, 6e-7),
-    ("tiny", lambda: W.single_phase(3, 5, kT=1e-5, seed=2), 300, 1.5e-6),
-    ("slab", lambda: W.slab(64, 128, kT=1e-6, seed=5), 500, 1.5e-4),
-    ("uncorrelated_sec5a", lambda: W.uncorrelated_sec5a(64, 64, kT=1e-7), 500, 9e-7),
+    ("tiny", lambda: W.single_phase(3, 5, kT=1e-5, seed=2), 300, 8e-7),
+    ("slab", lambda: W.slab(64, 128, kT=1e-6, seed=5), 500, 3e-5),
+    ("uncorrelated_sec5a", lambda: W.uncorrelated_sec5a(64, 64, kT=1e-7), 500, 8e-7),
     ("diagonal", lambda: W.single_phase(64, 48, kT=1e-5, seed=9, c0sq=0.0, A=0.05, noise="diagonal"), 400, 7e-7),
 ]
 
@@ -858,11 +858,12 @@ def test_full_size_two_phase_workloads_sampled(name):
 def test_slab_2048_at_its_length_fp32s_against_fp64():
     """The two-phase slab workload as stated (2048^2, kT = 1e-6, 10,000 steps) in FP32-shifted,
     plain FP32 and FP64 storage on the GPU (FP64 being pinned to the oracle at 2e-12): the
-    FP32-shifted moments against FP64 after the full run (measured 1.7e-4 of the density range,
-    2.5e-5 of j_x's, 6.9e-4 of the small cross-interface j_y's; plain FP32 6.9e-3 for the
-    density), and the physics of Sec. II.A on the FP64 run: bulk densities 1 +- sqrt(-A/B) =
-    1.5 / 0.5 within 2e-3, the x-averaged lower wall a tanh of half-width sqrt(-2 kappa / A) = 2
-    (eq. interf-width) within 5%."""
+    FP32-shifted moments against FP64 after the full run within 1.2e-4 of each moment's range
+    (measured 4.0e-5 for the density, 8e-6 for j_x and j_y; plain FP32 the same, 4.0e-5: after
+    10k noisy steps the FP32 normals, not the storage, set the error), and the physics of
+    Sec. II.A on the FP64 run: bulk densities 1 +- sqrt(-A/B) = 1.5 / 0.5 within 2e-3, the
+    x-averaged lower wall a tanh of half-width sqrt(-2 kappa / A) = 2 (eq. interf-width) within
+    5%."""
     from scipy.optimize import curve_fit
     L = _L()
     cfg = W.slab_2048()
@@ -881,7 +882,7 @@ def test_slab_2048_at_its_length_fp32s_against_fp64():
     e32s = [np.abs(res["fp32s"][a] - ref[a]).max() / rng_[a] for a in range(3)]
     e32 = [np.abs(res["fp32"][a] - ref[a]).max() / rng_[a] for a in range(3)]
     say("slab_2048 10k steps: fp32s err / range", e32s, "plain fp32", e32)
-    assert max(e32s) < 2e-3 and e32s[0] < 5e-4 and e32s[0] < e32[0] / 10
+    assert max(e32s) < 1.2e-4 and max(e32) < 1e-3
     rho = ref[0].mean(axis=1)
     ny = rho.size
     liquid, vapour = rho[ny // 2 - 50: ny // 2 + 50].mean(), np.r_[rho[:50], rho[-50:]].mean()
@@ -1172,7 +1173,7 @@ def test_capillary_full_size_and_cropped_parity():
     FP32-shifted storage.  Gates: FP64 the absolute gate of the parity tests; FP32-shifted
     relative to the fluctuation range, ~3x the measured error (the vapour holds deviations of
     0.5 from the rest state rho0 = 1, as in the slab)."""
-    for cfg, steps, tol32 in ((W.capillary(), 2, 6e-5), (W.capillary(256, 120, width=50, seed=9), 400, 3.5e-4)):
+    for cfg, steps, tol32 in ((W.capillary(), 2, 6e-5), (W.capillary(256, 120, width=50, seed=9), 400, 9e-5)):
         for precision in (0, 2):
             mg, mo = run_pair(cfg, precision, steps)
             if precision == 0:
