@@ -851,16 +851,16 @@ lb_status lb_init(const lb_params *p, int32_t n_rep, int32_t precision, uint32_t
         return LB_EDEVICE;
     }
     if (e == hipSuccess && !h->cn_reps.empty()) {
-        int max_nx = 0, max_cp = 0;
+        int max_nx = 0, max_ny = 0;
         for (int r : h->cn_reps) {
             const RepDesc &d = h->reps[r];
             max_nx = std::max(max_nx, d.nx);
-            max_cp = std::max(max_cp, cn_col_points(d.nx, d.ny));
+            max_ny = std::max(max_ny, d.ny);
             double *tw = h->cn_tw + 2 * d.tw_off;
             if (e == hipSuccess) e = launch_twiddles(tw, d.nx, h->stream);
             if (e == hipSuccess) e = launch_twiddles(tw + 2 * (d.nx / 2), d.ny, h->stream);
         }
-        if (e == hipSuccess) e = set_fft_lds_limit(max_nx, max_cp);
+        if (e == hipSuccess) e = set_fft_lds_limit(max_nx, max_ny);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) {
             delete h;

@@ -160,9 +160,8 @@ hipError_t launch_twiddles(double *tw, int n, hipStream_t s);
 hipError_t launch_correlated_noise(int precision, const RepDesc *d_reps, const RepDesc &h_rep, int rep_index,
                                    double *work, const double *tw_base, void *xi_base,
                                    const unsigned long long *tdev, int toff, hipStream_t s);
-// LDS limits of the correlated-noise kernels: widest row, most column points per block
-hipError_t set_fft_lds_limit(int max_nx, int max_col_points);
-int cn_col_points(int nx, int ny);
+// LDS limits of the correlated-noise kernels for replicas up to max_nx x max_ny
+hipError_t set_fft_lds_limit(int max_nx, int max_ny);
 
 // structure factor (lb_sk.hip).  Replicas are sampled together: every pass covers a range
 // [r0, r1) of replicas with one launch per kernel, whatever their sizes.

@@ -1087,6 +1087,28 @@ def test_correlated_noise_parity_long_lines(precision, shape):
         assert e.max() < 9e-7
 
 
+CN_SMALL = [(4, 64, 6), (64, 4, 6), (4, 4, 8), (8, 2048, 3)]
+
+
+@pytest.mark.parametrize("shape", CN_SMALL, ids=[f"{a}x{b}" for a, b, _ in CN_SMALL])
+@pytest.mark.parametrize("precision", [2, 0])
+def test_correlated_noise_parity_narrow_sides(precision, shape):
+    """The filter's edge shapes: the smallest sides (4), a lattice whose mirror-pair columns
+    all fit one drawing block (4 x 64), rows of a 4-row chunk (64 x 4), and 2048-point
+    columns of a narrow lattice, against the oracle as above (same gates)."""
+    nx, ny, steps = shape
+    cfg = dict(W.single_phase_8192(), nx=nx, ny=ny, noise="correlated", seed=23)
+    mg, mo = run_pair(cfg, precision, steps, chunks=1)
+    e = rel_err(mg, mo)
+    if precision == 0:
+        ok, err = abs_ok(mg, mo)
+        say("correlated", nx, ny, "fp64 abs err", err.max(), "normalised", e.max())
+        assert ok
+    else:
+        say("correlated", nx, ny, "fp32s err", e)
+        assert e.max() < 9e-7
+
+
 def test_correlated_and_uncorrelated_replicas_in_one_handle():
     L = _L()
     cfgs = [W.correlated_sec5a(32, 32, kT=1e-6, seed=1), W.uncorrelated_sec5a(48, 40, kT=1e-7, seed=2),
