@@ -241,7 +241,7 @@ Layout make_layout(const lb_params *p, int32_t n_rep, int32_t precision, uint32_
         L.sk_base = o; o += align_up(sizeof(double) * 18 * (size_t)n_rep);
     }
     if (L.cn_nodes > 0) {
-        L.xi = o; o += align_up((size_t)2 * L.cn_nodes * elem_size(precision));
+        L.xi = o; o += align_up((size_t)4 * L.cn_nodes * elem_size(precision));   // planes of steps t, t + 1
         L.cn_a = o; o += align_up(sizeof(double) * 2 * (size_t)L.cn_max_n);
         L.cn_tw = o; o += align_up(sizeof(double) * 2 * (size_t)L.cn_tw_elems);
     }
@@ -441,10 +441,21 @@ lb_status set_tiles2(lb_handle *h, int bx, double rows)
     return LB_OK;
 }
 
-// two steps (times t + toff, t + toff + 1) from buffer par into buffer par ^ 1
+// two steps (times t + toff, t + toff + 1) from buffer par into buffer par ^ 1; the correlated
+// noise of both steps first, in planes 0 and 1 of the xi buffer
 hipError_t step_pair(lb_handle *h, int par, int toff, hipStream_t s)
 {
+    const int64_t plane = 2 * h->L.cn_nodes;
+    for (int j = 0; j < 2; ++j)
+        for (int r : h->cn_reps) {
+            void *xi = (char *)h->xi + (size_t)j * plane * elem_size(h->precision);
+            hipError_t e = launch_correlated_noise(h->precision, h->reps_d, h->reps[r], r, h->cn_a, h->cn_tw, xi,
+                                                   h->tdev, toff + j, s);
+            if (e != hipSuccess) return e;
+        }
     Step2Launch a;
+    a.xi = h->cn_reps.empty() ? nullptr : h->xi;
+    a.xi_plane = plane;
     a.fin = h->fbuf[par];
     a.fout = h->fbuf[par ^ 1];
     a.reps = h->reps_d;
@@ -562,13 +573,11 @@ lb_status autotune(lb_handle *h)
     };
     int force_k = 0;
     if (const char *e = getenv("LBF_STEPS_PER_LAUNCH")) force_k = atoi(e) == 2 ? 2 : (atoi(e) == 1 ? 1 : 0);
-    const bool cn = !h->cn_reps.empty();   // correlated noise: one step per launch only
     int pbx = 0, pbx2 = 0;
     double prows = 0, prows2 = 0;
     const bool pin1 = pinned("LBF_TILE", MIN_BX, MIN_H, &pbx, &prows);
     const bool pin2 = pinned("LBF_TILE2", STEP2_MIN_BX, STEP2_MIN_H, &pbx2, &prows2);
     if (!force_k) force_k = pin1 && !pin2 ? 1 : (pin2 && !pin1 ? 2 : 0);
-    if (cn) force_k = 1;
 
     int bx0 = 256;
     while (bx0 > MIN_BX && bx0 / 2 >= min_nx) bx0 /= 2;

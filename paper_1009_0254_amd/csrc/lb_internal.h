@@ -115,6 +115,8 @@ std::vector<Tile> make_tiles(const std::vector<RepDesc> &reps, int bx, double h)
 // replica whose row fits a group (nx <= bx / G) has x0 = 0 and whole-row tiles; rep < 0
 // marks an empty group.
 struct Step2Launch {
+    const void *xi;       // correlated noise of step t (plane 0) and t + 1 (at xi_plane), or null
+    int64_t xi_plane;     // elements of the storage type between the two planes
     const void *fin;
     void *fout;
     const RepDesc *reps;

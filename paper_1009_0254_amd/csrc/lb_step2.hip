@@ -48,8 +48,11 @@ template <typename S, typename R> constexpr unsigned step2_group_bytes(unsigned 
     return W * (6 * (unsigned)sizeof(R) + 24 * (unsigned)sizeof(S));
 }
 
-template <typename S, typename R, bool PLAIN>
-__global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__restrict__ fout,
+// CN: the replica set has correlated noise; replicas with noise == 2 add the fields of step t
+// (xi) and t + 1 (xi + xi_plane) to modes 4 and 9 (see k_step).
+template <typename S, typename R, bool PLAIN, bool CN>
+__global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long long xi_plane,
+                                               const S *__restrict__ fin, S *__restrict__ fout,
                                                const RepDesc *__restrict__ reps, const Tile *__restrict__ tiles,
                                                const int32_t *__restrict__ wgs,
                                                const unsigned long long *__restrict__ tdev,
@@ -231,8 +234,14 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__r
                 for (int i = 0; i < Q; ++i) g[i] -= c.sub[i];
             }
             const unsigned y = (unsigned)(r - 3);   // inside [y0, y1): no wrap
-            const unsigned s2 = collide<R, false>(g, lap, gx, gy, c, d.noise, y * nx + xw, d.rep_id, t + 1,
-                                                  d.seed_lo, d.seed_hi, (R)0, (R)0);
+            R xi4 = 0, xi9 = 0;
+            if (CN && d.noise == 2) {
+                const S *__restrict__ xr = xi + xi_plane + 2 * (d.xi_off + (long long)y * nx + xw);
+                xi4 = (R)xr[0];
+                xi9 = (R)xr[1];
+            }
+            const unsigned s2 = collide<R, CN>(g, lap, gx, gy, c, d.noise, y * nx + xw, d.rep_id, t + 1, d.seed_lo,
+                                               d.seed_hi, xi4, xi9);
             const auto Wr = row_rsrc(Qo + (unsigned long long)y * pitch, rowb);
             if (store2) {
                 st |= s2;
@@ -252,8 +261,14 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__r
                 for (int i = 0; i < Q; ++i) cur[i] -= c.sub[i];
             }
             const unsigned yr = wrapy(r);
-            const unsigned s1f = collide<R, false>(cur, lap, gx, gy, c, d.noise, yr * nx + xw, d.rep_id, t,
-                                                   d.seed_lo, d.seed_hi, (R)0, (R)0);
+            R xi4 = 0, xi9 = 0;
+            if (CN && d.noise == 2) {
+                const S *__restrict__ xr = xi + 2 * (d.xi_off + (long long)yr * nx + xw);
+                xi4 = (R)xr[0];
+                xi9 = (R)xr[1];
+            }
+            const unsigned s1f = collide<R, CN>(cur, lap, gx, gy, c, d.noise, yr * nx + xw, d.rep_id, t, d.seed_lo,
+                                                d.seed_hi, xi4, xi9);
             st |= s1f;
             S o[Q];
 #pragma unroll
@@ -286,25 +301,31 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ fin, S *__r
     if (st && store2) atomicOr(flags, st);
 }
 
-template <typename S, typename R, bool PLAIN> static void launch_step2_t(const Step2Launch &a, hipStream_t s)
+template <typename S, typename R, bool PLAIN, bool CN> static void launch_step2_t(const Step2Launch &a, hipStream_t s)
 {
     const size_t lds = (size_t)a.max_groups * step2_group_bytes<S, R>((unsigned)(a.bx / a.max_groups + 2));
-    hipLaunchKernelGGL((k_step2<S, R, PLAIN>), dim3(a.nwg), dim3(a.bx), lds, s, (const S *)a.fin, (S *)a.fout, a.reps,
-                       a.tiles, a.wgs, a.tdev, a.flags, a.toff);
+    hipLaunchKernelGGL((k_step2<S, R, PLAIN, CN>), dim3(a.nwg), dim3(a.bx), lds, s, (const S *)a.xi,
+                       (long long)a.xi_plane, (const S *)a.fin, (S *)a.fout, a.reps, a.tiles, a.wgs, a.tdev, a.flags,
+                       a.toff);
+}
+
+template <typename S, typename R, bool PLAIN> static hipError_t set_step2_limit(int bytes)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)k_step2<S, R, PLAIN, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_step2<S, R, PLAIN, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                bytes);
+    return e;
 }
 
 hipError_t set_step2_lds_limit()
 {
     const int fp32 = (int)(8 * step2_group_bytes<float, float>(512 / 8 + 2));
     const int fp64 = (int)(8 * step2_group_bytes<double, double>(512 / 8 + 2));
-    hipError_t e = hipFuncSetAttribute((const void *)k_step2<double, double, false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, fp64);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_step2<float, float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                fp32);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_step2<float, float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                fp32);
+    hipError_t e = set_step2_limit<double, double, false>(fp64);
+    if (e == hipSuccess) e = set_step2_limit<float, float, false>(fp32);
+    if (e == hipSuccess) e = set_step2_limit<float, float, true>(fp32);
     return e;
 }
 
@@ -314,14 +335,22 @@ size_t step2_lds_bytes(int precision, int bx, int max_groups)
     return (size_t)max_groups * (precision == 0 ? step2_group_bytes<double, double>(W) : step2_group_bytes<float, float>(W));
 }
 
+template <typename S, typename R, bool PLAIN> static void launch_step2_cn(const Step2Launch &a, hipStream_t s)
+{
+    if (a.xi)
+        launch_step2_t<S, R, PLAIN, true>(a, s);
+    else
+        launch_step2_t<S, R, PLAIN, false>(a, s);
+}
+
 hipError_t launch_step2(int precision, const Step2Launch &a, hipStream_t s)
 {
     if (precision == 0)
-        launch_step2_t<double, double, false>(a, s);
+        launch_step2_cn<double, double, false>(a, s);
     else if (a.plain)
-        launch_step2_t<float, float, true>(a, s);
+        launch_step2_cn<float, float, true>(a, s);
     else
-        launch_step2_t<float, float, false>(a, s);
+        launch_step2_cn<float, float, false>(a, s);
     return hipGetLastError();
 }
 

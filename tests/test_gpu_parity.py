@@ -312,6 +312,9 @@ TWO_STEP_CASES = [
                W.wave(W.single_phase(3, 9, kT=0), 1, 1, 1e-4, 0, 1e-4),
                W.slab(40, 64, kT=1e-6, seed=25, replica=5)]),
     ("tiny", [W.single_phase(3, 5, kT=1e-5, seed=2)]),
+    ("correlated", [dict(W.correlated_sec5a(64, 32, kT=1e-6, seed=31), replica=0),
+                    W.single_phase(100, 36, kT=1e-5, seed=32, replica=1),
+                    dict(W.correlated_sec5a(512, 16, kT=1e-6, seed=33), replica=2)]),
 ]
 
 
@@ -321,8 +324,10 @@ def test_two_steps_per_launch_bitwise(monkeypatch, label, cfgs, precision):
     """The two-steps-per-launch kernel gives the bits of the one-step kernel, for every
     workgroup width and tile height: overlapping strips (a ragged last strip, tile heights
     that do not divide ny), whole rows packed 2 to 8 per workgroup with empty groups, a
-    3 x 5 lattice whose tile wraps its rows twice, all three storages; odd step counts end
-    with a one-step launch, 64 steps replay the captured graph.  Flags and time agree too."""
+    3 x 5 lattice whose tile wraps its rows twice, replicas with the exact Xi(k) noise (both
+    steps' fields made before the launch) beside a k = 0 one, all three storages; odd step
+    counts end with a one-step launch, 64 steps replay the captured graph.  Flags and time
+    agree too."""
     L = _L()
     def run(env):
         for k in ("LBF_TILE", "LBF_TILE2", "LBF_STEPS_PER_LAUNCH"):
