@@ -48,7 +48,7 @@ __global__ void k_fill(double *p, long long n, double v)
 
 constexpr int CN_THREADS = 1024;
 constexpr int CN_COL_POINTS = 4096;   // points per drawing block when columns are short
-constexpr int CN_LDS_POINT_BYTES = 131072;   // largest transform batch of one block, in bytes
+constexpr int CN_LDS_POINT_BYTES = 131072;   // largest transform batch of one block, in bytes (before its 1/16 pad)
 
 int cn_threads(int points) { return points >= 4096 ? 1024 : 256; }
 
@@ -211,26 +211,28 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_gen(void *__restrict__ Av, co
     const int first = (int)lb * per;
     const unsigned long long t = tdev[0] + (unsigned long long)toff;
     tw_cache_load(T, twy, ny);
-    const int sh = lds_pad_shift(logny);
+    // 1/16-pad layout, filled in destination order: lane e writes slot e of the bit-reversed
+    // column (its ky is bitrev(e)), radix-16 passes with the remainder last
+    const int sh = LDS_PAD16;
     const int cols = PAIRED ? 2 * per : per;
     if (PAIRED) {
         const int hy = ny >> 1;
         for (int e = threadIdx.x; e < (per << logny); e += blockDim.x) {
-            const int i = e >> logny, j = e & (ny - 1), p = first + i;
+            const int i = e >> logny, r = e & (ny - 1), p = first + i;
             const int s0 = (2 * i) << logny, s1 = (2 * i + 1) << logny;
             if (p > 0) {
-                // k = (p, j) and -k = (nx - p, ny - j mod ny)
-                const int my = (ny - j) & (ny - 1);
+                // k = (p, j) and -k = (nx - p, ny - j mod ny), j = bitrev(r)
+                const int j = (int)bitrev((unsigned)r, logny), my = (ny - j) & (ny - 1);
                 const uint32_t idx = (uint32_t)j * nx + p, midx = (uint32_t)my * nx + (nx - p);
                 const Chol49<R> L = cn_chol<R>(d, c, p, j);
                 C zk, zmk;
                 cn_pair<R>(d, L, idx < midx ? idx : midx, idx < midx ? (R)1 : (R)-1, t, zk, zmk);
-                X[lds_at(s0 + bitrev((unsigned)j, logny), sh)] = zk;
+                X[lds_at(s0 + r, sh)] = zk;
                 X[lds_at(s1 + bitrev((unsigned)my, logny), sh)] = zmk;
             } else {
-                // columns 0 (slot 0, threads j < ny/2) and nx/2 (slot 1): each column is its own
+                // columns 0 (slot 0, threads r < ny/2) and nx/2 (slot 1): each column is its own
                 // mirror; thread q > 0 takes ky = q and ny - q, thread 0 the real ky = 0, ny/2
-                const int kx = j < hy ? 0 : half, sb = j < hy ? s0 : s1, q = j & (hy - 1);
+                const int kx = r < hy ? 0 : half, sb = r < hy ? s0 : s1, q = r & (hy - 1);
                 if (q > 0) {
                     const Chol49<R> L = cn_chol<R>(d, c, kx, q);
                     C zk, zmk;
@@ -246,12 +248,12 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_gen(void *__restrict__ Av, co
         }
     } else {
         for (int e = threadIdx.x; e < (cols << logny); e += blockDim.x) {
-            const int cc = e >> logny, ky = e & (ny - 1);
-            X[lds_at((cc << logny) + bitrev((unsigned)ky, logny), sh)] = cn_z<R>(d, c, first + cc, ky, t);
+            const int cc = e >> logny, ky = (int)bitrev((unsigned)(e & (ny - 1)), logny);
+            X[lds_at(e, sh)] = cn_z<R>(d, c, first + cc, ky, t);
         }
     }
     __syncthreads();
-    fft_lds<false, R>(X, ny, logny, cols, T, ny);
+    fft_lds<false, R, 4, true>(X, ny, logny, cols, T, ny, sh);
     C *A = reinterpret_cast<C *>(Av);
     const int lch = cn_chunk_log(logny);
     for (int e = threadIdx.x; e < (cols << logny); e += blockDim.x) {
@@ -289,13 +291,14 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_out(const void *__restrict__ 
     if (lr < 0) return;
     const int y0 = (int)lr * ROWS;
     tw_cache_load(T, twx, nx);
-    const int sh = lds_pad_shift(lognx), lch = cn_chunk_log(d.logny);
+    const int sh = LDS_PAD16, lch = cn_chunk_log(d.logny);
     const C *src = A + cn_a_at(0, y0, nx, lch);   // element kx of row y0 + r at src[(kx << lch) + r]
+    // destination order: lane e fills slot e of each row's bit-reversed transform from kx = bitrev(e)
     for (int k0 = threadIdx.x; k0 < nx; k0 += U * blockDim.x) {
         C v[U][ROWS];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const long long kx = min(k0 + u * (int)blockDim.x, nx - 1);
+            const long long kx = bitrev((unsigned)min(k0 + u * (int)blockDim.x, nx - 1), lognx);
             if constexpr (ROWS == 2) {
                 const Q q = *reinterpret_cast<const Q *>(src + (kx << lch));
                 v[u][0] = mk2(q.x, q.y);
@@ -306,14 +309,14 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_out(const void *__restrict__ 
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int kx = k0 + u * (int)blockDim.x;
-            if (kx < nx)
+            const int e = k0 + u * (int)blockDim.x;
+            if (e < nx)
 #pragma unroll
-                for (int r = 0; r < ROWS; ++r) X[lds_at((r << lognx) + bitrev((unsigned)kx, lognx), sh)] = v[u][r];
+                for (int r = 0; r < ROWS; ++r) X[lds_at((r << lognx) + e, sh)] = v[u][r];
         }
     }
     __syncthreads();
-    fft_lds<false, S>(X, nx, lognx, ROWS, T, nx);
+    fft_lds<false, S, 4, true>(X, nx, lognx, ROWS, T, nx, sh);
     const S s = (S)rsqrt((double)nx * (double)ny);
     C *out = reinterpret_cast<C *>(xi + 2 * d.xi_off) + (long long)y0 * nx;
     for (int e = threadIdx.x; e < ROWS * nx; e += blockDim.x) {
@@ -326,8 +329,8 @@ template <typename R> static hipError_t set_cn_limits(int max_nx, int max_ny)
 {
     typedef typename V2<R>::type C;
     const CnGen g = cn_gen_shape(max_nx, max_ny, sizeof(C));
-    const int gb = (int)(sizeof(C) * lds_padded(g.points));
-    const int ob = (int)(sizeof(C) * lds_padded((long long)cn_out_rows(max_nx, sizeof(C)) * max_nx));
+    const int gb = (int)(sizeof(C) * lds_padded16(g.points));
+    const int ob = (int)(sizeof(C) * lds_padded16((long long)cn_out_rows(max_nx, sizeof(C)) * max_nx));
     hipError_t e = hipFuncSetAttribute((const void *)k_cn_gen<R, true>, hipFuncAttributeMaxDynamicSharedMemorySize, gb);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_cn_gen<R, false>, hipFuncAttributeMaxDynamicSharedMemorySize, gb);
@@ -351,7 +354,7 @@ static void launch_cn_t(const RepDesc *d_reps, const RepDesc &h, int rep_index, 
 {
     typedef typename V2<R>::type C;
     const CnGen g = cn_gen_shape(h.nx, h.ny, sizeof(C));
-    const size_t gb = sizeof(C) * lds_padded(g.points);
+    const size_t gb = sizeof(C) * lds_padded16(g.points);
     if (g.paired)
         hipLaunchKernelGGL((k_cn_gen<R, true>), dim3(xcd_grid(g.blocks)), dim3(cn_threads(g.points)), gb,
                            s, (void *)work, d_reps, rep_index, g.per_block, g.blocks, twy, tdev, toff);
@@ -359,7 +362,7 @@ static void launch_cn_t(const RepDesc *d_reps, const RepDesc &h, int rep_index, 
         hipLaunchKernelGGL((k_cn_gen<R, false>), dim3(xcd_grid(g.blocks)), dim3(cn_threads(g.points)),
                            gb, s, (void *)work, d_reps, rep_index, g.per_block, g.blocks, twy, tdev, toff);
     const int rows = cn_out_rows(h.nx, sizeof(C));
-    const size_t ob = sizeof(C) * lds_padded((long long)rows * h.nx);
+    const size_t ob = sizeof(C) * lds_padded16((long long)rows * h.nx);
     if (rows == 2)
         hipLaunchKernelGGL((k_cn_out<R, 2>), dim3(xcd_grid(h.ny / 2)), dim3(cn_threads(2 * h.nx)), ob, s,
                            (const void *)work, xi, d_reps, rep_index, twx);

@@ -39,14 +39,22 @@ inline unsigned xcd_grid(long long total) { return (unsigned)(((total + 7) >> 3)
 
 constexpr int TW_LO = 64, TW_HI = 128;   // N <= 2 * 64 * 128 = 16384
 
-// LDS layout of a batch of length-n transforms: element i sits at lds_at(i, sh) = i + (i >> sh)
-// with sh = lds_pad_shift(log2 n), one pad slot after every 2^sh elements.  The bit-reversed
-// fill sends the 64 lanes of a wave to elements n / 64 apart, which without the pad share one
-// LDS bank; with it they fall into distinct banks.
+// LDS layout of a batch of length-n transforms: element i sits at lds_at(i, sh) = i + (i >> sh),
+// one pad slot after every 2^sh elements.  Two periods are used:
+//   sh = lds_pad_shift(log2 n) = max(log2 n - 6, 5): the bit-reversed fill by consecutive source
+//     index sends the lanes of a wave to elements n / 64 apart, which the pad spreads over the
+//     banks (the register-fed fill of the structure factor's rows);
+//   sh = LDS_PAD16 = 4: for radix-16 passes with the remainder pass last (fft_lds REM_LAST) a
+//     lane's 16 elements, or 16 lanes' elements of one stride, fall in 16 distinct bank pairs
+//     (8-byte elements) in every pass, provided the bit-reversed fill goes in destination order
+//     (lane e writes slot e, reading its source at bitrev(e)).
 __host__ __device__ constexpr int lds_pad_shift(int logn) { return logn - 6 > 5 ? logn - 6 : 5; }
+constexpr int LDS_PAD16 = 4;
 __device__ __forceinline__ int lds_at(int i, int sh) { return i + (i >> sh); }
 // LDS elements that hold `total` elements of transforms of any length (pad at most 1/32)
 constexpr long long lds_padded(long long total) { return total + (total >> 5) + 1; }
+// the same for the 1/16 pad
+constexpr long long lds_padded16(long long total) { return total + (total >> 4) + 1; }
 
 template <typename T> struct TwCacheT {
     typedef typename V2<T>::type C;
@@ -139,14 +147,16 @@ __device__ __forceinline__ void fft_pass(typename V2<T>::type *X, int logn, int 
     constexpr int R = 1 << RL;
     const int lq = s - 1, q = 1 << lq;
     const int groups = (count << logn) >> RL, gmask = (1 << (logn - RL)) - 1;
-    const bool uniform = lq >= sh;
-    const int stride = q + (q >> sh);
+    // a lane's elements sit a uniform stride apart when q is a multiple of the pad period, or
+    // when all R of them lie inside one aligned block of 2^(lq + RL) <= 2^sh elements
+    const bool wide = lq >= sh, narrow = lq + RL <= sh;
+    const int stride = wide ? q + (q >> sh) : q;
     for (int b = threadIdx.x; b < groups; b += blockDim.x) {
         const int g = b >> (logn - RL), bb = b & gmask;
         const int pos = bb & (q - 1);
         const int base = (g << logn) + ((bb >> lq) << (lq + RL)) + pos;
         C x[R];
-        if (uniform) {
+        if (wide || narrow) {
             const int a0 = lds_at(base, sh);
 #pragma unroll
             for (int j = 0; j < R; ++j) x[j] = X[a0 + j * stride];
@@ -165,27 +175,44 @@ __device__ __forceinline__ void fft_pass(typename V2<T>::type *X, int logn, int 
 }
 
 // `count` independent in-place decimation-in-time transforms of length n = 2^logn (n >= 2)
-// stored back to back in X (through lds_at), each already in bit-reversed order, with the
-// twiddles of an N-point table in T: one pass of radix 2^(logn mod RMAX) for the first
-// stages, then radix-2^RMAX passes (each lane keeps 2^RMAX points in registers for RMAX
-// stages).  INV uses the conjugate twiddles exp(+2 pi i k / n) and does not scale.  Ends
-// with a barrier.
-template <bool INV, typename T, int RMAX = 4>
+// stored back to back in X (through lds_at with period 2^sh; sh < 0: lds_pad_shift(logn)),
+// each already in bit-reversed order, with the twiddles of an N-point table in T: radix-2^RMAX
+// passes (each lane keeps 2^RMAX points in registers for RMAX stages) and one pass of radix
+// 2^(logn mod RMAX), first or (REM_LAST) last.  INV uses the conjugate twiddles
+// exp(+2 pi i k / n) and does not scale.  Ends with a barrier.
+template <bool INV, typename T, int RMAX = 4, bool REM_LAST = false>
 __device__ __forceinline__ void fft_lds(typename V2<T>::type *X, int n, int logn, int count, const TwCacheT<T> &Tc,
-                                        int N)
+                                        int N, int sh = -1)
 {
     static_assert(RMAX >= 2 && RMAX <= 4, "radix 4, 8 or 16");
-    const int sh = lds_pad_shift(logn), rem = logn % RMAX;
+    if (sh < 0) sh = lds_pad_shift(logn);
+    const int rem = logn % RMAX;
     (void)n;
-    if (rem == 1) fft_pass<INV, 1, true, T>(X, logn, count, 1, sh, Tc, N);
-    if (RMAX > 2 && rem == 2) fft_pass<INV, 2, true, T>(X, logn, count, 1, sh, Tc, N);
-    if (RMAX > 3 && rem == 3) fft_pass<INV, 3, true, T>(X, logn, count, 1, sh, Tc, N);
-    int s = 1 + rem;
-    if (rem == 0) {
+    auto rem_pass = [&](int s, bool first) {
+        if (rem == 1) {
+            if (first) fft_pass<INV, 1, true, T>(X, logn, count, s, sh, Tc, N);
+            else fft_pass<INV, 1, false, T>(X, logn, count, s, sh, Tc, N);
+        }
+        if (RMAX > 2 && rem == 2) {
+            if (first) fft_pass<INV, 2, true, T>(X, logn, count, s, sh, Tc, N);
+            else fft_pass<INV, 2, false, T>(X, logn, count, s, sh, Tc, N);
+        }
+        if (RMAX > 3 && rem == 3) {
+            if (first) fft_pass<INV, 3, true, T>(X, logn, count, s, sh, Tc, N);
+            else fft_pass<INV, 3, false, T>(X, logn, count, s, sh, Tc, N);
+        }
+    };
+    int s = 1;
+    if (!REM_LAST && rem) {
+        rem_pass(1, true);
+        s += rem;
+    }
+    if (s == 1 && logn >= RMAX) {
         fft_pass<INV, RMAX, true, T>(X, logn, count, 1, sh, Tc, N);
         s += RMAX;
     }
-    for (; s <= logn; s += RMAX) fft_pass<INV, RMAX, false, T>(X, logn, count, s, sh, Tc, N);
+    for (; s + RMAX - 1 <= logn; s += RMAX) fft_pass<INV, RMAX, false, T>(X, logn, count, s, sh, Tc, N);
+    if (REM_LAST && rem) rem_pass(s, s == 1);
 }
 
 }  // namespace lbf

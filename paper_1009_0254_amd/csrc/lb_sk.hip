@@ -293,58 +293,77 @@ __global__ void __launch_bounds__(SK_THREADS)
     const double inv_n = 1.0 / ((double)q.nx * (double)ny);
     // added to the real part of output 0 of this block when that output is k = 0
     const double k0 = kx0 == 0 && par == 0 ? (double)q.nx * (double)ny * base[18 * r + a] : 0.0;
-    const int L = ny / split, logL = q.logny - (split - 1), sh = lds_pad_shift(logL);
+    const int L = ny / split, logL = q.logny - (split - 1);
+    // P16 (FP32): the 1/16-pad layout, filled in destination order (lane e writes slot e of the
+    // bit-reversed line and reads its source at bitrev(e)), the remainder pass last; FP64 keeps
+    // the wide pad and a source-ordered fill
+    constexpr bool P16 = sizeof(Tt) == 4;
+    const int sh = P16 ? LDS_PAD16 : lds_pad_shift(logL);
     if (split == 1) {
-        // lanes over (y, c) with c < Cp = 2^ceil(log2 C_); c >= C_ idle
-        const int lCp = C_ > 1 ? 32 - __clz(C_ - 1) : 0, tot = ny << lCp;
-        for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * blockDim.x) {
-            C v[4];
-            for (int u = 0; u < 4; ++u) {
-                const int e = min(e0 + u * (int)blockDim.x, tot - 1), y = e >> lCp;
-                const int c = min(e & ((1 << lCp) - 1), C_ - 1);
-                v[u] = S0[sk_at(y, kx0 + c, ny)];
+        if (P16) {
+            const int tot = C_ << logL;
+            for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * blockDim.x) {
+                C v[4];
+                for (int u = 0; u < 4; ++u) {
+                    const int e = min(e0 + u * (int)blockDim.x, tot - 1);
+                    const int y = (int)bitrev((unsigned)(e & (L - 1)), logL);
+                    v[u] = S0[sk_at32(y, kx0 + (e >> logL), ny)];
+                }
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * (int)blockDim.x;
+                    if (e < tot) X[lds_at(e, sh)] = v[u];
+                }
             }
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * (int)blockDim.x, y = e >> lCp, c = e & ((1 << lCp) - 1);
-                if (e < tot && c < C_) X[lds_at(c * ny + bitrev((unsigned)y, logL), sh)] = v[u];
+        } else {
+            // lanes over (y, c) with c < Cp = 2^ceil(log2 C_); c >= C_ idle
+            const int lCp = C_ > 1 ? 32 - __clz(C_ - 1) : 0, tot = ny << lCp;
+            for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * blockDim.x) {
+                C v[4];
+                for (int u = 0; u < 4; ++u) {
+                    const int e = min(e0 + u * (int)blockDim.x, tot - 1), y = e >> lCp;
+                    const int c = min(e & ((1 << lCp) - 1), C_ - 1);
+                    v[u] = S0[sk_at(y, kx0 + c, ny)];
+                }
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * (int)blockDim.x, y = e >> lCp, c = e & ((1 << lCp) - 1);
+                    if (e < tot && c < C_) X[lds_at(c * ny + bitrev((unsigned)y, logL), sh)] = v[u];
+                }
             }
         }
     } else {
         // X_{2k+p} = sum_n [x_n + (-1)^p x_{n+L}] W^{pn} exp(-2 pi i n k / L), W = exp(-2 pi i / ny)
         const int wstride = nmax / ny;
-        for (int n = threadIdx.x; n < L; n += blockDim.x) {
-            const C u = S0[sk_at(n, kx0, ny)], v = S0[sk_at(n + L, kx0, ny)];
-            X[lds_at(bitrev((unsigned)n, logL), sh)] = par == 0 ? cadd(u, v) : cmul(csub(u, v), twiddle(T, n * wstride));
+        for (int r = threadIdx.x; r < L; r += blockDim.x) {
+            const int n = P16 ? (int)bitrev((unsigned)r, logL) : r;
+            const C u = S0[sk_at32(n, kx0, ny)], v = S0[sk_at32(n + L, kx0, ny)];
+            X[lds_at(P16 ? r : (int)bitrev((unsigned)n, logL), sh)] =
+                par == 0 ? cadd(u, v) : cmul(csub(u, v), twiddle(T, n * wstride));
         }
     }
     __syncthreads();
-    fft_lds<false, Tt, RMAX>(X, L, logL, split == 1 ? C_ : 1, T, nmax);
+    fft_lds<false, Tt, RMAX, P16>(X, L, logL, split == 1 ? C_ : 1, T, nmax, sh);
     const int tot = (split == 1 ? C_ : 1) * L;
     auto power = [&](int e) {
         const C v = X[lds_at(e, sh)];
         const double re = (double)v.x + (e == 0 ? k0 : 0.0), im = (double)v.y;
         return (re * re + im * im) * inv_n;
     };
+    // output e of this block is k = e mod L of column kx0 + e / L: index c ny + k split + par,
+    // that is e (one column per output parity when split, else L = ny)
     if (SNAP) {
         double *D = plane + (long long)kx0 * ny;
-        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-            const int c = e >> logL, k = e & (L - 1);
-            D[(long long)c * ny + k * split + par] = power(e);
-        }
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) D[split == 1 ? e : 2 * e + par] = power(e);
     } else {
         double *A = acc + q.acc_off + (long long)a * nh * ny + (long long)kx0 * ny;
         for (int e0 = threadIdx.x; e0 < tot; e0 += 4 * blockDim.x) {
             double old[4];
             for (int u = 0; u < 4; ++u) {
-                const int e = min(e0 + u * (int)blockDim.x, tot - 1), c = e >> logL, k = e & (L - 1);
-                old[u] = A[(long long)c * ny + k * split + par];
+                const int e = min(e0 + u * (int)blockDim.x, tot - 1);
+                old[u] = A[split == 1 ? e : 2 * e + par];
             }
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u * (int)blockDim.x;
-                if (e < tot) {
-                    const int c = e >> logL, k = e & (L - 1);
-                    A[(long long)c * ny + k * split + par] = old[u] + power(e);
-                }
+                if (e < tot) A[split == 1 ? e : 2 * e + par] = old[u] + power(e);
             }
         }
     }
@@ -421,7 +440,7 @@ __global__ void k_sk_read(const double *__restrict__ acc, double *__restrict__ o
 }
 
 // radix of the in-LDS passes: 8, except 4 for the FP64 column transforms (at 8 their
-// registers allow only one 1024-lane workgroup per CU)
+// registers allow only one 1024-lane workgroup per CU; so would 16 for the FP32 columns)
 template <typename Tt> constexpr int SK_ROW_RADIX = 3;
 template <typename Tt> constexpr int SK_COL_RADIX = sizeof(Tt) == 4 ? 3 : 2;
 
@@ -456,11 +475,17 @@ hipError_t launch_rows(int precision, const SkLaunch &a, int a_first, int a_coun
     return hipGetLastError();
 }
 
+// dynamic LDS of a column block of `points` transform points (FP32: 1/16 pad)
+size_t sk_col_lds_bytes(int precision, long long points)
+{
+    return (size_t)sk_elem(precision) * (size_t)(precision == 0 ? lds_padded(points) : lds_padded16(points));
+}
+
 template <typename Tt, bool SNAP>
 void cols_kernel(int precision, const SkLaunch &a, unsigned modes, double *plane, hipStream_t s)
 {
     hipLaunchKernelGGL((k_sk_cols<Tt, SNAP, SK_COL_RADIX<Tt>>), dim3(xcd_grid(a.cols), modes),
-                       dim3(sk_threads(a.lds_cols)), (size_t)sk_elem(precision) * lds_padded(a.lds_cols), s,
+                       dim3(sk_threads(a.lds_cols)), sk_col_lds_bytes(precision, a.lds_cols), s,
                        (const typename V2<Tt>::type *)a.spec, a.sk, a.r0, a.r1, (long long)a.col_base,
                        (long long)a.cols, (long long)a.Ptot, 0, SNAP ? nullptr : a.acc, plane, (const double *)a.base,
                        (const double2 *)a.tw, a.nmax);
@@ -506,7 +531,7 @@ int sk_cols_per_block(int precision, int nx, int ny)
 hipError_t set_sk_lds_limits(int precision, int G, int max_row, int max_col)
 {
     const size_t rows = (size_t)sk_elem(precision) * lds_padded((long long)G * (max_row / 2)),
-                 cols = (size_t)sk_elem(precision) * lds_padded(max_col);
+                 cols = sk_col_lds_bytes(precision, max_col);
     return precision == 0 ? lds_limits_of<double, double>(rows, cols) : lds_limits_of<float, float>(rows, cols);
 }
 

@@ -15,5 +15,10 @@ __host__ __device__ inline long long sk_at(int ky, int kx, int ny)
 {
     return ((long long)(kx / SK_KG) * ny + ky) * SK_KG + (kx % SK_KG);
 }
+// the same in 32-bit arithmetic (one replica's mode slot holds fewer than 2^32 elements)
+__device__ inline unsigned sk_at32(int ky, int kx, int ny)
+{
+    return (((unsigned)kx / SK_KG) * (unsigned)ny + (unsigned)ky) * SK_KG + ((unsigned)kx % SK_KG);
+}
 
 }  // namespace lbf
