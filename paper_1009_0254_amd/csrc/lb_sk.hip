@@ -242,20 +242,29 @@ __global__ void __launch_bounds__(SK_THREADS)
         const int nt = gcount << lRp;
         fft_lds<false, Tt, RMAX>(X, M, logM, nt, T, nmax);
         // X_k = E_k + W^k O_k with E = (Z_k + conj Z_{M-k}) / 2, O = (Z_k - conj Z_{M-k}) / 2i,
-        // W = exp(-2 pi i / nx), for k = 0..M (Z has period M); k = M in the second loop
+        // W = exp(-2 pi i / nx), for k = 0..M (Z has period M).  The partner M - k reuses both
+        // reads and the twiddle: E_{M-k} = conj E_k, O_{M-k} = conj O_k, W^{M-k} = -conj W^k,
+        // so X_{M-k} = conj(E_k - W^k O_k).  A lane takes k < M/2 and its partner; k = M/2 in
+        // the second loop.
         const Tt h = (Tt)0.5;
         auto untangle = [&](int t, int k) {
             const int c = t >> lRp, rr = t & (Rp - 1);
             if (rr >= R) return;
-            const C Zk = X[lds_at(t * M + (k & (M - 1)), sh)];
+            const C Zk = X[lds_at(t * M + k, sh)];
             const C Zm = X[lds_at(t * M + ((M - k) & (M - 1)), sh)];
             const C E = mk2(h * (Zk.x + Zm.x), h * (Zk.y - Zm.y));
             const C O = mk2(h * (Zk.y + Zm.y), -h * (Zk.x - Zm.x));
-            const C W = k < M ? twiddle(T, k * wstride) : mk2((Tt)-1, (Tt)0);
-            spec[(a0 + c) * Ptot + q.soff + sk_at(y0 + rr, k, ny)] = cadd(E, cmul(W, O));
+            const C WO = cmul(twiddle(T, k * wstride), O);
+            typename V2<Tt>::type *out = spec + (a0 + c) * Ptot + q.soff;
+            out[sk_at(y0 + rr, k, ny)] = cadd(E, WO);
+            if (2 * k != M) {
+                const C D = csub(E, WO);
+                out[sk_at(y0 + rr, M - k, ny)] = mk2(D.x, -D.y);
+            }
         };
-        for (int idx = threadIdx.x; idx < nt << logM; idx += blockDim.x) untangle(idx >> logM, idx & (M - 1));
-        for (int t = threadIdx.x; t < nt; t += blockDim.x) untangle(t, M);
+        const int lh = logM - 1;   // M/2 = 2^lh
+        for (int idx = threadIdx.x; idx < nt << lh; idx += blockDim.x) untangle(idx >> lh, idx & ((1 << lh) - 1));
+        for (int t = threadIdx.x; t < nt; t += blockDim.x) untangle(t, M >> 1);
         __syncthreads();   // X is reused by the next group
     }
 }

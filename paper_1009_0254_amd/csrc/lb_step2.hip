@@ -95,9 +95,14 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
 
     // columns.  whole: lane l is column l (lanes past the row duplicate column l mod nx and
     // never store; whole waves past it only keep the barriers).  strip: lane l is column
-    // x0 - 3 + l (mod nx).
+    // x0 - 3 + l (mod nx).  The last strip of a row stores columns [x0, nx), which need lanes
+    // l < nx - x0 + 6 (its results at lanes 3 .. nx - x0 + 2 depend on lanes 0 .. nx - x0 + 5);
+    // whole waves past them only keep the barriers.  The first idle lane's LDS slots are never
+    // written, as the slots beyond a strip's ends are not: only lanes whose results are not
+    // needed read them.
     const bool whole = nx <= BG;
-    const bool idle = gidle || (whole && (tid - grp * BG) / 64 * 64 >= nx);   // uniform per wave
+    const int wl0 = (int)((tid - grp * BG) / 64 * 64);   // first lane of this wave in its group
+    const bool idle = gidle || (whole ? wl0 >= (int)nx : wl0 >= (int)nx - tl.x0 + 6);   // uniform per wave
     unsigned xw;
     if (whole) {
         xw = l < nx ? l : l % nx;
