@@ -41,10 +41,13 @@ __global__ void k_fill(double *p, long long n, double v)
 // taken along ky in the kernel that draws the noise and then along kx in the kernel that
 // stores the fields.
 //
-// The intermediate plane between the two passes is stored in chunks of CH = min(16, ny)
-// rows: element (kx, y) at ((y / CH) nx + kx) CH + y mod CH.  The drawing kernel writes each
-// column as runs of CH contiguous elements; the storing kernel reads rows across kx from one
-// contiguous region of nx CH elements (the rows of a chunk share its cache lines).
+// The intermediate plane between the two passes is stored in chunks of CH = min(4, ny) rows:
+// element (kx, y) at ((y / CH) nx + kx) CH + y mod CH.  The drawing kernel writes each column as
+// runs of CH contiguous elements; the storing kernel reads two rows across kx from one contiguous
+// region of nx CH elements, one 16-byte piece per kx at a stride of CH elements, so that a wave's
+// reads touch 16 cache lines.  (At 8192^2: 16-row chunks, whose rows all read different lines,
+// made the storing kernel 0.52 ms; 4-row chunks 0.41 ms, for 0.01 ms more in the drawing kernel,
+// whose writes become 32-byte pieces; 2-row chunks moved the cost there.)
 
 constexpr int CN_THREADS = 1024;
 constexpr int CN_COL_POINTS = 4096;   // points per drawing block when columns are short
@@ -183,7 +186,7 @@ __device__ __forceinline__ typename V2<R>::type cn_z(const RepDesc &d, const Con
 }
 
 // the intermediate plane's chunk length and element index
-__device__ __forceinline__ int cn_chunk_log(int logny) { return logny < 4 ? logny : 4; }
+__device__ __forceinline__ int cn_chunk_log(int logny) { return logny < 2 ? logny : 2; }
 __device__ __forceinline__ long long cn_a_at(int kx, int y, int nx, int lch)
 {
     return ((((long long)(y >> lch) * nx) + kx) << lch) | (y & ((1 << lch) - 1));
