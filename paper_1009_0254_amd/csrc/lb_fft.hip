@@ -185,6 +185,19 @@ __device__ __forceinline__ typename V2<R>::type cn_z(const RepDesc &d, const Con
     return zk;
 }
 
+// `count` transforms of length n = 2^logn in the 1/16-pad layout: radix 16, remainder last; the
+// lengths of the large lattices with compile-time strides
+template <typename R>
+__device__ __forceinline__ void cn_fft(typename V2<R>::type *X, int logn, int count, const TwCacheT<R> &T, int n)
+{
+    if (logn == 13)
+        fft_lds_c<false, R, 4, true, 13, LDS_PAD16>(X, count, T, n);
+    else if (logn == 12)
+        fft_lds_c<false, R, 4, true, 12, LDS_PAD16>(X, count, T, n);
+    else
+        fft_lds<false, R, 4, true>(X, n, logn, count, T, n, LDS_PAD16);
+}
+
 // the intermediate plane's chunk length and element index
 __device__ __forceinline__ int cn_chunk_log(int logny) { return logny < 2 ? logny : 2; }
 __device__ __forceinline__ long long cn_a_at(int kx, int y, int nx, int lch)
@@ -256,7 +269,7 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_gen(void *__restrict__ Av, co
         }
     }
     __syncthreads();
-    fft_lds<false, R, 4, true>(X, ny, logny, cols, T, ny, sh);
+    cn_fft<R>(X, logny, cols, T, ny);
     C *A = reinterpret_cast<C *>(Av);
     const int lch = cn_chunk_log(logny);
     for (int e = threadIdx.x; e < (cols << logny); e += blockDim.x) {
@@ -319,7 +332,7 @@ __global__ void __launch_bounds__(CN_THREADS) k_cn_out(const void *__restrict__ 
         }
     }
     __syncthreads();
-    fft_lds<false, S, 4, true>(X, nx, lognx, ROWS, T, nx, sh);
+    cn_fft<S>(X, lognx, ROWS, T, nx);
     const S s = (S)rsqrt((double)nx * (double)ny);
     C *out = reinterpret_cast<C *>(xi + 2 * d.xi_off) + (long long)y0 * nx;
     for (int e = threadIdx.x; e < ROWS * nx; e += blockDim.x) {

@@ -215,4 +215,64 @@ __device__ __forceinline__ void fft_lds(typename V2<T>::type *X, int n, int logn
     if (REM_LAST && rem) rem_pass(s, s == 1);
 }
 
+// The same passes with the transform length and the pad period fixed at compile time: every
+// stride is a constant, so a lane's LDS accesses are one base address plus immediate offsets
+// (the runtime version computes an address per element).  For the lengths the large lattices
+// use; fft_lds covers the rest.
+template <bool INV, int RL, bool FIRST, typename T, int LOGN, int S, int SH>
+__device__ __forceinline__ void fft_pass_c(typename V2<T>::type *X, int count, const TwCacheT<T> &Tc, int N)
+{
+    typedef typename V2<T>::type C;
+    constexpr int R = 1 << RL, lq = S - 1, q = 1 << lq;
+    constexpr bool wide = lq >= SH, narrow = lq + RL <= SH;
+    constexpr int stride = wide ? q + (q >> SH) : q;
+    const int groups = (count << LOGN) >> RL;
+    for (int b = threadIdx.x; b < groups; b += blockDim.x) {
+        const int g = b >> (LOGN - RL), bb = b & ((1 << (LOGN - RL)) - 1);
+        const int pos = bb & (q - 1);
+        const int base = (g << LOGN) + ((bb >> lq) << (lq + RL)) + pos;
+        C x[R];
+        if constexpr (wide || narrow) {
+            C *Xa = X + lds_at(base, SH);
+#pragma unroll
+            for (int j = 0; j < R; ++j) x[j] = Xa[j * stride];
+            pass_stages<INV, RL, 0, FIRST, T>(x, pos, S, Tc, N);
+#pragma unroll
+            for (int j = 0; j < R; ++j) Xa[j * stride] = x[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) x[j] = X[lds_at(base + j * q, SH)];
+            pass_stages<INV, RL, 0, FIRST, T>(x, pos, S, Tc, N);
+#pragma unroll
+            for (int j = 0; j < R; ++j) X[lds_at(base + j * q, SH)] = x[j];
+        }
+    }
+    __syncthreads();
+}
+
+// radix-2^RMAX passes from stage S on, then the remainder (REM_LAST) or nothing
+template <bool INV, typename T, int RMAX, bool REM_LAST, int LOGN, int SH, int S>
+__device__ __forceinline__ void fft_passes_c(typename V2<T>::type *X, int count, const TwCacheT<T> &Tc, int N)
+{
+    if constexpr (S + RMAX - 1 <= LOGN) {
+        fft_pass_c<INV, RMAX, S == 1, T, LOGN, S, SH>(X, count, Tc, N);
+        fft_passes_c<INV, T, RMAX, REM_LAST, LOGN, SH, S + RMAX>(X, count, Tc, N);
+    } else if constexpr (REM_LAST && S <= LOGN) {
+        fft_pass_c<INV, LOGN - S + 1, S == 1, T, LOGN, S, SH>(X, count, Tc, N);
+    }
+}
+
+// fft_lds for n = 2^LOGN and pad period 2^SH known at compile time (same passes, same order)
+template <bool INV, typename T, int RMAX, bool REM_LAST, int LOGN, int SH>
+__device__ __forceinline__ void fft_lds_c(typename V2<T>::type *X, int count, const TwCacheT<T> &Tc, int N)
+{
+    constexpr int rem = LOGN % RMAX;
+    if constexpr (!REM_LAST && rem != 0) {
+        fft_pass_c<INV, rem, true, T, LOGN, 1, SH>(X, count, Tc, N);
+        fft_passes_c<INV, T, RMAX, false, LOGN, SH, 1 + rem>(X, count, Tc, N);
+    } else {
+        fft_passes_c<INV, T, RMAX, REM_LAST, LOGN, SH, 1>(X, count, Tc, N);
+    }
+}
+
 }  // namespace lbf
