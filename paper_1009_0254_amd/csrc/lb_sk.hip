@@ -122,6 +122,22 @@ __device__ __forceinline__ void pair_moments(const S *__restrict__ P, int nx, in
     for (int a = 0; a < 9; ++a) m[a] = mk2(me[a], mo[a]);
 }
 
+// `count` transforms of length n = 2^logn, pad period 2^sh (the 1/16 pad with the remainder pass
+// last when P16, else the wide pad with the remainder first); the lengths of the large lattices
+// with compile-time strides
+template <typename Tt, int RMAX, bool P16, bool FIXED = true>
+__device__ __forceinline__ void sk_fft(typename V2<Tt>::type *X, int n, int logn, int count, const TwCacheT<Tt> &T,
+                                       int nmax, int sh)
+{
+    constexpr int SH12 = P16 ? LDS_PAD16 : lds_pad_shift(12), SH13 = P16 ? LDS_PAD16 : lds_pad_shift(13);
+    if (FIXED && logn == 12 && sh == SH12)
+        fft_lds_c<false, Tt, RMAX, P16, 12, SH12>(X, count, T, nmax);
+    else if (FIXED && logn == 13 && sh == SH13)
+        fft_lds_c<false, Tt, RMAX, P16, 13, SH13>(X, count, T, nmax);
+    else
+        fft_lds<false, Tt, RMAX, P16>(X, n, logn, count, T, nmax, sh);
+}
+
 constexpr int SK_REF_THREADS = 256;
 
 // The reference of replica r: the mean over row 0 of each pulled population, in FP64 with a
@@ -240,7 +256,9 @@ __global__ void __launch_bounds__(SK_THREADS)
         __syncthreads();
         // slots rr >= R (the last rows of a replica) hold no data; their results are dropped
         const int nt = gcount << lRp;
-        fft_lds<false, Tt, RMAX>(X, M, logM, nt, T, nmax);
+        // (the register-cached variant keeps the runtime strides: the fixed ones need registers
+        // it holds the moments in)
+        sk_fft<Tt, RMAX, false, !CACHE>(X, M, logM, nt, T, nmax, lds_pad_shift(logM));
         // X_k = E_k + W^k O_k with E = (Z_k + conj Z_{M-k}) / 2, O = (Z_k - conj Z_{M-k}) / 2i,
         // W = exp(-2 pi i / nx), for k = 0..M (Z has period M).  The partner M - k reuses both
         // reads and the twiddle: E_{M-k} = conj E_k, O_{M-k} = conj O_k, W^{M-k} = -conj W^k,
@@ -350,7 +368,7 @@ __global__ void __launch_bounds__(SK_THREADS)
         }
     }
     __syncthreads();
-    fft_lds<false, Tt, RMAX, P16>(X, L, logL, split == 1 ? C_ : 1, T, nmax, sh);
+    sk_fft<Tt, RMAX, P16>(X, L, logL, split == 1 ? C_ : 1, T, nmax, sh);
     const int tot = (split == 1 ? C_ : 1) * L;
     auto power = [&](int e) {
         const C v = X[lds_at(e, sh)];
