@@ -441,14 +441,15 @@ def fp64_spectrum_tol(n, smax):
     return 1e-10 + 8 * 2 * eps * np.log2(n) * n / np.sqrt(n * smax)
 
 
-SK_SHAPES = [(64, 32), (16384, 16), (16, 16384), (16, 8192), (2048, 8), (4096, 64), (8192, 16), (4, 4)]
+SK_SHAPES = [(64, 32), (16384, 16), (16, 16384), (16, 8192), (8, 4096), (2048, 8), (4096, 64), (8192, 16), (4, 4)]
 
 
 @pytest.mark.parametrize("shape", SK_SHAPES, ids=[f"{a}x{b}" for a, b in SK_SHAPES])
 @pytest.mark.parametrize("precision", [0, 2])
 def test_structure_factor_matches_oracle_fft(precision, shape):
     """All nine |m_a(k)|^2 against numpy's FFT of the oracle's moments: rows of length 16384
-    (real-to-complex split), columns of 8192 and 16384 (one decimation-in-frequency stage),
+    (real-to-complex split), columns of 4096, 8192 and 16384 (the last with one
+    decimation-in-frequency stage; 4096 and 8192 on the compile-time-length transforms),
     all nine modes per pass (up to 2048 wide), rows of 4096 and 8192 whose FP32 moments stay
     in registers across mode groups (8 + 1 and 4 + 4 + 1), and the smallest lattice."""
     L = _L()
@@ -1092,15 +1093,16 @@ def test_correlated_noise_parity_long_lines(precision, shape):
         assert e.max() < 9e-7
 
 
-CN_SMALL = [(4, 64, 6), (64, 4, 6), (4, 4, 8), (8, 2048, 3)]
+CN_SMALL = [(4, 64, 6), (64, 4, 6), (4, 4, 8), (8, 2048, 3), (8, 4096, 3), (4096, 8, 3)]
 
 
 @pytest.mark.parametrize("shape", CN_SMALL, ids=[f"{a}x{b}" for a, b, _ in CN_SMALL])
 @pytest.mark.parametrize("precision", [2, 0])
 def test_correlated_noise_parity_narrow_sides(precision, shape):
     """The filter's edge shapes: the smallest sides (4), a lattice whose mirror-pair columns
-    all fit one drawing block (4 x 64), rows of a 4-row chunk (64 x 4), and 2048-point
-    columns of a narrow lattice, against the oracle as above (same gates)."""
+    all fit one drawing block (4 x 64), rows of a 4-row chunk (64 x 4), 2048-point columns
+    of a narrow lattice, and 4096-point columns and rows (the compile-time-length
+    transforms), against the oracle as above (same gates)."""
     nx, ny, steps = shape
     cfg = dict(W.single_phase_8192(), nx=nx, ny=ny, noise="correlated", seed=23)
     mg, mo = run_pair(cfg, precision, steps, chunks=1)
