@@ -139,9 +139,21 @@ __device__ __forceinline__ void pass_stages(typename V2<T>::type *x, int pos, in
 // table lookup) times the constant W_{2^(t+1)}^(j mod 2^t).  FIRST: s = 1, where pos = 0 and
 // every looked-up twiddle is 1.  When q is a multiple of the pad period the lane's elements
 // sit a uniform stride apart.  Ends with a barrier.
+// Lane order of a pass: lane b takes butterfly group perm(b), perm a rotation right by r of the
+// bit field [lo, lo + w) of b (packed lo | w << 4 | r << 8; 0: identity).  It changes only
+// which lane computes which group, so the results are the same; chosen so that 16 consecutive
+// lanes touch 16 distinct bank pairs where the layout alone does not give that.
+__device__ __forceinline__ int lane_perm(int b, unsigned perm)
+{
+    if (perm == 0) return b;
+    const int lo = perm & 15, w = (perm >> 4) & 15, r = perm >> 8;
+    const int mask = (1 << w) - 1, f = (b >> lo) & mask;
+    return (b & ~(mask << lo)) | ((((f >> r) | (f << (w - r))) & mask) << lo);
+}
+
 template <bool INV, int RL, bool FIRST, typename T>
 __device__ __forceinline__ void fft_pass(typename V2<T>::type *X, int logn, int count, int s, int sh,
-                                         const TwCacheT<T> &Tc, int N)
+                                         const TwCacheT<T> &Tc, int N, unsigned perm = 0)
 {
     typedef typename V2<T>::type C;
     constexpr int R = 1 << RL;
@@ -151,7 +163,11 @@ __device__ __forceinline__ void fft_pass(typename V2<T>::type *X, int logn, int 
     // when all R of them lie inside one aligned block of 2^(lq + RL) <= 2^sh elements
     const bool wide = lq >= sh, narrow = lq + RL <= sh;
     const int stride = wide ? q + (q >> sh) : q;
-    for (int b = threadIdx.x; b < groups; b += blockDim.x) {
+    // a permutation of the lanes needs whole blocks of 2^(lo + w) groups (uniform: scalar)
+    perm = __builtin_amdgcn_readfirstlane(perm);
+    if (perm && (groups & ((1 << ((perm & 15) + ((perm >> 4) & 15))) - 1))) perm = 0;
+    for (int b0 = threadIdx.x; b0 < groups; b0 += blockDim.x) {
+        const int b = lane_perm(b0, perm);
         const int g = b >> (logn - RL), bb = b & gmask;
         const int pos = bb & (q - 1);
         const int base = (g << logn) + ((bb >> lq) << (lq + RL)) + pos;
@@ -174,32 +190,38 @@ __device__ __forceinline__ void fft_pass(typename V2<T>::type *X, int logn, int 
     __syncthreads();
 }
 
+struct NoLanePerm {
+    __device__ unsigned operator()(int, int, int) const { return 0; }
+};
+
 // `count` independent in-place decimation-in-time transforms of length n = 2^logn (n >= 2)
 // stored back to back in X (through lds_at with period 2^sh; sh < 0: lds_pad_shift(logn)),
 // each already in bit-reversed order, with the twiddles of an N-point table in T: radix-2^RMAX
 // passes (each lane keeps 2^RMAX points in registers for RMAX stages) and one pass of radix
-// 2^(logn mod RMAX), first or (REM_LAST) last.  INV uses the conjugate twiddles
-// exp(+2 pi i k / n) and does not scale.  Ends with a barrier.
-template <bool INV, typename T, int RMAX = 4, bool REM_LAST = false>
+// 2^(logn mod RMAX), first or (REM_LAST) last.  perm_of(logn, s, RL) gives each pass's lane
+// permutation (lane_perm).  INV uses the conjugate twiddles exp(+2 pi i k / n) and does not
+// scale.  Ends with a barrier.
+template <bool INV, typename T, int RMAX = 4, bool REM_LAST = false, typename P = NoLanePerm>
 __device__ __forceinline__ void fft_lds(typename V2<T>::type *X, int n, int logn, int count, const TwCacheT<T> &Tc,
-                                        int N, int sh = -1)
+                                        int N, int sh = -1, P perm_of = P())
 {
     static_assert(RMAX >= 2 && RMAX <= 4, "radix 4, 8 or 16");
     if (sh < 0) sh = lds_pad_shift(logn);
     const int rem = logn % RMAX;
     (void)n;
     auto rem_pass = [&](int s, bool first) {
+        const unsigned pm = perm_of(logn, s, rem);
         if (rem == 1) {
-            if (first) fft_pass<INV, 1, true, T>(X, logn, count, s, sh, Tc, N);
-            else fft_pass<INV, 1, false, T>(X, logn, count, s, sh, Tc, N);
+            if (first) fft_pass<INV, 1, true, T>(X, logn, count, s, sh, Tc, N, pm);
+            else fft_pass<INV, 1, false, T>(X, logn, count, s, sh, Tc, N, pm);
         }
         if (RMAX > 2 && rem == 2) {
-            if (first) fft_pass<INV, 2, true, T>(X, logn, count, s, sh, Tc, N);
-            else fft_pass<INV, 2, false, T>(X, logn, count, s, sh, Tc, N);
+            if (first) fft_pass<INV, 2, true, T>(X, logn, count, s, sh, Tc, N, pm);
+            else fft_pass<INV, 2, false, T>(X, logn, count, s, sh, Tc, N, pm);
         }
         if (RMAX > 3 && rem == 3) {
-            if (first) fft_pass<INV, 3, true, T>(X, logn, count, s, sh, Tc, N);
-            else fft_pass<INV, 3, false, T>(X, logn, count, s, sh, Tc, N);
+            if (first) fft_pass<INV, 3, true, T>(X, logn, count, s, sh, Tc, N, pm);
+            else fft_pass<INV, 3, false, T>(X, logn, count, s, sh, Tc, N, pm);
         }
     };
     int s = 1;
@@ -208,10 +230,11 @@ __device__ __forceinline__ void fft_lds(typename V2<T>::type *X, int n, int logn
         s += rem;
     }
     if (s == 1 && logn >= RMAX) {
-        fft_pass<INV, RMAX, true, T>(X, logn, count, 1, sh, Tc, N);
+        fft_pass<INV, RMAX, true, T>(X, logn, count, 1, sh, Tc, N, perm_of(logn, 1, RMAX));
         s += RMAX;
     }
-    for (; s + RMAX - 1 <= logn; s += RMAX) fft_pass<INV, RMAX, false, T>(X, logn, count, s, sh, Tc, N);
+    for (; s + RMAX - 1 <= logn; s += RMAX)
+        fft_pass<INV, RMAX, false, T>(X, logn, count, s, sh, Tc, N, perm_of(logn, s, RMAX));
     if (REM_LAST && rem) rem_pass(s, s == 1);
 }
 
@@ -220,14 +243,17 @@ __device__ __forceinline__ void fft_lds(typename V2<T>::type *X, int n, int logn
 // (the runtime version computes an address per element).  For the lengths the large lattices
 // use; fft_lds covers the rest.
 template <bool INV, int RL, bool FIRST, typename T, int LOGN, int S, int SH>
-__device__ __forceinline__ void fft_pass_c(typename V2<T>::type *X, int count, const TwCacheT<T> &Tc, int N)
+__device__ __forceinline__ void fft_pass_c(typename V2<T>::type *X, int count, const TwCacheT<T> &Tc, int N,
+                                           unsigned perm)
 {
     typedef typename V2<T>::type C;
     constexpr int R = 1 << RL, lq = S - 1, q = 1 << lq;
     constexpr bool wide = lq >= SH, narrow = lq + RL <= SH;
     constexpr int stride = wide ? q + (q >> SH) : q;
     const int groups = (count << LOGN) >> RL;
-    for (int b = threadIdx.x; b < groups; b += blockDim.x) {
+    if (perm && (groups & ((1 << ((perm & 15) + ((perm >> 4) & 15))) - 1))) perm = 0;
+    for (int b0 = threadIdx.x; b0 < groups; b0 += blockDim.x) {
+        const int b = lane_perm(b0, perm);
         const int g = b >> (LOGN - RL), bb = b & ((1 << (LOGN - RL)) - 1);
         const int pos = bb & (q - 1);
         const int base = (g << LOGN) + ((bb >> lq) << (lq + RL)) + pos;
@@ -251,27 +277,29 @@ __device__ __forceinline__ void fft_pass_c(typename V2<T>::type *X, int count, c
 }
 
 // radix-2^RMAX passes from stage S on, then the remainder (REM_LAST) or nothing
-template <bool INV, typename T, int RMAX, bool REM_LAST, int LOGN, int SH, int S>
-__device__ __forceinline__ void fft_passes_c(typename V2<T>::type *X, int count, const TwCacheT<T> &Tc, int N)
+template <bool INV, typename T, int RMAX, bool REM_LAST, int LOGN, int SH, int S, typename P>
+__device__ __forceinline__ void fft_passes_c(typename V2<T>::type *X, int count, const TwCacheT<T> &Tc, int N,
+                                             P perm_of)
 {
     if constexpr (S + RMAX - 1 <= LOGN) {
-        fft_pass_c<INV, RMAX, S == 1, T, LOGN, S, SH>(X, count, Tc, N);
-        fft_passes_c<INV, T, RMAX, REM_LAST, LOGN, SH, S + RMAX>(X, count, Tc, N);
+        fft_pass_c<INV, RMAX, S == 1, T, LOGN, S, SH>(X, count, Tc, N, perm_of(LOGN, S, RMAX));
+        fft_passes_c<INV, T, RMAX, REM_LAST, LOGN, SH, S + RMAX>(X, count, Tc, N, perm_of);
     } else if constexpr (REM_LAST && S <= LOGN) {
-        fft_pass_c<INV, LOGN - S + 1, S == 1, T, LOGN, S, SH>(X, count, Tc, N);
+        fft_pass_c<INV, LOGN - S + 1, S == 1, T, LOGN, S, SH>(X, count, Tc, N, perm_of(LOGN, S, LOGN - S + 1));
     }
 }
 
 // fft_lds for n = 2^LOGN and pad period 2^SH known at compile time (same passes, same order)
-template <bool INV, typename T, int RMAX, bool REM_LAST, int LOGN, int SH>
-__device__ __forceinline__ void fft_lds_c(typename V2<T>::type *X, int count, const TwCacheT<T> &Tc, int N)
+template <bool INV, typename T, int RMAX, bool REM_LAST, int LOGN, int SH, typename P = NoLanePerm>
+__device__ __forceinline__ void fft_lds_c(typename V2<T>::type *X, int count, const TwCacheT<T> &Tc, int N,
+                                          P perm_of = P())
 {
     constexpr int rem = LOGN % RMAX;
     if constexpr (!REM_LAST && rem != 0) {
-        fft_pass_c<INV, rem, true, T, LOGN, 1, SH>(X, count, Tc, N);
-        fft_passes_c<INV, T, RMAX, false, LOGN, SH, 1 + rem>(X, count, Tc, N);
+        fft_pass_c<INV, rem, true, T, LOGN, 1, SH>(X, count, Tc, N, perm_of(LOGN, 1, rem));
+        fft_passes_c<INV, T, RMAX, false, LOGN, SH, 1 + rem>(X, count, Tc, N, perm_of);
     } else {
-        fft_passes_c<INV, T, RMAX, REM_LAST, LOGN, SH, 1>(X, count, Tc, N);
+        fft_passes_c<INV, T, RMAX, REM_LAST, LOGN, SH, 1>(X, count, Tc, N, perm_of);
     }
 }
 

@@ -30,6 +30,7 @@
 // shell arithmetic.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "lb_fftcore.h"
 #include "lb_internal.h"
@@ -125,17 +126,40 @@ __device__ __forceinline__ void pair_moments(const S *__restrict__ P, int nx, in
 // `count` transforms of length n = 2^logn, pad period 2^sh (the 1/16 pad with the remainder pass
 // last when P16, else the wide pad with the remainder first); the lengths of the large lattices
 // with compile-time strides
-template <typename Tt, int RMAX, bool P16, bool FIXED = true>
+template <typename Tt, int RMAX, bool P16, bool FIXED = true, typename P = NoLanePerm>
 __device__ __forceinline__ void sk_fft(typename V2<Tt>::type *X, int n, int logn, int count, const TwCacheT<Tt> &T,
                                        int nmax, int sh)
 {
     constexpr int SH12 = P16 ? LDS_PAD16 : lds_pad_shift(12), SH13 = P16 ? LDS_PAD16 : lds_pad_shift(13);
     if (FIXED && logn == 12 && sh == SH12)
-        fft_lds_c<false, Tt, RMAX, P16, 12, SH12>(X, count, T, nmax);
+        fft_lds_c<false, Tt, RMAX, P16, 12, SH12>(X, count, T, nmax, P());
     else if (FIXED && logn == 13 && sh == SH13)
-        fft_lds_c<false, Tt, RMAX, P16, 13, SH13>(X, count, T, nmax);
+        fft_lds_c<false, Tt, RMAX, P16, 13, SH13>(X, count, T, nmax, P());
     else
-        fft_lds<false, Tt, RMAX, P16>(X, n, logn, count, T, nmax, sh);
+        fft_lds<false, Tt, RMAX, P16>(X, n, logn, count, T, nmax, sh, P());
+}
+
+// Lane orders of the row transforms' passes (radix 8, remainder first, the wide pad
+// lds_pad_shift(logn)) whose 16 consecutive lanes would otherwise share LDS bank pairs (4- and
+// 2-way at 4096 points, 8- and 2-way at 8192): lane_perm rotations found by enumerating the
+// lanes' slots, packed lo | w << 4 | r << 8.
+struct SkRowPerm {
+    __device__ unsigned operator()(int logn, int s, int) const
+    {
+        if (logn == 12) return s == 1 ? (1u | 5u << 4 | 3u << 8) : s == 4 ? (3u | 4u << 4 | 1u << 8) : 0u;
+        if (logn == 11) return s == 1 ? (2u | 3u << 4 | 2u << 8) : s == 3 ? (2u | 4u << 4 | 2u << 8) : 0u;
+        if (logn == 13) return s == 1 ? (3u | 4u << 4 | 1u << 8) : s == 2 ? (1u | 7u << 4 | 3u << 8) : 0u;
+        return 0u;
+    }
+};
+
+// The rows' register-fed bit-reversed fill: lane e of a wave writes slot bitrev(pair) + pad,
+// which for consecutive pairs puts 16 lanes on 4 bank pairs; lanes of a 16-lane group take
+// pairs 4 apart instead (the wave still covers 64 consecutive pairs, so its loads touch the same
+// cache lines).  Needs whole blocks of 64 pairs.
+__device__ __forceinline__ int sk_fill_pair(int e, bool whole64)
+{
+    return whole64 ? (e & ~63) | ((e & 15) << 2) | ((e >> 4) & 3) : e;
 }
 
 constexpr int SK_REF_THREADS = 256;
@@ -187,9 +211,10 @@ __global__ void __launch_bounds__(SK_REF_THREADS)
 // reference of k_sk_ref); a constant only moves the k = 0 coefficient, which the column pass
 // restores in FP64 as X(0) + n m_a(vref + shift).  CACHE: a lane's node pairs (at most
 // SK_CACHE_PAIRS) are pulled once and their nine moments kept in registers for all mode
-// groups; otherwise each group of G modes pulls the row again (the repeats hit L2 or the
-// MALL).
-template <typename S, typename Tt, int RMAX, bool CACHE>
+// groups, which are GC modes each and fixed at compile time (so that a placed group's
+// registers are free for the transforms); otherwise each group of G modes pulls the row
+// again (the repeats hit L2 or the MALL).
+template <typename S, typename Tt, int RMAX, bool CACHE, int GC>
 __global__ void __launch_bounds__(SK_THREADS)
     k_sk_rows(const S *__restrict__ f, const RepDesc *__restrict__ reps, const SkRep *__restrict__ sk, int r0, int r1,
               long long row_base, long long nrows, int a_first, int a_count, int G, long long Ptot,
@@ -217,34 +242,40 @@ __global__ void __launch_bounds__(SK_THREADS)
     const int wstride = nmax / nx, sh = lds_pad_shift(logM);
     if (threadIdx.x < 9) vref[threadIdx.x] = (Tt)base[18 * r + 9 + threadIdx.x];
     __syncthreads();   // vref (the reference)
+    // (the cached variant pulls once; pulling in the permuted order every group costs more than
+    // the fill's bank conflicts)
+    const bool whole64 = CACHE && (pairs & 63) == 0;
     C cm[CACHE ? SK_CACHE_PAIRS : 1][9];
     if (CACHE) {
 #pragma unroll
         for (int j = 0; j < SK_CACHE_PAIRS; ++j) {
             const int e = threadIdx.x + j * (int)blockDim.x;
             if (e < pairs) {
-                const int rr = e >> logM, n = e & (M - 1);
+                const int ep = sk_fill_pair(e, whole64), rr = ep >> logM, n = ep & (M - 1);
                 pair_moments(P, nx, ny, 2 * n, y0 + rr, vref, cm[j]);
             }
         }
     }
-    for (int a0 = a_first; a0 < a_first + a_count; a0 += G) {
-        const int gcount = min(G, a_first + a_count - a0);
-        if (CACHE) {
+    // one group of modes [a0, a0 + gcount): place them (bit-reversed), transform, untangle into
+    // the spectra.  A0, GN: compile-time a0 and gcount (the cached variant, whose moments of a
+    // placed group are then dead), or -1 for the runtime a0_rt, gn_rt.
+    auto run_group = [&](auto A0, auto GN, int a0_rt, int gn_rt) {
+        constexpr int a0c = decltype(A0)::value, gnc = decltype(GN)::value;
+        const int a0 = a0c >= 0 ? a0c : a0_rt, gcount = gnc >= 0 ? gnc : gn_rt;
+        if constexpr (CACHE) {
 #pragma unroll
             for (int j = 0; j < SK_CACHE_PAIRS; ++j) {
                 const int e = threadIdx.x + j * (int)blockDim.x;
                 if (e < pairs) {
-                    const int rr = e >> logM, n = e & (M - 1);
+                    const int ep = sk_fill_pair(e, whole64), rr = ep >> logM, n = ep & (M - 1);
                     const unsigned jb = bitrev((unsigned)n, logM);
 #pragma unroll
-                    for (int c = 0; c < 9; ++c)
-                        if (c >= a0 && c < a0 + gcount) X[lds_at((((c - a0) << lRp) + rr) * M + jb, sh)] = cm[j][c];
+                    for (int c = a0c; c < a0c + gnc; ++c) X[lds_at((((c - a0c) << lRp) + rr) * M + jb, sh)] = cm[j][c];
                 }
             }
         } else {
             for (int e = threadIdx.x; e < pairs; e += blockDim.x) {
-                const int rr = e >> logM, n = e & (M - 1);
+                const int ep = sk_fill_pair(e, whole64), rr = ep >> logM, n = ep & (M - 1);
                 C m[9];
                 pair_moments(P, nx, ny, 2 * n, y0 + rr, vref, m);
                 const unsigned jb = bitrev((unsigned)n, logM);
@@ -256,9 +287,7 @@ __global__ void __launch_bounds__(SK_THREADS)
         __syncthreads();
         // slots rr >= R (the last rows of a replica) hold no data; their results are dropped
         const int nt = gcount << lRp;
-        // (the register-cached variant keeps the runtime strides: the fixed ones need registers
-        // it holds the moments in)
-        sk_fft<Tt, RMAX, false, !CACHE>(X, M, logM, nt, T, nmax, lds_pad_shift(logM));
+        sk_fft<Tt, RMAX, false, true, SkRowPerm>(X, M, logM, nt, T, nmax, lds_pad_shift(logM));
         // X_k = E_k + W^k O_k with E = (Z_k + conj Z_{M-k}) / 2, O = (Z_k - conj Z_{M-k}) / 2i,
         // W = exp(-2 pi i / nx), for k = 0..M (Z has period M).  The partner M - k reuses both
         // reads and the twiddle: E_{M-k} = conj E_k, O_{M-k} = conj O_k, W^{M-k} = -conj W^k,
@@ -284,6 +313,21 @@ __global__ void __launch_bounds__(SK_THREADS)
         for (int idx = threadIdx.x; idx < nt << lh; idx += blockDim.x) untangle(idx >> lh, idx & ((1 << lh) - 1));
         for (int t = threadIdx.x; t < nt; t += blockDim.x) untangle(t, M >> 1);
         __syncthreads();   // X is reused by the next group
+    };
+    if constexpr (CACHE) {
+        // the nine modes (a_first = 0, a_count = 9) in groups of GC
+        static_assert(GC == 4 || GC == 8, "cached rows run 4 + 4 + 1 or 8 + 1 modes");
+        (void)a_first;
+        (void)a_count;
+        (void)G;
+        run_group(std::integral_constant<int, 0>{}, std::integral_constant<int, GC>{}, 0, 0);
+        run_group(std::integral_constant<int, GC>{}, std::integral_constant<int, 9 - GC < GC ? 9 - GC : GC>{}, 0, 0);
+        if constexpr (2 * GC < 9)
+            run_group(std::integral_constant<int, 2 * GC>{}, std::integral_constant<int, 9 - 2 * GC>{}, 0, 0);
+    } else {
+        for (int a0 = a_first; a0 < a_first + a_count; a0 += G)
+            run_group(std::integral_constant<int, -1>{}, std::integral_constant<int, -1>{}, a0,
+                      min(G, a_first + a_count - a0));
     }
 }
 
@@ -471,11 +515,11 @@ __global__ void k_sk_read(const double *__restrict__ acc, double *__restrict__ o
 template <typename Tt> constexpr int SK_ROW_RADIX = 3;
 template <typename Tt> constexpr int SK_COL_RADIX = sizeof(Tt) == 4 ? 3 : 2;
 
-template <typename S, typename Tt, int RMAX, bool CACHE>
+template <typename S, typename Tt, int RMAX, bool CACHE, int GC = 0>
 void rows_kernel(const SkLaunch &a, int a_first, int a_count, int G, int threads, hipStream_t s)
 {
     const size_t lds = (size_t)sk_elem(sizeof(Tt) == 8 ? 0 : 1) * lds_padded((long long)G * (a.lds_rows / 2));
-    hipLaunchKernelGGL((k_sk_rows<S, Tt, RMAX, CACHE>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s, (const S *)a.f,
+    hipLaunchKernelGGL((k_sk_rows<S, Tt, RMAX, CACHE, GC>), dim3(xcd_grid(a.rows)), dim3(threads), lds, s, (const S *)a.f,
                        a.reps, a.sk, a.r0, a.r1, (long long)a.row_base, (long long)a.rows, a_first, a_count, G,
                        (long long)a.Ptot, (typename V2<Tt>::type *)a.spec, a.base, (const double2 *)a.tw, a.nmax);
 }
@@ -492,11 +536,14 @@ hipError_t launch_rows(int precision, const SkLaunch &a, int a_first, int a_coun
     const int threads = sk_threads(a.lds_rows);
     // FP32: with at most SK_CACHE_PAIRS node pairs per lane the nine moments stay in
     // registers across the mode groups (FP64 would spill)
-    const bool cache = precision != 0 && a_count > G && a.lds_rows / 2 <= SK_CACHE_PAIRS * threads;
+    const bool cache = precision != 0 && a_first == 0 && a_count == 9 && (G == 4 || G == 8) &&
+                       a.lds_rows / 2 <= SK_CACHE_PAIRS * threads;
     if (precision == 0)
         rows_kernel<double, double, SK_ROW_RADIX<double>, false>(a, a_first, a_count, G, threads, s);
+    else if (cache && G == 4)
+        rows_kernel<float, float, SK_ROW_RADIX<float>, true, 4>(a, a_first, a_count, G, threads, s);
     else if (cache)
-        rows_kernel<float, float, SK_ROW_RADIX<float>, true>(a, a_first, a_count, G, threads, s);
+        rows_kernel<float, float, SK_ROW_RADIX<float>, true, 8>(a, a_first, a_count, G, threads, s);
     else
         rows_kernel<float, float, SK_ROW_RADIX<float>, false>(a, a_first, a_count, G, threads, s);
     return hipGetLastError();
@@ -525,9 +572,11 @@ template <typename K> hipError_t lds_limit(K kernel, size_t bytes)
 
 template <typename S, typename Tt> hipError_t lds_limits_of(size_t rows, size_t cols)
 {
-    hipError_t e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, false>, rows);
-    if constexpr (sizeof(Tt) == 4)   // the register-cached row variant exists for FP32 only
-        if (e == hipSuccess) e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, true>, rows);
+    hipError_t e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, false, 0>, rows);
+    if constexpr (sizeof(Tt) == 4) {   // the register-cached row variants exist for FP32 only
+        if (e == hipSuccess) e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, true, 4>, rows);
+        if (e == hipSuccess) e = lds_limit(k_sk_rows<S, Tt, SK_ROW_RADIX<Tt>, true, 8>, rows);
+    }
     if (e == hipSuccess) e = lds_limit(k_sk_cols<Tt, false, SK_COL_RADIX<Tt>>, cols);
     if (e == hipSuccess) e = lds_limit(k_sk_cols<Tt, true, SK_COL_RADIX<Tt>>, cols);
     return e;
