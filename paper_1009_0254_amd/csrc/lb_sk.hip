@@ -153,6 +153,12 @@ struct SkRowPerm {
     }
 };
 
+// The FP32 columns (radix 8, remainder last, 1/16 pad): the stride-8 pass puts 16 consecutive
+// lanes on 8 bank pairs; swapping bits 3 and 4 of the lane's group index spreads them.
+struct SkColPerm {
+    __device__ unsigned operator()(int, int s, int rl) const { return s == 4 && rl == 3 ? (3u | 2u << 4 | 1u << 8) : 0u; }
+};
+
 // The rows' register-fed bit-reversed fill: lane e of a wave writes slot bitrev(pair) + pad,
 // which for consecutive pairs puts 16 lanes on 4 bank pairs; lanes of a 16-lane group take
 // pairs 4 apart instead (the wave still covers 64 consecutive pairs, so its loads touch the same
@@ -412,7 +418,8 @@ __global__ void __launch_bounds__(SK_THREADS)
         }
     }
     __syncthreads();
-    sk_fft<Tt, RMAX, P16>(X, L, logL, split == 1 ? C_ : 1, T, nmax, sh);
+    sk_fft<Tt, RMAX, P16, true, typename std::conditional<P16, SkColPerm, NoLanePerm>::type>(X, L, logL, split == 1 ? C_ : 1, T,
+                                                                                         nmax, sh);
     const int tot = (split == 1 ? C_ : 1) * L;
     auto power = [&](int e) {
         const C v = X[lds_at(e, sh)];
