@@ -552,6 +552,50 @@ void radial_metric(int nx, int ny, int *P, int *xwide, int *nbins)
     *nbins = (int)((s + *P) / (2 * *P)) + 1;
 }
 
+// Two-step launch shapes to time: widths 512, 256, 384, 448 with tiles of 32, 16 and 64 rows,
+// and for each width the tile heights whose workgroup lists just fill 2, 3, 4 or 6 rounds of the
+// workgroups resident at once (a launch whose last round is partly empty leaves CUs idle while it
+// drains; at 8192^2 and 256 lanes, 89-row tiles, three rounds: 2% faster than 32-row ones).
+std::vector<std::pair<int, int>> step2_shapes(const lb_handle *h)
+{
+    std::vector<std::pair<int, int>> shapes;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess)
+        ncu = 0;
+    int max_ny = 0;
+    for (const auto &d : h->reps) max_ny = std::max(max_ny, d.ny);
+    const bool plain = h->precision == LB_FP32, cn = !h->cn_reps.empty();
+    for (int bx : {512, 256, 384, 448}) {
+        std::vector<int> heights = {32, 16, 64};
+        // workgroups of tiles about `rows` high, and the resident ones
+        auto counts = [&](int rows, long long *slots) {
+            std::vector<Tile> t;
+            std::vector<int32_t> w;
+            const int gmax = make_tiles2(h->reps, bx, rows, t, w);
+            *slots = (long long)step2_blocks_per_cu(h->precision, plain, cn, bx, gmax) * ncu;
+            return (long long)w.size() - 1;
+        };
+        for (int r : {2, 3, 4, 6}) {
+            if (ncu == 0) break;
+            // the smallest height whose list fits r rounds (the count falls as the height grows)
+            int lo = STEP2_MIN_H, hi = std::max(STEP2_MIN_H, max_ny);
+            long long slots = 0;
+            if (counts(hi, &slots) > r * slots) continue;
+            while (lo < hi) {
+                const int mid = (lo + hi) / 2;
+                if (counts(mid, &slots) <= r * slots)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            if (std::find(heights.begin(), heights.end(), lo) == heights.end()) heights.push_back(lo);
+        }
+        for (int rows : heights) shapes.push_back({bx, rows});
+    }
+    return shapes;
+}
+
 // time a few steps of each candidate launch shape and keep the fastest: for k_step (one step
 // per launch) the strip width and rows per tile, for k_step2 (two steps) the workgroup width
 // and rows per tile; then the faster of the two kernels.  The trial steps read the current
@@ -606,8 +650,9 @@ lb_status autotune(lb_handle *h)
     if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) return LB_EDEVICE;
     hipEvent_t e0 = ev.a, e1 = ev.b;
     // every candidate is timed once after a warm-up, the three fastest of each kernel are timed
-    // again, and among those re-timings a later one replaces an earlier one only when at least
-    // 2% faster, so that near-ties resolve the same way on every device.  Trial length: at least
+    // again over eight times as many steps, and among those re-timings a later one replaces an
+    // earlier one only when at least 0.5% faster, so that near-ties resolve the same way on every
+    // device (LBF_TUNE_LOG prints the timings).  Trial length: at least
     // ~3 ms of steps (short trials of small lattices are noisy), from the first candidate's time
     // per step; ms is the time per step.
     int trial = 4;
@@ -631,36 +676,45 @@ lb_status autotune(lb_handle *h)
     };
     bool warmed = false;
     // candidates of one kernel in order of how often they win; returns the chosen one
-    auto tune = [&](int kk, const std::vector<int> &widths, const std::vector<int> &heights, Cand *best) -> lb_status {
+    typedef std::vector<std::pair<int, int>> Shapes;   // (width, rows)
+    auto tune = [&](int kk, const Shapes &shapes, Cand *best) -> lb_status {
         std::vector<Cand> cands;
-        for (int bx : widths) {
-            for (int rows : heights) {
-                float ms = 0;
-                if (!warmed) {   // clocks ramp up during the first launches
-                    for (int k = 0; k < 3; ++k) {
-                        lb_status st = time_shape(kk, bx, rows, &ms);
-                        if (st == LB_EDEVICE) return st;
-                    }
-                    if (ms > 0) trial = std::max(4, std::min(64, (int)ceilf(3.0f / ms)));
-                    warmed = true;
+        for (const auto &sh : shapes) {
+            const int bx = sh.first, rows = sh.second;
+            float ms = 0;
+            if (!warmed) {   // clocks ramp up during the first launches
+                for (int k = 0; k < 3; ++k) {
+                    lb_status st = time_shape(kk, bx, rows, &ms);
+                    if (st == LB_EDEVICE) return st;
                 }
-                lb_status st = time_shape(kk, bx, rows, &ms);
-                if (st == LB_EDEVICE) return st;
-                if (st == LB_OK) cands.push_back(Cand{kk, bx, rows, (int)cands.size(), ms});
+                if (ms > 0) trial = std::max(4, std::min(64, (int)ceilf(3.0f / ms)));
+                warmed = true;
             }
+            lb_status st = time_shape(kk, bx, rows, &ms);
+            if (st == LB_EDEVICE) return st;
+            if (st == LB_OK) cands.push_back(Cand{kk, bx, rows, (int)cands.size(), ms});
         }
         if (cands.empty()) return LB_EINVAL;
+        const bool log = getenv("LBF_TUNE_LOG") != nullptr;
+        if (log)
+            for (const auto &c : cands) fprintf(stderr, "[lbf tune] k=%d %d,%d: %.4f ms/step\n", kk, c.bx, c.rows, c.ms);
         std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
         if (cands.size() > 3) cands.resize(3);
+        // the three fastest again over eight times as many steps; that time decides (the minimum
+        // of two short trials favoured shapes whose short trials vary more)
+        const int short_trial = trial;
+        trial = 8 * short_trial;
         for (auto &c : cands) {
             float ms = 0;
             if (time_shape(kk, c.bx, c.rows, &ms) == LB_EDEVICE) return LB_EDEVICE;
-            c.ms = std::min(c.ms, ms);
+            c.ms = ms;
+            if (log) fprintf(stderr, "[lbf tune] k=%d %d,%d again: %.4f ms/step\n", kk, c.bx, c.rows, c.ms);
         }
+        trial = short_trial;
         std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.order < b.order; });
         float bm = 1e30f;
         for (const auto &c : cands)
-            if (c.ms < 0.98f * bm) {
+            if (c.ms < 0.995f * bm) {
                 bm = c.ms;
                 *best = c;
             }
@@ -668,14 +722,15 @@ lb_status autotune(lb_handle *h)
     };
     Cand b1{1, bx0, 16, 0, 1e30f}, b2{2, bx20, 16, 0, 1e30f};
     if (!pin1) {
-        std::vector<int> widths;
+        Shapes shapes;
         for (int bx : {512, 256, 128, 64})   // strips much wider than the narrowest replica only add idle lanes
-            if (bx <= std::max(2 * min_nx, 64)) widths.push_back(bx);
-        lb_status st = tune(1, widths, {16, 8, 4, 32, 64}, &b1);
+            if (bx <= std::max(2 * min_nx, 64))
+                for (int rows : {16, 8, 4, 32, 64}) shapes.push_back({bx, rows});
+        lb_status st = tune(1, shapes, &b1);
         if (st == LB_EDEVICE) return st;
     }
     if (!pin2 && force_k != 1) {
-        lb_status st = tune(2, {512, 256, 384, 448}, {32, 16, 64}, &b2);
+        lb_status st = tune(2, step2_shapes(h), &b2);
         if (st == LB_EDEVICE) return st;
     }
     if (hipMemcpyAsync(h->flags, &h->init_flags, sizeof(unsigned), hipMemcpyHostToDevice, h->stream) != hipSuccess)

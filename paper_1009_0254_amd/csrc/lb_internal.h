@@ -139,6 +139,8 @@ int make_tiles2(const std::vector<RepDesc> &reps, int bx, double h, std::vector<
 long long max_tiles2(const std::vector<int> &nx, const std::vector<int> &ny);
 hipError_t launch_step2(int precision, const Step2Launch &a, hipStream_t s);
 size_t step2_lds_bytes(int precision, int bx, int max_groups);
+// resident two-step workgroups of bx lanes (max_groups lane groups) per CU (0 if unknown)
+int step2_blocks_per_cu(int precision, bool plain, bool cn, int bx, int max_groups);
 // allow k_step2 the dynamic LDS of its largest configuration (512 lanes in 8 groups)
 hipError_t set_step2_lds_limit();
 

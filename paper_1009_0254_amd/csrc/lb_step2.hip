@@ -334,6 +334,25 @@ hipError_t set_step2_lds_limit()
     return e;
 }
 
+template <typename K> static int blocks_per_cu(K kernel, int bx, size_t lds)
+{
+    int nb = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kernel, bx, lds) == hipSuccess ? nb : 0;
+}
+
+int step2_blocks_per_cu(int precision, bool plain, bool cn, int bx, int max_groups)
+{
+    const size_t lds = step2_lds_bytes(precision, bx, max_groups);
+    if (precision == 0)
+        return cn ? blocks_per_cu(k_step2<double, double, false, true>, bx, lds)
+                  : blocks_per_cu(k_step2<double, double, false, false>, bx, lds);
+    if (plain)
+        return cn ? blocks_per_cu(k_step2<float, float, true, true>, bx, lds)
+                  : blocks_per_cu(k_step2<float, float, true, false>, bx, lds);
+    return cn ? blocks_per_cu(k_step2<float, float, false, true>, bx, lds)
+              : blocks_per_cu(k_step2<float, float, false, false>, bx, lds);
+}
+
 size_t step2_lds_bytes(int precision, int bx, int max_groups)
 {
     const unsigned W = (unsigned)(bx / max_groups + 2);
