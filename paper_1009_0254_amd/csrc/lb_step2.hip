@@ -102,7 +102,10 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
     // needed read them.
     const bool whole = nx <= BG;
     const int wl0 = (int)((tid - grp * BG) / 64 * 64);   // first lane of this wave in its group
-    const bool idle = gidle || (whole ? wl0 >= (int)nx : wl0 >= (int)nx - tl.x0 + 6);   // uniform per wave
+    // uniform per wave; readfirstlane says so to the compiler, which otherwise treats branches on
+    // it as divergent and moves the pull offsets into vector registers (a waterfall loop per load)
+    const bool idle = __builtin_amdgcn_readfirstlane(
+        (int)(gidle || (whole ? wl0 >= (int)nx : wl0 >= (int)nx - tl.x0 + 6))) != 0;
     unsigned xw;
     if (whole) {
         xw = l < nx ? l : l % nx;
