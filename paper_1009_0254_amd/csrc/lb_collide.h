@@ -74,6 +74,25 @@ __device__ __forceinline__ void stencil9(R C, R E, R Wv, R N, R NE, R NW, R Sv, 
     gy = (4 * (N - Sv) + (NE - SE) + (NW - SW)) * (R)(1.0 / 12.0);
 }
 
+// Uniform constants that the collision's FMAs meet beside another uniform operand: a vector
+// instruction reads at most one scalar register, so each such FMA would first move one of them
+// into a vector register, per node.  Copied into vector registers once per kernel instead
+// (FP32; the FP64 kernels have no registers to spare and keep the moves).
+template <typename R> struct VConsts {
+    R dp3, A, k44x2, k49m, k99x125;
+};
+template <typename R> __device__ __forceinline__ R vreg(R x) { return x; }
+template <> __device__ __forceinline__ float vreg<float>(float x)
+{
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+template <typename R> __device__ __forceinline__ VConsts<R> vconsts(const Consts<R> &c)
+{
+    return VConsts<R>{vreg<R>(c.dp3), vreg<R>(c.A), vreg<R>(c.k44x2), vreg<R>(c.k49m), vreg<R>(c.k99x125)};
+}
+
 // ------------------------------------------------------------------ the collision
 // Deviations df_i = f_i - fbar_i from the rest state fbar = T^-1 m^eq(rho0, u = 0) in,
 // post-collision deviations out.  The moments of df are m - mbar (mbar: rho0 and the rest
@@ -82,7 +101,8 @@ __device__ __forceinline__ void stencil9(R C, R E, R Wv, R N, R NE, R NW, R Sv, 
 // status bits (LB_FLAG_*).
 // CN: the replica set has correlated noise (noise == 2 possible)
 template <typename R, bool CN>
-__device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Consts<R> &c, uint32_t noise,
+__device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Consts<R> &c, const VConsts<R> &vk,
+                                            uint32_t noise,
                                             uint32_t node, uint32_t rep, unsigned long long t, uint32_t k0,
                                             uint32_t k1, R xi4, R xi9)
 {
@@ -113,7 +133,7 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
     // local thermodynamics (Sec. II.A): pex = p0 - rho sigma_s^2 relative to its rest value,
     // from the exact Taylor expansion at rho0 in drho
     const R kap = c.kappa;
-    const R pex = drho * (c.dp1 + drho * (c.dp2 + drho * (c.dp3 + drho * c.dp4)));
+    const R pex = drho * (c.dp1 + drho * (c.dp2 + drho * (vk.dp3 + drho * c.dp4)));
     const R piso = pex - kap * rho * lap;
 
     // Table II (C_n = 0), minus the rest values mbar_4 = 6 pex(rho0), mbar_9 = -6 pex(rho0)
@@ -154,10 +174,10 @@ __device__ __forceinline__ unsigned collide(R f[Q], R lap, R gx, R gy, const Con
             rr = 0;
         }
         const R xx = c.xr0 + (rr - c.rho0);
-        const R cs2 = c.c0sq + rr * (c.A + c.B3 * (xx * xx));
-        const R a44 = c.k44x2 + c.k44n3 * cs2;        // k44 (2 - 3 c_s^2)
-        const R a49 = c.k49 * cs2 + c.k49m;           // k49 (c_s^2 - 1/3)
-        const R a99 = c.k99x125 + c.k99n075 * cs2;    // k99 (5/4 - 3 c_s^2 / 4)
+        const R cs2 = c.c0sq + rr * (vk.A + c.B3 * (xx * xx));
+        const R a44 = vk.k44x2 + c.k44n3 * cs2;        // k44 (2 - 3 c_s^2)
+        const R a49 = c.k49 * cs2 + vk.k49m;           // k49 (c_s^2 - 1/3)
+        const R a99 = vk.k99x125 + c.k99n075 * cs2;    // k99 (5/4 - 3 c_s^2 / 4)
         R nu[6];
         normals6s<R>(node, rep, t, k0, k1, fsqrt<R>(rr * c.kT3), nu);
         R l44 = 0, l94 = 0;

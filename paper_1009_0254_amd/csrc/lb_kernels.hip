@@ -38,6 +38,7 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
     const Tile tl = tiles[blockIdx.x];
     const RepDesc &d = reps[tl.rep];
     const Consts<R> &c = consts<R>(d);
+    const VConsts<R> vk = vconsts<R>(c);
     const unsigned nx = (unsigned)d.nx, ny = (unsigned)d.ny;
     const unsigned long long pitch = 9ull * nx;   // elements per lattice row
     constexpr unsigned ESZ = sizeof(S);
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(512) k_step(const S *__restrict__ xi, const S 
             xi4 = (R)xr[0];
             xi9 = (R)xr[1];
         }
-        st |= collide<R, CN>(cur, lap, gx, gy, c, d.noise, (unsigned)y * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi,
+        st |= collide<R, CN>(cur, lap, gx, gy, c, vk, d.noise, (unsigned)y * nx + xw, d.rep_id, t, d.seed_lo, d.seed_hi,
                          xi4, xi9);
         const auto W = row_rsrc(Qo + (unsigned long long)(unsigned)y * pitch, rowb);
         if (store) {

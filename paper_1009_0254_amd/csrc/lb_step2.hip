@@ -78,6 +78,7 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
     const bool gidle = tl.rep < 0;
     const RepDesc &d = reps[gidle ? 0 : tl.rep];
     const Consts<R> &c = consts<R>(d);
+    const VConsts<R> vk = vconsts<R>(c);
     const unsigned nx = (unsigned)d.nx, ny = (unsigned)d.ny;
     const unsigned long long pitch = 9ull * nx;
     constexpr unsigned ES = sizeof(S);
@@ -248,7 +249,7 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
                 xi4 = (R)xr[0];
                 xi9 = (R)xr[1];
             }
-            const unsigned s2 = collide<R, CN>(g, lap, gx, gy, c, d.noise, y * nx + xw, d.rep_id, t + 1, d.seed_lo,
+            const unsigned s2 = collide<R, CN>(g, lap, gx, gy, c, vk, d.noise, y * nx + xw, d.rep_id, t + 1, d.seed_lo,
                                                d.seed_hi, xi4, xi9);
             const auto Wr = row_rsrc(Qo + (unsigned long long)y * pitch, rowb);
             if (store2) {
@@ -275,7 +276,7 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
                 xi4 = (R)xr[0];
                 xi9 = (R)xr[1];
             }
-            const unsigned s1f = collide<R, CN>(cur, lap, gx, gy, c, d.noise, yr * nx + xw, d.rep_id, t, d.seed_lo,
+            const unsigned s1f = collide<R, CN>(cur, lap, gx, gy, c, vk, d.noise, yr * nx + xw, d.rep_id, t, d.seed_lo,
                                                 d.seed_hi, xi4, xi9);
             st |= s1f;
             S o[Q];
