@@ -75,18 +75,27 @@ __device__ __forceinline__ void stencil9(R C, R E, R Wv, R N, R NE, R NW, R Sv, 
 }
 
 // Uniform constants that the collision's FMAs meet beside another uniform operand: a vector
-// instruction reads at most one scalar register, so each such FMA would first move one of them
-// into a vector register, per node.  Copied into vector registers once per kernel instead
-// (FP32; the FP64 kernels have no registers to spare and keep the moves).
+// instruction reads at most one scalar register (pair), so each such FMA would first move one of
+// them into vector registers, per node.  Copied into vector registers once per kernel instead.
 template <typename R> struct VConsts {
     R dp3, A, k44x2, k49m, k99x125;
 };
-template <typename R> __device__ __forceinline__ R vreg(R x) { return x; }
-template <> __device__ __forceinline__ float vreg<float>(float x)
+__device__ __forceinline__ uint32_t vreg32(uint32_t x)
 {
-    float r;
+    uint32_t r;
     asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
     return r;
+}
+template <typename R> __device__ __forceinline__ R vreg(R x);
+template <> __device__ __forceinline__ float vreg<float>(float x)
+{
+    return __builtin_bit_cast(float, vreg32(__builtin_bit_cast(uint32_t, x)));
+}
+template <> __device__ __forceinline__ double vreg<double>(double x)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long lo = vreg32((uint32_t)u), hi = vreg32((uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
 }
 template <typename R> __device__ __forceinline__ VConsts<R> vconsts(const Consts<R> &c)
 {
