@@ -77,6 +77,8 @@ __device__ __forceinline__ void stencil9(R C, R E, R Wv, R N, R NE, R NW, R Sv, 
 // Uniform constants that the collision's FMAs meet beside another uniform operand: a vector
 // instruction reads at most one scalar register (pair), so each such FMA would first move one of
 // them into vector registers, per node.  Copied into vector registers once per kernel instead.
+// The copy reads a scalar register: c must be the same for every lane of a wave (the step
+// kernels take it from their tile's replica, one replica per wave).
 template <typename R> struct VConsts {
     R dp3, A, k44x2, k49m, k99x125;
 };
