@@ -59,12 +59,17 @@ __device__ __forceinline__ void bits21(uint4 x, uint32_t b[6])
 // Box-Muller on u = (b + 1/2) 2^-21 (exact in float and double)
 template <typename R> struct Gauss;
 
+// the angle's revolutions plus one whole turn, 1 + (b + 1/2) 2^-21, assembled from the bits
+// (exponent of 1, mantissa 4 b + 2): v_sin/v_cos take revolutions, so the added turn changes
+// nothing and saves the conversion
+__device__ __forceinline__ float turn21(uint32_t b) { return __builtin_bit_cast(float, 0x3F800002u | (b << 2)); }
+
 template <> struct Gauss<float> {
     static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, float &a, float &b)
     {
 #pragma clang fp contract(on)
         const float ue = ((float)be + 0.5f) * 0x1p-21f;
-        const float uo = ((float)bo + 0.5f) * 0x1p-21f;
+        const float uo = turn21(bo);
         // -2 ln u = -2 ln(2) log2(u); v_log_f32 is log2, v_sin/v_cos take revolutions
         const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ue));
         a = r * __builtin_amdgcn_cosf(uo);
@@ -92,7 +97,7 @@ template <> __device__ __forceinline__ void gauss_pair_scaled<float>(uint32_t be
 {
 #pragma clang fp contract(on)
     const float ue = ((float)be + 0.5f) * 0x1p-21f;
-    const float uo = ((float)bo + 0.5f) * 0x1p-21f;
+    const float uo = turn21(bo);
     const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ue)) * scale;
     a = r * __builtin_amdgcn_cosf(uo);
     b = r * __builtin_amdgcn_sinf(uo);
