@@ -172,7 +172,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the lattice would shard as y-slabs with a 2-row halo exchange per step; not built).",
               file=sys.stderr)
         sys.exit(2)

@@ -28,10 +28,10 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         // The callers vary only the first counter word across lanes, so some words stay uniform
-        // for a round or two: round 0's products of words 2 and 3 and its x, y; round 1's
-        // hi0, lo0 (from that x).  There the exclusive ors pair the uniform operands first
-        // (scalar instructions), as a three-way vector or may read only one scalar operand and
-        // would need a move for the second; from round 2 on one v_bitop3 each.
+        // for the first rounds: the first round's products of words 2 and 3 and its x, y; the
+        // second round's hi0, lo0 (from that x).  There the exclusive ors pair the uniform
+        // operands first (scalar instructions), as a three-way vector or may read only one scalar
+        // operand and would need a move for the second; from the third round on one v_bitop3 each.
         if (r == 0)
             c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         else if (r == 1)
