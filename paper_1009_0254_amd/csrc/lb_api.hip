@@ -566,8 +566,17 @@ std::vector<std::pair<int, int>> step2_shapes(const lb_handle *h)
     int max_ny = 0;
     for (const auto &d : h->reps) max_ny = std::max(max_ny, d.ny);
     const bool plain = h->precision == LB_FP32, cn = !h->cn_reps.empty();
+    // Near-ties go to the earlier candidate.  For a population buffer of more than 1 GiB the
+    // heights that just fill whole rounds of resident workgroups come first (at 8192^2 the 67- and
+    // 89-row tiles run about 1% faster than 32-row ones in the kernel trace, within the tuner's
+    // margin); for smaller states 32, 16 and 64 rows come first: their trials read an input that
+    // the 256 MB last-level cache partly holds from the trial before, which ranks the shapes
+    // differently from the running lattice (the ensemble's 512 x 64 tiles: 0.126 ms per step in
+    // the trials against 512 x 32's 0.128, 0.131 against 0.127 when stepping)
+    const bool fill_first = (double)h->L.nodes * 9 * elem_size(h->precision) > (double)(1ll << 30);
     for (int bx : {512, 256, 384, 448}) {
-        std::vector<int> heights = {32, 16, 64};
+        std::vector<int> heights;
+        if (!fill_first) heights = {32, 16, 64};
         // workgroups of tiles about `rows` high, and the resident ones
         auto counts = [&](int rows, long long *slots) {
             std::vector<Tile> t;
@@ -576,7 +585,7 @@ std::vector<std::pair<int, int>> step2_shapes(const lb_handle *h)
             *slots = (long long)step2_blocks_per_cu(h->precision, plain, cn, bx, gmax) * ncu;
             return (long long)w.size() - 1;
         };
-        for (int r : {2, 3, 4, 6}) {
+        for (int r : {4, 3, 6, 2}) {
             if (ncu == 0) break;
             // the smallest height whose list fits r rounds (the count falls as the height grows)
             int lo = STEP2_MIN_H, hi = std::max(STEP2_MIN_H, max_ny);
@@ -591,6 +600,8 @@ std::vector<std::pair<int, int>> step2_shapes(const lb_handle *h)
             }
             if (std::find(heights.begin(), heights.end(), lo) == heights.end()) heights.push_back(lo);
         }
+        for (int rows : {32, 16, 64})
+            if (std::find(heights.begin(), heights.end(), rows) == heights.end()) heights.push_back(rows);
         for (int rows : heights) shapes.push_back({bx, rows});
     }
     return shapes;
