@@ -34,6 +34,11 @@
 //   F56[5][2][W]   populations 5, 6 of the last five
 //   F78[3][2][W]   populations 7, 8 of the last three
 // (each kept as long as a density pull or a collision pull still reads it).
+//
+// BGC > 0: the launch holds one group of BGC lanes per workgroup (a single lattice's strips), so
+// W is a compile-time constant; F13 and F56 then hold six rows and the row loop is unrolled six
+// times, which makes every ring slot a compile-time offset (an LDS instruction's immediate)
+// instead of an address computed per access.
 
 #include "lb_collide.h"
 #include "lb_internal.h"
@@ -43,14 +48,14 @@
 
 namespace lbf {
 
-template <typename S, typename R> constexpr unsigned step2_group_bytes(unsigned W)
+template <typename S, typename R, int BGC = 0> constexpr unsigned step2_group_bytes(unsigned W)
 {
-    return W * (6 * (unsigned)sizeof(R) + 24 * (unsigned)sizeof(S));
+    return W * (6 * (unsigned)sizeof(R) + (BGC ? 30u : 24u) * (unsigned)sizeof(S));
 }
 
 // CN: the replica set has correlated noise; replicas with noise == 2 add the fields of step t
 // (xi) and t + 1 (xi + xi_plane) to modes 4 and 9 (see k_step).
-template <typename S, typename R, bool PLAIN, bool CN>
+template <typename S, typename R, bool PLAIN, bool CN, int BGC = 0>
 __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long long xi_plane,
                                                const S *__restrict__ fin, S *__restrict__ fout,
                                                const RepDesc *__restrict__ reps, const Tile *__restrict__ tiles,
@@ -59,12 +64,12 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
                                                unsigned *__restrict__ flags, int toff)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const unsigned BX = blockDim.x;
+    const unsigned BX = BGC ? (unsigned)BGC : blockDim.x;
     const int gbeg = wgs[blockIdx.x];
-    const unsigned G = (unsigned)(wgs[blockIdx.x + 1] - gbeg);
+    const unsigned G = BGC ? 1u : (unsigned)(wgs[blockIdx.x + 1] - gbeg);
     const unsigned BG = BX / G;
     const unsigned tid = threadIdx.x;
-    const unsigned grp = __builtin_amdgcn_readfirstlane(tid / BG);   // uniform per wave
+    const unsigned grp = BGC ? 0u : __builtin_amdgcn_readfirstlane(tid / BG);   // uniform per wave
     const unsigned l = tid - grp * BG;
     const unsigned W = BG + 2;
 
@@ -87,12 +92,13 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
     const S *__restrict__ P = fin + d.off;
     S *__restrict__ Qo = fout + d.off;
 
-    unsigned char *gb = smem_raw + grp * step2_group_bytes<S, R>(W);
+    unsigned char *gb = smem_raw + grp * step2_group_bytes<S, R, BGC>(W);
     R *ring1 = reinterpret_cast<R *>(gb);
     R *ring2 = ring1 + 3 * W;
+    constexpr unsigned N13 = BGC ? 6 : 4, N56 = BGC ? 6 : 5;
     S *F13 = reinterpret_cast<S *>(ring2 + 3 * W);
-    S *F56 = F13 + 8 * W;
-    S *F78 = F56 + 10 * W;
+    S *F56 = F13 + 2 * N13 * W;
+    S *F78 = F56 + 2 * N56 * W;
 
     // columns.  whole: lane l is column l (lanes past the row duplicate column l mod nx and
     // never store; whole waves past it only keep the barriers).  strip: lane l is column
@@ -201,17 +207,35 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
         g[7] = (R)f78[ip];
         g[8] = (R)f78[W + im];
     };
-    // LDS row slots of the stage-1 output row rho = ys0 + j
-    auto s13 = [&](int j) { return F13 + (unsigned)(j & 3) * 2 * W; };
-    auto s56 = [&](int j) { return F56 + (unsigned)(j % 5) * 2 * W; };
-    auto s78 = [&](int j) { return F78 + (unsigned)(j % 3) * 2 * W; };
+    // LDS row slots of the stage-1 output row rho = ys0 + k + J, for the iteration k whose index
+    // in the unrolled group is U (k = U mod the group's length)
+    constexpr int UN = BGC ? 6 : 3;
+    auto s13 = [&](auto Uc, auto Jc, int k) {
+        constexpr int U = decltype(Uc)::value, J = decltype(Jc)::value;
+        if constexpr (BGC) return F13 + (unsigned)((U + J + 6) % 6) * 2 * W;
+        else return F13 + (unsigned)((k + J) & 3) * 2 * W;
+    };
+    auto s56 = [&](auto Uc, auto Jc, int k) {
+        constexpr int U = decltype(Uc)::value, J = decltype(Jc)::value;
+        if constexpr (BGC) return F56 + (unsigned)((U + J + 6) % 6) * 2 * W;
+        else return F56 + (unsigned)((k + J) % 5) * 2 * W;
+    };
+    auto s78 = [&](auto Uc, auto Jc, int) {
+        constexpr int U = decltype(Uc)::value, J = decltype(Jc)::value;
+        return F78 + (unsigned)((U + J + 6) % 3) * 2 * W;
+    };
+    using Jm4 = std::integral_constant<int, -4>;
+    using Jm3 = std::integral_constant<int, -3>;
+    using Jm2 = std::integral_constant<int, -2>;
+    using Jm1 = std::integral_constant<int, -1>;
+    using J0 = std::integral_constant<int, 0>;
 
     // one iteration; K = k mod 3 fixes the slots of the three-row rings (all modulo 3):
     //   ring1 (rho(t)):    row rho at slot (rho - ys0 + 1), so row r + j at K + 1 + j
     //   ring2 (rho(t+1)):  row rho at slot (rho - ys0), so row r - 2 + j at K + 1 + j
     //   F0r, F2r, F4r:     row rho at slot (rho - ys0), row r at K
-    auto iter = [&](auto Kc, int k, R cur[Q], R nxt[Q], R nn[Q]) {
-        constexpr unsigned K = decltype(Kc)::value;
+    auto iter = [&](auto Uc, int k, R cur[Q], R nxt[Q], R nn[Q]) {
+        constexpr unsigned K = decltype(Uc)::value % 3;
         const int r = ys0 + k;
         const bool s1 = !idle && r < ys1;                    // stage 1 on row r
         const bool p2 = !idle && r >= ys0 + 3 && r <= ys1;   // stage-2 density of row r - 2
@@ -224,7 +248,7 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
         }
         if (p2) {
             R g[Q];
-            pull2(F0r[(K + 1) % 3], F2r[K], F4r[(K + 2) % 3], s13(k - 2), s56(k - 3), s78(k - 1), g);
+            pull2(F0r[(K + 1) % 3], F2r[K], F4r[(K + 2) % 3], s13(Uc, Jm2{}, k), s56(Uc, Jm3{}, k), s78(Uc, Jm1{}, k), g);
             ring2[((K + 1) % 3) * W + i0] = dens(g);
         }
         __syncthreads();
@@ -232,7 +256,7 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
         // row r and its output
         if (c2) {
             R g[Q];
-            pull2(F0r[K], F2x, F4r[(K + 1) % 3], s13(k - 3), s56(k - 4), s78(k - 2), g);
+            pull2(F0r[K], F2x, F4r[(K + 1) % 3], s13(Uc, Jm3{}, k), s56(Uc, Jm4{}, k), s78(Uc, Jm2{}, k), g);
             // densities of rows r - 4, r - 3, r - 2 at ring2 slots K + 2, K, K + 1
             const unsigned s0 = K * W, sm = ((K + 2) % 3) * W, sp = ((K + 1) % 3) * W;
             R lap, gx, gy;
@@ -286,7 +310,7 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
             F2x = F2r[K];
             F2r[K] = o[2];
             F4r[K] = o[4];
-            S *f13 = s13(k), *f56 = s56(k), *f78 = s78(k);
+            S *f13 = s13(Uc, J0{}, k), *f56 = s56(Uc, J0{}, k), *f78 = s78(Uc, J0{}, k);
             f13[i0] = o[1];
             f13[W + i0] = o[3];
             f56[i0] = o[5];
@@ -296,13 +320,21 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
         }
         __syncthreads();
     };
-    using K0 = std::integral_constant<unsigned, 0>;
-    using K1 = std::integral_constant<unsigned, 1>;
-    using K2 = std::integral_constant<unsigned, 2>;
-    for (int k = 0; k < nit; k += 3) {
-        iter(K0{}, k, fa, fb, fc);
-        if (k + 1 < nit) iter(K1{}, k + 1, fb, fc, fa);
-        if (k + 2 < nit) iter(K2{}, k + 2, fc, fa, fb);
+    using U0 = std::integral_constant<int, 0>;
+    using U1 = std::integral_constant<int, 1>;
+    using U2 = std::integral_constant<int, 2>;
+    using U3 = std::integral_constant<int, 3>;
+    using U4 = std::integral_constant<int, 4>;
+    using U5 = std::integral_constant<int, 5>;
+    for (int k = 0; k < nit; k += UN) {
+        iter(U0{}, k, fa, fb, fc);
+        if (k + 1 < nit) iter(U1{}, k + 1, fb, fc, fa);
+        if (k + 2 < nit) iter(U2{}, k + 2, fc, fa, fb);
+        if constexpr (UN == 6) {
+            if (k + 3 < nit) iter(U3{}, k + 3, fa, fb, fc);
+            if (k + 4 < nit) iter(U4{}, k + 4, fb, fc, fa);
+            if (k + 5 < nit) iter(U5{}, k + 5, fc, fa, fb);
+        }
     }
     // the stage-1 results of a storing lane are those of nodes whose second step it stores (its
     // column; rows outside the tile are also other tiles' rows), so the flags of every node and
@@ -310,21 +342,49 @@ __global__ void __launch_bounds__(512) k_step2(const S *__restrict__ xi, long lo
     if (st && store2) atomicOr(flags, st);
 }
 
-template <typename S, typename R, bool PLAIN, bool CN> static void launch_step2_t(const Step2Launch &a, hipStream_t s)
+// the group-width specialisation a launch takes: BGC = bx for one group per workgroup of 256 or
+// 512 lanes in FP32 storage (the FP64 loop unrolled six times would outgrow the instruction
+// cache), else 0 (runtime group width)
+static int step2_bgc(int precision, int bx, int max_groups)
 {
-    const size_t lds = (size_t)a.max_groups * step2_group_bytes<S, R>((unsigned)(a.bx / a.max_groups + 2));
-    hipLaunchKernelGGL((k_step2<S, R, PLAIN, CN>), dim3(a.nwg), dim3(a.bx), lds, s, (const S *)a.xi,
+    return precision != 0 && max_groups == 1 && (bx == 256 || bx == 512) ? bx : 0;
+}
+
+template <typename S, typename R, bool PLAIN, bool CN, int BGC> static void launch_step2_b(const Step2Launch &a, hipStream_t s)
+{
+    const size_t lds = (size_t)a.max_groups * step2_group_bytes<S, R, BGC>((unsigned)(a.bx / a.max_groups + 2));
+    hipLaunchKernelGGL((k_step2<S, R, PLAIN, CN, BGC>), dim3(a.nwg), dim3(a.bx), lds, s, (const S *)a.xi,
                        (long long)a.xi_plane, (const S *)a.fin, (S *)a.fout, a.reps, a.tiles, a.wgs, a.tdev, a.flags,
                        a.toff);
 }
 
-template <typename S, typename R, bool PLAIN> static hipError_t set_step2_limit(int bytes)
+template <typename S, typename R, bool PLAIN, bool CN> static void launch_step2_t(const Step2Launch &a, hipStream_t s)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)k_step2<S, R, PLAIN, false>,
+    if constexpr (sizeof(S) == 4) {
+        const int bgc = step2_bgc(1, a.bx, a.max_groups);
+        if (bgc == 256) return launch_step2_b<S, R, PLAIN, CN, 256>(a, s);
+        if (bgc == 512) return launch_step2_b<S, R, PLAIN, CN, 512>(a, s);
+    }
+    launch_step2_b<S, R, PLAIN, CN, 0>(a, s);
+}
+
+template <typename S, typename R, bool PLAIN, int BGC> static hipError_t set_step2_limit_b(int bytes)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)k_step2<S, R, PLAIN, false, BGC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_step2<S, R, PLAIN, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                bytes);
+        e = hipFuncSetAttribute((const void *)k_step2<S, R, PLAIN, true, BGC>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+}
+
+template <typename S, typename R, bool PLAIN> static hipError_t set_step2_limit(int bytes)
+{
+    hipError_t e = set_step2_limit_b<S, R, PLAIN, 0>(bytes);
+    if constexpr (sizeof(S) == 4) {
+        if (e == hipSuccess) e = set_step2_limit_b<S, R, PLAIN, 256>((int)step2_group_bytes<S, R, 256>(258));
+        if (e == hipSuccess) e = set_step2_limit_b<S, R, PLAIN, 512>((int)step2_group_bytes<S, R, 512>(514));
+    }
     return e;
 }
 
@@ -344,23 +404,32 @@ template <typename K> static int blocks_per_cu(K kernel, int bx, size_t lds)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)kernel, bx, lds) == hipSuccess ? nb : 0;
 }
 
+template <bool PLAIN, int BGC> static int blocks_per_cu_f(bool cn, int bx, size_t lds)
+{
+    return cn ? blocks_per_cu(k_step2<float, float, PLAIN, true, BGC>, bx, lds)
+              : blocks_per_cu(k_step2<float, float, PLAIN, false, BGC>, bx, lds);
+}
+
 int step2_blocks_per_cu(int precision, bool plain, bool cn, int bx, int max_groups)
 {
     const size_t lds = step2_lds_bytes(precision, bx, max_groups);
     if (precision == 0)
         return cn ? blocks_per_cu(k_step2<double, double, false, true>, bx, lds)
                   : blocks_per_cu(k_step2<double, double, false, false>, bx, lds);
+    const int bgc = step2_bgc(precision, bx, max_groups);
     if (plain)
-        return cn ? blocks_per_cu(k_step2<float, float, true, true>, bx, lds)
-                  : blocks_per_cu(k_step2<float, float, true, false>, bx, lds);
-    return cn ? blocks_per_cu(k_step2<float, float, false, true>, bx, lds)
-              : blocks_per_cu(k_step2<float, float, false, false>, bx, lds);
+        return bgc == 256 ? blocks_per_cu_f<true, 256>(cn, bx, lds)
+                          : bgc == 512 ? blocks_per_cu_f<true, 512>(cn, bx, lds) : blocks_per_cu_f<true, 0>(cn, bx, lds);
+    return bgc == 256 ? blocks_per_cu_f<false, 256>(cn, bx, lds)
+                      : bgc == 512 ? blocks_per_cu_f<false, 512>(cn, bx, lds) : blocks_per_cu_f<false, 0>(cn, bx, lds);
 }
 
 size_t step2_lds_bytes(int precision, int bx, int max_groups)
 {
     const unsigned W = (unsigned)(bx / max_groups + 2);
-    return (size_t)max_groups * (precision == 0 ? step2_group_bytes<double, double>(W) : step2_group_bytes<float, float>(W));
+    if (precision == 0) return (size_t)max_groups * step2_group_bytes<double, double>(W);
+    return (size_t)max_groups * (step2_bgc(precision, bx, max_groups) ? step2_group_bytes<float, float, 1>(W)
+                                                                     : step2_group_bytes<float, float>(W));
 }
 
 template <typename S, typename R, bool PLAIN> static void launch_step2_cn(const Step2Launch &a, hipStream_t s)
@@ -383,3 +452,4 @@ hipError_t launch_step2(int precision, const Step2Launch &a, hipStream_t s)
 }
 
 }  // namespace lbf
+
