@@ -145,10 +145,20 @@ DET = [
     ("wave_ragged", lambda: W.wave(W.single_phase(100, 37, kT=0, tau_bulk=0.7, tau_q=0.9), 3, 2, 1e-4, 1e-4, 0),
      100, 1e-5),
     ("tiny", lambda: W.wave(W.single_phase(3, 5, kT=0), 1, 1, 1e-4, 1e-4, 0), 4, 1e-5),
+    # the 3x5 lattice's slowest wave (k = 2 pi/5 along y) over 40 steps, in which it decays by
+    # ~5e-3; compared about each side's mean (see MEAN_REMOVED)
+    ("tiny_40", lambda: W.wave(W.single_phase(3, 5, kT=0), 0, 1, 1e-3, 1e-3, 0), 40, 1e-5),
     ("flow", lambda: W.wave(W.single_phase(96, 64, kT=0), 2, 1, 1e-4, 0, 1e-4, U=0.02), 300, 6e-4),
     ("slab", lambda: W.slab(64, 128, kT=0), 500, 1e-5),
     ("spinodal", lambda: W.spinodal(128, 96, kT=0, amp=0.01, seed=2), 300, 1e-5),
 ]
+
+
+# Cases compared as fluctuations about each side's own lattice mean.  The means of rho, j_x and
+# j_y are conserved totals, so in FP32-shifted storage they keep the one rounding of the stored
+# initial state (~1e-11 per node at amplitude 1e-3) while the decaying wave's range shrinks below
+# it; the totals have their own conservation tests.
+MEAN_REMOVED = {"tiny_40"}
 
 
 @pytest.mark.parametrize("label,cfgf,steps,tol32", DET, ids=[d[0] for d in DET])
@@ -156,6 +166,9 @@ DET = [
 def test_deterministic_parity(label, cfgf, steps, tol32, precision):
     cfg = cfgf()
     mg, mo = run_pair(cfg, precision, steps, chunks=2)
+    if label in MEAN_REMOVED:
+        mg = mg - mg.mean(axis=(1, 2), keepdims=True)
+        mo = mo - mo.mean(axis=(1, 2), keepdims=True)
     e = rel_err(mg, mo)
     if precision == 0:
         ok, err = abs_ok(mg, mo)
