@@ -552,7 +552,8 @@ void radial_metric(int nx, int ny, int *P, int *xwide, int *nbins)
     *nbins = (int)((s + *P) / (2 * *P)) + 1;
 }
 
-// Two-step launch shapes to time: widths 512, 256, 384, 448 with tiles of 32, 16 and 64 rows,
+// Two-step launch shapes to time: widths 512, 256, 384, 448 (256 first for a population buffer of
+// more than 1 GiB) with tiles of 32, 16 and 64 rows,
 // and for each width the tile heights whose workgroup lists just fill 2, 3, 4 or 6 rounds of the
 // workgroups resident at once (a launch whose last round is partly empty leaves CUs idle while it
 // drains; at 8192^2 and 256 lanes, 89-row tiles, three rounds: 2% faster than 32-row ones).
@@ -574,7 +575,11 @@ std::vector<std::pair<int, int>> step2_shapes(const lb_handle *h)
     // differently from the running lattice (the ensemble's 512 x 64 tiles: 0.126 ms per step in
     // the trials against 512 x 32's 0.128, 0.131 against 0.127 when stepping)
     const bool fill_first = (double)h->L.nodes * 9 * elem_size(h->precision) > (double)(1ll << 30);
-    for (int bx : {512, 256, 384, 448}) {
+    // and for those large states the 256-lane strips come first: over 600 steps of the 8192^2
+    // lattice on one box, 256 x 67 and 256 x 32 tiles ran 0.630 and 0.631 ms per step, every
+    // 512-lane shape 0.638-0.657, while the short trials ranked 512 x 92 within 1% of them
+    const std::vector<int> widths = fill_first ? std::vector<int>{256, 512, 384, 448} : std::vector<int>{512, 256, 384, 448};
+    for (int bx : widths) {
         std::vector<int> heights;
         if (!fill_first) heights = {32, 16, 64};
         // workgroups of tiles about `rows` high, and the resident ones
@@ -662,8 +667,12 @@ lb_status autotune(lb_handle *h)
     hipEvent_t e0 = ev.a, e1 = ev.b;
     // every candidate is timed once after a warm-up, the three fastest of each kernel (up to six
     // when they are close) are timed again over four times as many steps, and among those
-    // re-timings a later one replaces an earlier one only when at least 0.5% faster, so that
-    // near-ties resolve the same way on every device (LBF_TUNE_LOG prints the timings).  Trial
+    // re-timings a later one replaces an earlier one only when at least 1.5% faster, so that
+    // near-ties resolve the same way on every device (LBF_TUNE_LOG prints the timings).  The
+    // margin also covers what these ~40 ms trials miss: they run 3-4% faster than the sustained
+    // rate, and more so for short tiles, whose recomputed halo rows cost more at the lower clock
+    // of a long run (8192^2: 256 x 16 two-step tiles 0.6147 ms per step in the trial, 0.6415 over
+    // 600 steps; 256 x 67 0.6200 and 0.6290).  Trial
     // length: at least ~10 ms of steps, from the first candidate's time per step; ms is the time
     // per step.
     int trial = 4;
@@ -736,7 +745,7 @@ lb_status autotune(lb_handle *h)
         std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.order < b.order; });
         float bm = 1e30f;
         for (const auto &c : cands)
-            if (c.ms < 0.995f * bm) {
+            if (c.ms < 0.985f * bm) {
                 bm = c.ms;
                 *best = c;
             }
