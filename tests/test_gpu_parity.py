@@ -615,12 +615,14 @@ def test_radial_snapshot_16384_plane_wave_closed_form():
 # ------------------------------------------------------------------ full size, sampled
 
 
-def test_full_size_8192_sampled_parity():
-    """The bench workload (8192^2 single phase, FP32-shifted, autotuned tiles): one and
-    two steps against the oracle on the full lattice, compared at sampled nodes."""
+@pytest.mark.parametrize("precision", [2, 0])
+def test_full_size_8192_sampled_parity(precision):
+    """The bench workload (8192^2 single phase, autotuned tiles) in FP32-shifted storage and in
+    the FP64 storage bench times beside it: one and two steps against the oracle on the full
+    lattice, compared at sampled nodes (FP64: the absolute gate of the small FP64 cases)."""
     L = _L()
     cfg = W.single_phase_8192()
-    lat = L.Lattice(cfg, precision=2)
+    lat = L.Lattice(cfg, precision=precision)
     ora = O.Oracle(cfg)
     rng = np.random.default_rng(0)
     idx = rng.integers(0, 8192 * 8192, size=200_000)
@@ -630,6 +632,11 @@ def test_full_size_8192_sampled_parity():
         mg, _ = lat.lb_moments(0, True)
         mg = mg.reshape(9, -1)[:, torch.from_numpy(idx).to(mg.device)].cpu().numpy()
         mo = ora.moments().reshape(9, -1)[:, idx]
+        if precision == 0:
+            ok, err = abs_ok(mg, mo)
+            say("8192^2 fp64 t=", ora.t, "abs err", err)
+            assert ok
+            continue
         scale = np.abs(mo - mo.mean(axis=1, keepdims=True)).max(axis=1)
         e = np.abs(mg - mo).max(axis=1) / scale
         say("8192^2 t=", ora.t, "err", e)
@@ -846,19 +853,21 @@ def test_full_size_16384_quench_growth_follows_linear_theory():
 FULL_GATES = {"slab_2048": 2e-5, "quench_16384": 8e-7}   # ~3x the measured FP32-shifted errors
 
 
+@pytest.mark.parametrize("precision", [2, 0])
 @pytest.mark.parametrize("name", ["slab_2048", "quench_16384"])
-def test_full_size_two_phase_workloads_sampled(name):
+def test_full_size_two_phase_workloads_sampled(name, precision):
     """The 2048^2 slab and the 16384^2 spinodal quench at full size, in the launch configuration
     bench.py times (FP32-shifted, autotuned tiles): two steps against the oracle at 200,000
     sampled nodes, whose moments the oracle forms there from its pre-collision populations.
     Gates ~3x the measured errors (slab 7.3e-6: its bulk phases hold O(0.5) deviations from
-    the rest state; quench 2.7e-7)."""
+    the rest state; quench 2.7e-7); FP64 storage (autotuned FP64 tiles) at the absolute gate of
+    the small FP64 cases."""
     L = _L()
     cfg = getattr(W, name)()
     nx, ny = cfg["nx"], cfg["ny"]
     rng = np.random.default_rng(3)
     idx = rng.integers(0, nx * ny, size=200_000)
-    lat = L.Lattice(cfg, precision=2)
+    lat = L.Lattice(cfg, precision=precision)
     lat.step(2)
     mg, _ = lat.lb_moments(0, True)
     mg = mg.reshape(9, -1)[:, torch.from_numpy(idx).to(mg.device)].cpu().numpy()
@@ -868,6 +877,11 @@ def test_full_size_two_phase_workloads_sampled(name):
     T = O.tables()[0]
     mo = T @ ora.f.reshape(9, -1)[:, idx]
     del ora
+    if precision == 0:
+        ok, err = abs_ok(mg, mo)
+        say(name, "full size fp64, 2 steps, abs err", err)
+        assert ok
+        return
     scale = np.abs(mo - mo.mean(axis=1, keepdims=True)).max(axis=1)
     e = np.abs(mg - mo).max(axis=1) / scale
     say(name, "full size, 2 steps, err", e)
@@ -914,18 +928,24 @@ def test_slab_2048_at_its_length_fp32s_against_fp64():
     assert abs(p[3] / 2.0 - 1) < 0.05
 
 
-def test_full_size_ensemble_sampled_replicas():
+@pytest.mark.parametrize("precision", [2, 0])
+def test_full_size_ensemble_sampled_replicas(precision):
     """The bench's 336-replica ensemble (256 x 128^2, 64 x 256^2, 16 x 512^2, kT over two
-    decades) in one launch, FP32-shifted: two steps against the oracle for the first and last
-    replica of each size class."""
+    decades) in one launch, FP32-shifted and FP64: two steps against the oracle for the first
+    and last replica of each size class."""
     L = _L()
     cfgs = W.ensemble_336()
-    lat = L.Lattice(cfgs, precision=2)
+    lat = L.Lattice(cfgs, precision=precision)
     lat.step(2)
     worst = 0.0
     for r in (0, 255, 256, 319, 320, 335):
         o = O.Oracle(cfgs[r])
         o.step(2)
+        if precision == 0:
+            ok, err = abs_ok(lat.moments(r), o.moments())
+            say("ensemble fp64 replica", r, cfgs[r]["nx"], "kT", cfgs[r]["kT"], "abs err", err.max())
+            assert ok
+            continue
         e = rel_err(lat.moments(r), o.moments())
         say("ensemble replica", r, cfgs[r]["nx"], "kT", cfgs[r]["kT"], "err", e.max())
         worst = max(worst, e.max())
