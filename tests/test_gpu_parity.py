@@ -1126,6 +1126,38 @@ def test_correlated_noise_parity_long_lines(precision, shape):
         assert e.max() < 9e-7
 
 
+def test_full_size_8192_correlated_noise_sampled():
+    """The bench's correlated-noise leg at full size: the 8192^2 single-phase lattice with the
+    exact Xi(k) noise, in FP32-shifted and FP64 storage and their autotuned launches, two steps
+    against the oracle (numpy-FFT fields, FP64 step) at 200,000 sampled nodes.  Gates as for the
+    long lines: 9e-7 of the fluctuation range (FP32-shifted), 2e-12 absolute (FP64)."""
+    L = _L()
+    cfg = dict(W.single_phase_8192(), noise="correlated", seed=17)
+    rng = np.random.default_rng(5)
+    idx = rng.integers(0, cfg["nx"] * cfg["ny"], size=200_000)
+    ora = O.Oracle(cfg)
+    ora.step(2)
+    mo = O.tables()[0] @ ora.f.reshape(9, -1)[:, idx]
+    del ora
+    for precision in (2, 0):
+        lat = L.Lattice(cfg, precision=precision)
+        lat.step(2)
+        mg, _ = lat.lb_moments(0, True)
+        mg = mg.reshape(9, -1)[:, torch.from_numpy(idx).to(mg.device)].cpu().numpy()
+        flags, t = lat.lb_status_flags()
+        lat.close()
+        assert flags == 0 and t == 2
+        if precision == 0:
+            ok, err = abs_ok(mg, mo)
+            say("correlated 8192^2 fp64 abs err", err)
+            assert ok
+        else:
+            scale = np.abs(mo - mo.mean(axis=1, keepdims=True)).max(axis=1)
+            e = np.abs(mg - mo).max(axis=1) / scale
+            say("correlated 8192^2 fp32s err", e)
+            assert e.max() < 9e-7
+
+
 CN_SMALL = [(4, 64, 6), (64, 4, 6), (4, 4, 8), (8, 2048, 3), (8, 4096, 3), (4096, 8, 3)]
 
 
