@@ -57,6 +57,78 @@ __device__ __forceinline__ void bits21(uint4 x, uint32_t b[6])
 }
 
 // Box-Muller on u = (b + 1/2) 2^-21 (exact in float and double)
+// ------------------------------------------------------------------ FP64 ln u, sin and cos of 2 pi u
+// Box-Muller meets these only at u = (b + 1/2) 2^-21 with b a 21-bit integer, which admits exact
+// argument reductions and short series instead of the general-argument library routines.  The
+// operations are products, sums, explicit fma, one division and bit manipulation, all correctly
+// rounded, so a host build of these functions gives the same bits (checked there over every b
+// against long-double references).
+
+// ln u: u = (2 b + 1) 2^-22 (exact) = m 2^e with m in [sqrt(1/2), sqrt(2)), m - 1 exact; ln m =
+// 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.1716, by its series to the s^19 term (truncation
+// below 3e-17 relative); e ln 2 with ln 2 in two parts, the first exact times |e| <= 22.
+__host__ __device__ inline double u21_ln(uint32_t b)
+{
+    const double u = (double)(2u * b + 1u) * 0x1p-22;
+    const unsigned long long bits = __builtin_bit_cast(unsigned long long, u);
+    int e = (int)((bits >> 52) & 0x7FFu) - 1023;
+    double m = __builtin_bit_cast(double, (bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull);
+    if (m > 1.4142135623730951) {
+        m *= 0.5;
+        ++e;
+    }
+    const double f = m - 1.0;
+    const double sv = f / (2.0 + f);
+    const double z = sv * sv;
+    double p = 1.0 / 19.0;
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double s2 = 2.0 * sv;
+    const double lnm = fma(s2 * z, p, s2);
+    const double de = (double)e;
+    return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, lnm));
+}
+
+// sin and cos of 2 pi u: the angle is n pi 2^-21 with n = 2 b + 1; its quarter turns q = n >> 20
+// and the odd rest m = n mod 2^20 reduce it exactly to x = m' pi 2^-21 in (0, pi/4] (m' = m, or
+// 2^20 - m with sine and cosine exchanged); sin x and cos x by their Taylor series to x^17 and
+// x^18 (truncation below 1e-19).
+__host__ __device__ inline void u21_sincos_turn(uint32_t b, double &sn, double &cs)
+{
+    const uint32_t n = 2u * b + 1u, q = n >> 20, m = n & 0xFFFFFu;
+    const bool comp = m > 0x80000u;
+    const double x = (double)(comp ? 0x100000u - m : m) * 0x1.921fb54442d18p-20;   // pi 2^-21
+    const double z = x * x;
+    double ps = 1.0 / 355687428096000.0;   // 1/17!
+    ps = fma(ps, z, -1.0 / 1307674368000.0);
+    ps = fma(ps, z, 1.0 / 6227020800.0);
+    ps = fma(ps, z, -1.0 / 39916800.0);
+    ps = fma(ps, z, 1.0 / 362880.0);
+    ps = fma(ps, z, -1.0 / 5040.0);
+    ps = fma(ps, z, 1.0 / 120.0);
+    ps = fma(ps, z, -1.0 / 6.0);
+    const double sx = fma(x * z, ps, x);
+    double pc = -1.0 / 6402373705728000.0;   // -1/18!
+    pc = fma(pc, z, 1.0 / 20922789888000.0);
+    pc = fma(pc, z, -1.0 / 87178291200.0);
+    pc = fma(pc, z, 1.0 / 479001600.0);
+    pc = fma(pc, z, -1.0 / 3628800.0);
+    pc = fma(pc, z, 1.0 / 40320.0);
+    pc = fma(pc, z, -1.0 / 720.0);
+    pc = fma(pc, z, 1.0 / 24.0);
+    pc = fma(pc, z, -0.5);
+    const double cx = fma(z, pc, 1.0);
+    const double s0 = comp ? cx : sx, c0 = comp ? sx : cx;   // of the rest m pi 2^-21
+    sn = q == 0 ? s0 : (q == 1 ? c0 : (q == 2 ? -s0 : -c0));
+    cs = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
+}
+
 template <typename R> struct Gauss;
 
 // the angle's revolutions plus one whole turn, 1 + (b + 1/2) 2^-21, assembled from the bits
@@ -81,11 +153,9 @@ template <> struct Gauss<double> {
     static __device__ __forceinline__ void pair(uint32_t be, uint32_t bo, double &a, double &b)
     {
 #pragma clang fp contract(on)
-        const double ue = ((double)be + 0.5) * 0x1p-21;
-        const double uo = ((double)bo + 0.5) * 0x1p-21;
-        const double r = sqrt(-2.0 * log(ue));
+        const double r = sqrt(-2.0 * u21_ln(be));
         double s, c;
-        sincospi(2.0 * uo, &s, &c);
+        u21_sincos_turn(bo, s, c);
         a = r * c;
         b = r * s;
     }
@@ -105,11 +175,9 @@ template <> __device__ __forceinline__ void gauss_pair_scaled<float>(uint32_t be
 template <> __device__ __forceinline__ void gauss_pair_scaled<double>(uint32_t be, uint32_t bo, double scale, double &a, double &b)
 {
 #pragma clang fp contract(on)
-    const double ue = ((double)be + 0.5) * 0x1p-21;
-    const double uo = ((double)bo + 0.5) * 0x1p-21;
-    const double r = sqrt(-2.0 * log(ue)) * scale;
+    const double r = sqrt(-2.0 * u21_ln(be)) * scale;
     double s, c;
-    sincospi(2.0 * uo, &s, &c);
+    u21_sincos_turn(bo, s, c);
     a = r * c;
     b = r * s;
 }
