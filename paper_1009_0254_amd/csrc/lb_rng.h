@@ -66,7 +66,8 @@ __device__ __forceinline__ void bits21(uint4 x, uint32_t b[6])
 
 // ln u: u = (2 b + 1) 2^-22 (exact) = m 2^e with m in [sqrt(1/2), sqrt(2)), m - 1 exact; ln m =
 // 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.1716, by its series to the s^19 term (truncation
-// below 3e-17 relative); e ln 2 with ln 2 in two parts, the first exact times |e| <= 22.
+// below 3e-17 relative); e ln 2 with ln 2 = hi + lo, hi being ln 2 rounded to 40 significant
+// bits (so that e hi is exact for |e| <= 22) and lo the rest rounded to double.
 __host__ __device__ inline double u21_ln(uint32_t b)
 {
     const double u = (double)(2u * b + 1u) * 0x1p-22;
@@ -92,7 +93,7 @@ __host__ __device__ inline double u21_ln(uint32_t b)
     const double s2 = 2.0 * sv;
     const double lnm = fma(s2 * z, p, s2);
     const double de = (double)e;
-    return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, lnm));
+    return fma(de, 0x1.62e42fefa4000p-1, fma(de, -0x1.8432a1b0e2634p-43, lnm));
 }
 
 // sin and cos of 2 pi u: the angle is n pi 2^-21 with n = 2 b + 1; its quarter turns q = n >> 20
