@@ -576,7 +576,7 @@ std::vector<std::pair<int, int>> step2_shapes(const lb_handle *h)
     // the trials against 512 x 32's 0.128, 0.131 against 0.127 when stepping)
     const bool fill_first = (double)h->L.nodes * 9 * elem_size(h->precision) > (double)(1ll << 30);
     // and for those large states the 256-lane strips come first: over 600 steps of the 8192^2
-    // lattice on one box, 256 x 67 and 256 x 32 tiles ran 0.630 and 0.631 ms per step, every
+    // lattice on one MI355X, 256 x 67 and 256 x 32 tiles ran 0.630 and 0.631 ms per step, every
     // 512-lane shape 0.638-0.657, while the short trials ranked 512 x 92 within 1% of them
     const std::vector<int> widths = fill_first ? std::vector<int>{256, 512, 384, 448} : std::vector<int>{512, 256, 384, 448};
     for (int bx : widths) {
